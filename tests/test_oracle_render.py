@@ -1,0 +1,346 @@
+"""Pins for the oracle renderers (Section 4): majorant grid, emission-
+absorption marching, delta tracking and the path tracer.  Closed forms,
+brute force, library interpolation and an independent analytic Monte Carlo
+estimator stand against the oracle."""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from synth import scenes
+
+TF5 = dict(tf=[(0.2, 0.3, 0.9, 0.0), (0.9, 0.1, 0.2, 0.8), (0.4, 0.4, 0.4, 0.3),
+               (1.0, 1.0, 0.0, 1.0), (0.0, 1.0, 1.0, 0.5)], tf_range=(0.1, 0.9))
+
+
+def _f32(x):
+    return np.asarray(x, np.float32).astype(np.float64)
+
+
+def _alpha(med, s):
+    tf = _f32(med["tf"])
+    lo, hi = _f32(med.get("tf_range", (0.0, 1.0)))
+    xs = lo + np.arange(len(tf)) * (hi - lo) / (len(tf) - 1)
+    return np.interp(s, xs, tf[:, 3])
+
+
+def _rgb(med, s):
+    tf = _f32(med["tf"])
+    lo, hi = _f32(med.get("tf_range", (0.0, 1.0)))
+    xs = lo + np.arange(len(tf)) * (hi - lo) / (len(tf) - 1)
+    return np.array([np.interp(s, xs, tf[:, c]) for c in range(3)])
+
+
+def _vol(shape, seed, zero=0.5):
+    rng = np.random.default_rng(seed)
+    v = rng.random(shape, dtype=np.float32)
+    v[rng.random(shape) < zero] = 0.0
+    return v
+
+
+# ------------------------------ majorant ------------------------------
+
+@pytest.mark.parametrize("C", [4, 8, 16])
+def test_majorant_bruteforce(C):
+    v = _vol((21, 26, 30), 1)
+    buf, st = oracle.encode(v, 0.5)
+    R = oracle.reconstruct(v, 0.5)
+    B = st["background"]
+    med = dict(sigma_scale=5.0, **TF5)
+    maj = oracle.majorant(oracle.VdbField(buf), med, C)
+    nz, ny, nx = v.shape
+    gz, gy, gx = maj.shape
+    pad = np.full((gz * C + 2, gy * C + 2, gx * C + 2), B, np.float32)
+    pad[1:nz + 1, 1:ny + 1, 1:nx + 1] = R
+    ds = 5.0 / max(v.shape)
+    tf = np.asarray(med["tf"])
+    lo, hi = _f32(med["tf_range"])
+    knots = lo + np.arange(len(tf)) * (hi - lo) / (len(tf) - 1)
+    for cz in range(gz):
+        for cy in range(gy):
+            for cx in range(gx):
+                blk = pad[cz * C:cz * C + C + 2, cy * C:cy * C + C + 2, cx * C:cx * C + C + 2]
+                a, b = float(blk.min()), float(blk.max())
+                s = np.concatenate([[a, b], knots[(knots > a) & (knots < b)],
+                                    np.linspace(a, b, 257)])
+                assert maj[cz, cy, cx] == pytest.approx(ds * _alpha(med, s).max(), abs=1e-15)
+
+
+def test_majorant_bounds_every_sample():
+    v = _vol((40, 33, 27), 2)
+    buf, _ = oracle.encode(v, 0.3)
+    f = oracle.VdbField(buf)
+    med = dict(sigma_scale=7.0, **TF5)
+    C = 8
+    maj = oracle.majorant(f, med, C)
+    rng = np.random.default_rng(3)
+    p = (rng.random((50000, 3)) * [27, 33, 40] - 0.5).astype(np.float32)
+    sig = 7.0 / 40 * _alpha(med, oracle.sample(f, p))
+    cell = np.floor((p.astype(np.float64) + 0.5) / C).astype(int)
+    assert np.all(sig <= maj[cell[:, 2], cell[:, 1], cell[:, 0]] * (1 + 1e-12))
+
+
+# ------------------------------ emission-absorption ------------------------------
+
+def test_ea_homogeneous_slab_closed_form():
+    c = 0.6
+    n = 32
+    v = np.full((n, n, n), c, np.float32)
+    buf, st = oracle.encode(v, 1.0)
+    med = scenes.ea_medium(8.0)
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    for step in (0.5, 0.25, 1.0):
+        img = oracle.render_ea(oracle.VdbField(buf), cam, med, dict(step=step))
+        sigma = 8.0 / n * float(np.float32(c))
+        alpha = 1 - math.exp(-sigma * step)
+        T = (1 - alpha) ** int(round(n / step))
+        rgb = _rgb(med, float(np.float32(c)))
+        np.testing.assert_allclose(img[..., 3], 1 - T, rtol=1e-12)
+        for ch in range(3):
+            np.testing.assert_allclose(img[..., ch], rgb[ch] * (1 - T), rtol=1e-12)
+    # small steps approach Beer-Lambert exp(-sigma d)
+    img = oracle.render_ea(oracle.VdbField(buf), cam, med, dict(step=1 / 64))
+    assert img[0, 0, 3] == pytest.approx(1 - math.exp(-8.0 * float(np.float32(c))), rel=1e-9)
+
+
+def test_ea_front_to_back_two_layers():
+    n, m = 16, 6
+    a, b = 0.9, 0.3
+    v = np.full((n, n, n), b, np.float32)
+    v[:m] = a          # front layer (small z) first along +z
+    med = scenes.ea_medium(8.0)
+    f = oracle.DenseField(v, 0.0)
+    cam = scenes.ortho_z_camera(n, n, 4, 4)
+    img = oracle.render_ea(f, cam, med, dict(step=1.0))  # samples on voxel centres
+    sa, sb = 8.0 / n * float(np.float32(a)), 8.0 / n * float(np.float32(b))
+    Ta, Tb = math.exp(-sa) ** m, math.exp(-sb) ** (n - m)
+    ca, cb = _rgb(med, float(np.float32(a))), _rgb(med, float(np.float32(b)))
+    want = ca * (1 - Ta) + Ta * cb * (1 - Tb)
+    for ch in range(3):
+        np.testing.assert_allclose(img[..., ch], want[ch], rtol=1e-12)
+    np.testing.assert_allclose(img[..., 3], 1 - Ta * Tb, rtol=1e-12)
+
+
+def test_ea_early_termination_threshold():
+    v = np.full((32, 32, 32), 1.0, np.float32)
+    f = oracle.DenseField(v, 1.0)
+    med = scenes.ea_medium(80.0)
+    cam = scenes.ortho_z_camera(32, 32, 4, 4)
+    full = oracle.render_ea(f, cam, med, dict(step=0.5))
+    cut = oracle.render_ea(f, cam, med, dict(step=0.5, t_terminate=1e-3))
+    assert np.all(cut[..., 3] >= 1 - 1e-3)
+    assert np.all(np.abs(cut - full) <= 1e-3 + 1e-12)
+
+
+# ------------------------------ delta tracking ------------------------------
+
+def _chord(n, o, d):
+    # brute force: inside-length of the parametric line sampled finely
+    t = np.linspace(0, 4 * n, 4_000_001)
+    pts = np.asarray(o)[None, :] + t[:, None] * np.asarray(d)[None, :]
+    inside = np.all((pts >= -0.5) & (pts <= n - 0.5), axis=1)
+    return inside.sum() * (t[1] - t[0])
+
+
+@pytest.mark.parametrize("C", [4, 8, 16])
+def test_transmittance_homogeneous_beer_lambert(C):
+    n = 24
+    v = np.full((n, n, n), 1.0, np.float32)
+    buf, _ = oracle.encode(v, 1.0)
+    f = oracle.VdbField(buf)
+    med = dict(sigma_scale=30.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)])
+    d = np.array([1.0, 2.0, 3.0])
+    d /= np.linalg.norm(d)
+    o = np.array([3.3, -0.9, -5.0]) - 0.0
+    o = o - 10 * d
+    L = _chord(n, o, d)
+    trials = 200_000
+    T = oracle.transmittance(f, med, o, d, trials, seed=C, C_=C)
+    want = math.exp(-30.0 / n * L)
+    se = math.sqrt(want * (1 - want) / trials)
+    assert abs(T - want) < 4 * se + 1e-4
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (8, 2)])
+def test_transmittance_heterogeneous_matches_ray_marched(n, seed):
+    v = _vol((n, n, n), seed, zero=0.3)
+    f = oracle.DenseField(v, 0.0)
+    med = dict(sigma_scale=3.0 * n, tf=[(1, 1, 1, 0), (1, 1, 1, 1)])
+    rng = np.random.default_rng(seed)
+    for ray in range(3):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        o = np.full(3, (n - 1) / 2.0) + rng.uniform(-1, 1, 3) - 2 * n * d
+        o32, d32 = o.astype(np.float32), d.astype(np.float32)
+        o64, d64 = o32.astype(np.float64), d32.astype(np.float64)
+        d64 = d64 / np.linalg.norm(d64)
+        # ray-marched optical depth, midpoint rule at 1/256 voxel
+        dt = 1.0 / 256
+        t = (np.arange(int(4 * n / dt)) + 0.5) * dt
+        pts = o64[None] + t[:, None] * d64[None]
+        inside = np.all((pts >= -0.5) & (pts <= n - 0.5), axis=1)
+        s = ndimage.map_coordinates(v.astype(np.float64), pts[inside][:, ::-1].T, order=1,
+                                    mode="grid-constant", cval=0.0)
+        tau = (3.0 * n / n) * s.sum() * dt
+        want = math.exp(-tau)
+        trials = 200_000
+        T = oracle.transmittance(f, med, o32, d32, trials, seed=seed * 10 + ray, C_=4)
+        se = math.sqrt(max(want * (1 - want), 1e-6) / trials)
+        assert abs(T - want) < 4 * se + 2e-3, (T, want)
+
+
+# ------------------------------ path tracer ------------------------------
+
+def test_isotropic_directions_uniform_on_sphere():
+    # midpoint grid over the unit square -> quadrature of the sphere moments:
+    # |d| = 1, E[d] = 0, E[d d^T] = I / 3, E[d_x^4] = 1 / 5
+    m = 200
+    u = (np.arange(m) + 0.5) / m
+    D = np.array([oracle.isotropic(a, b) for a in u for b in u])
+    np.testing.assert_allclose(np.linalg.norm(D, axis=1), 1.0, atol=1e-12)
+    np.testing.assert_allclose(D.mean(axis=0), 0.0, atol=1e-3)
+    np.testing.assert_allclose(D.T @ D / len(D), np.eye(3) / 3, atol=1e-3)
+    np.testing.assert_allclose((D ** 4).mean(axis=0), 0.2, atol=1e-3)
+
+
+def _homog(n, value=1.0):
+    v = np.full((n, n, n), value, np.float32)
+    buf, _ = oracle.encode(v, 1.0)
+    return oracle.VdbField(buf)
+
+
+def test_pt_zero_density_is_ambient():
+    n = 16
+    f = oracle.DenseField(np.zeros((n, n, n), np.float32), 0.0)
+    med = scenes.pt_medium(64.0)
+    cam = scenes.orbit_camera((n, n, n), 8, 8)
+    rgba, aov = oracle.render_pt(f, cam, med, dict(spp=4, max_bounces=4, seed=3), aov=True)
+    assert np.all(rgba[:, :3] == np.asarray(med["ambient"], np.float32).astype(np.float64))
+    assert np.all(rgba[:, 3] == 0) and np.all(aov == 1.0)
+
+
+def test_pt_white_furnace():
+    # albedo 1, white medium, no light, constant ambient: every path that
+    # escapes carries exactly the ambient radiance
+    n = 16
+    f = _homog(n)
+    med = dict(sigma_scale=40.0, albedo=1.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(0.25, 0.5, 1.0))
+    cam = scenes.orbit_camera((n, n, n), 8, 8)
+    rgba = oracle.render_pt(f, cam, med, dict(spp=8, max_bounces=10_000, seed=4))
+    np.testing.assert_allclose(rgba[:, :3], np.tile([0.25, 0.5, 1.0], (64, 1)), rtol=1e-12)
+
+
+def test_pt_albedo_zero_is_attenuated_ambient():
+    n, sigma_scale = 16, 24.0
+    f = _homog(n)
+    med = dict(sigma_scale=sigma_scale, albedo=0.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 0, -1), light_E=(5, 5, 5), ambient=(1.0, 1.0, 1.0))
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    spp = 64
+    rgba, aov = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=4, seed=5), aov=True)
+    tau = sigma_scale
+    T = math.exp(-tau / n * n)
+    N = 256 * spp
+    se = math.sqrt(T * (1 - T) / N)
+    assert abs(rgba[:, 0].mean() - T) < 4 * se
+    assert abs(aov[:, 1].mean() - T) < 4 * se
+    # mean first-scatter depth fraction: (1 - e^-tau) / tau
+    dmean = (1 - math.exp(-tau)) / tau
+    assert abs(aov[:, 0].mean() - dmean) < 4 * math.sqrt(1.0 / (12 * N)) + 4 * se
+
+
+def test_pt_single_scatter_closed_form():
+    # light from the camera side, one scattering event, no ambient:
+    # E[L] = albedo * E / (4 pi) * (1 - exp(-2 sigma d)) / 2
+    n, sigma_scale, albedo, E = 16, 12.0, 0.8, 2.0
+    f = _homog(n)
+    med = dict(sigma_scale=sigma_scale, albedo=albedo, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 0, -1), light_E=(E, E, E), ambient=(0, 0, 0))
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    spp = 64
+    rgba = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=1, seed=6))
+    sd = sigma_scale
+    p = (1 - math.exp(-2 * sd)) / 2
+    k = albedo * E / (4 * math.pi)
+    N = 256 * spp
+    se = k * math.sqrt(p * (1 - p) / N)
+    assert abs(rgba[:, 1].mean() - k * p) < 4 * se
+
+
+def _numpy_homog_pt(n, sigma, albedo, E, ldir, amb, bounces, N, seed):
+    """Independent analytic estimator for a homogeneous cube: exponential
+    free flights, exact shadow transmittance, isotropic scattering."""
+    rng = np.random.default_rng(seed)
+    o = np.stack([rng.uniform(-0.5, n - 0.5, N), rng.uniform(-0.5, n - 0.5, N),
+                  np.full(N, -0.5)], 1)
+    d = np.tile([0.0, 0.0, 1.0], (N, 1))
+    L = np.zeros(N)
+    beta = np.ones(N)
+    alive = np.ones(N, bool)
+    ldir = np.asarray(ldir, np.float64)
+
+    def exit_dist(p, dd):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t1 = np.where(dd > 0, (n - 0.5 - p) / dd, np.where(dd < 0, (-0.5 - p) / dd, np.inf))
+        return t1.min(axis=1)
+
+    for b in range(bounces):
+        te = exit_dist(o, d)
+        t = -np.log(1 - rng.random(N)) / sigma
+        esc = alive & (t >= te)
+        L[esc] += beta[esc] * amb
+        alive &= ~esc
+        x = o + t[:, None] * d
+        beta = beta * albedo
+        tl = exit_dist(x, np.tile(ldir, (N, 1)))
+        L[alive] += beta[alive] * E / (4 * math.pi) * np.exp(-sigma * tl[alive])
+        if b + 1 == bounces:
+            break
+        z = 1 - 2 * rng.random(N)
+        phi = 2 * math.pi * rng.random(N)
+        r = np.sqrt(np.maximum(0, 1 - z * z))
+        d = np.stack([r * np.cos(phi), r * np.sin(phi), z], 1)
+        o = x
+    return L
+
+
+def test_pt_multiple_scattering_matches_analytic_estimator():
+    n, sigma_scale, albedo = 16, 32.0, 0.9
+    E, amb, bounces = 3.0, 0.1, 8
+    ldir = np.array([-0.4, 0.8, 0.45])
+    ldir /= np.linalg.norm(ldir)
+    f = _homog(n)
+    med = dict(sigma_scale=sigma_scale, albedo=albedo, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=tuple(ldir), light_E=(E, E, E), ambient=(amb, amb, amb))
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    spp = 256
+    L1 = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=bounces, seed=7))[:, 0]
+    L2 = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=bounces, seed=8))[:, 0]
+    Lo = 0.5 * (L1 + L2)
+    # Monte Carlo noise of the mean from two independent renders
+    se_o = math.sqrt(np.var(L1 - L2) / 4 / len(Lo))
+    ld32 = np.asarray(ldir, np.float32).astype(np.float64)
+    Ln = _numpy_homog_pt(n, sigma_scale / n, albedo, E, ld32, amb, bounces, 1_000_000, 8)
+    se = math.sqrt(se_o ** 2 + Ln.var() / len(Ln))
+    assert abs(Lo.mean() - Ln.mean()) < 4 * se, (Lo.mean(), Ln.mean(), se)
+    # multiple scattering matters at this albedo: single scattering differs
+    S = _numpy_homog_pt(n, sigma_scale / n, albedo, E, ld32, amb, 1, 400_000, 9)
+    assert abs(S.mean() - Ln.mean()) > 10 * se
+
+
+def test_pt_deterministic_per_pixel():
+    # a pixel's estimate depends only on (seed, pixel, sample), not on which
+    # other pixels are rendered in the same call
+    n = 16
+    v = _vol((n, n, n), 12, zero=0.4)
+    buf, _ = oracle.encode(v, 0.5)
+    f = oracle.VdbField(buf)
+    med = scenes.pt_medium(32.0)
+    cam = scenes.orbit_camera((n, n, n), 12, 10)
+    prm = dict(spp=3, max_bounces=5, seed=99)
+    full = oracle.render_pt(f, cam, med, prm)
+    sub = oracle.render_pt(f, cam, med, prm, pixels=np.array([119, 5, 60], np.uint32))
+    assert np.array_equal(sub, full[[119, 5, 60]])

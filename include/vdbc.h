@@ -1,0 +1,231 @@
+/*
+ * vdbc — fixed-rate hierarchical (VDB) compression of dense float32 volumes
+ * and GPU random-access sampling / rendering of the compressed tree on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: "GPU Volume Rendering with Hierarchical Compression Using VDB"
+ * (Zellmann, Jaros, Amstutz, Wald).  The encoder is Alg. 1 ("Compress",
+ * Section 3.1) with the tree of Section 3.2 (8^3 leaves, 16^3-child lower
+ * nodes, 32^3-child upper nodes, child/tile bit masks with popcount offsets);
+ * sampling is the level-0 nearest / trilinear reconstruction of Section 3.2.2
+ * with the background value where no voxel exists; rendering is the
+ * emission-absorption marcher and the majorant-grid delta-tracking path tracer
+ * of Section 4.
+ *
+ * Conventions for every call:
+ *  - Every call returns a vdbc_status and never aborts.  Arguments are checked
+ *    before any work is enqueued; on error nothing is enqueued and
+ *    vdbc_last_error() (thread-local) holds a description.  Faults inside a
+ *    kernel surface at the caller's stream synchronisation.
+ *  - Device calls are stream-ordered on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream) and return once the work is enqueued.
+ *  - The library allocates no device memory: every device pointer (buffer,
+ *    positions, outputs, workspace) is owned by the caller and must stay valid
+ *    until the enqueued work has finished.
+ *  - Volumes are x-fastest: voxel (x,y,z) is element x + nx*(y + ny*z).
+ *    Sample positions are in index space: voxel centres on the integers, the
+ *    volume covering the box [-0.5, n-0.5] on each axis.
+ */
+#ifndef VDBC_H
+#define VDBC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VDBC_ABI_VERSION 1u
+
+typedef enum {
+    VDBC_OK = 0,
+    VDBC_E_INVALID = 1,          /* bad argument (null, size, range, NaN/Inf input) */
+    VDBC_E_NOMEM = 2,            /* host allocation failed */
+    VDBC_E_BUFFER_TOO_SMALL = 3, /* output capacity or workspace too small */
+    VDBC_E_FORMAT = 4,           /* buffer header/structure is not format v1 */
+    VDBC_E_DEVICE = 5,           /* HIP runtime error at enqueue */
+    VDBC_E_UNSUPPORTED = 6
+} vdbc_status;
+
+const char* vdbc_status_string(vdbc_status s);
+/* Detail of the last failing call on this thread ("" if none). */
+const char* vdbc_last_error(void);
+uint32_t vdbc_abi_version(void);
+
+typedef struct {
+    uint32_t nx, ny, nz;
+} vdbc_dims;
+
+/* ------------------------------------------------------------------------ */
+/* Host encoder: Alg. 1 (Section 3.1) + tree build and linearisation        */
+/* (Section 3.2).                                                            */
+/* ------------------------------------------------------------------------ */
+
+enum {
+    VDBC_BG_EXPLICIT = 1u, /* use params.background instead of the histogram mode */
+    VDBC_NO_CORNERS = 2u,  /* do not force-activate the two extreme corner voxels */
+    VDBC_NO_PRUNE = 4u     /* keep uniform leaves/lower nodes instead of tiles */
+};
+
+enum { VDBC_METRIC_CLOSEST = 1u, VDBC_METRIC_FARTHEST = 2u, VDBC_METRIC_MEDIAN = 3u };
+
+typedef struct {
+    float rate;         /* quality q in (0,1]: fraction of 32^3 bricks activated
+                           (1:10 -> 0.10); K = min(N, floor(q*N + 0.5)) */
+    uint32_t metric;    /* Eq. (1) closest, (2) farthest (default), (3) median */
+    uint32_t flags;     /* VDBC_BG_EXPLICIT | VDBC_NO_CORNERS | VDBC_NO_PRUNE */
+    float background;   /* used iff VDBC_BG_EXPLICIT */
+    uint32_t threads;   /* host worker threads; 0 = all hardware threads */
+} vdbc_encode_params;
+
+typedef struct {
+    float background;
+    uint64_t n_bricks, k_bricks, n_leaf, n_lower, n_upper, n_lower_tiles,
+        n_upper_tiles, active_voxels, bytes;
+    double achieved_rate; /* active voxels / (nx*ny*nz) */
+} vdbc_encode_stats;
+
+typedef struct vdbc_encoder vdbc_encoder;
+
+/* Phase 1: analyse `dense` (host, caller-owned, x-fastest, finite values;
+ * must stay unchanged until phase 2) and size the output.  On success *h is a
+ * handle to pass to vdbc_encode_finish or vdbc_encode_abort, *bytes the exact
+ * buffer size.  NaN/Inf input, zero dims, rate outside (0,1] or a bad metric
+ * -> VDBC_E_INVALID. */
+vdbc_status vdbc_encode_begin(const float* dense, vdbc_dims dims, const vdbc_encode_params* p,
+                              vdbc_encoder** h, uint64_t* bytes, vdbc_encode_stats* stats);
+/* Phase 2: write the canonical buffer (format v1) into host memory `out`
+ * (capacity >= *bytes from phase 1, 256-byte aligned) and release the handle
+ * (also on error). */
+vdbc_status vdbc_encode_finish(vdbc_encoder* h, void* out, uint64_t capacity);
+void vdbc_encode_abort(vdbc_encoder* h);
+/* One-shot form: out == NULL or capacity too small -> VDBC_E_BUFFER_TOO_SMALL
+ * with *bytes set (the analysis is then repeated by the next call). */
+vdbc_status vdbc_encode(const float* dense, vdbc_dims dims, const vdbc_encode_params* p,
+                        void* out, uint64_t capacity, uint64_t* bytes,
+                        vdbc_encode_stats* stats);
+/* Full host-side structural check of a buffer (magic, version, offsets,
+ * counts, running popcount prefixes, root table). */
+vdbc_status vdbc_validate(const void* buf_host, uint64_t bytes, vdbc_encode_stats* info);
+
+/* ------------------------------------------------------------------------ */
+/* Device buffer handle                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* A canonical buffer resident in device memory plus a host copy of its
+ * 256-byte header (the host needs dims and section offsets for launch
+ * geometry without reading device memory). */
+typedef struct {
+    const void* device;   /* device pointer to the whole buffer, 256-B aligned */
+    uint64_t bytes;
+    uint8_t header[256];
+} vdbc_grid;
+
+/* Fill *g from a device pointer and the host copy of the buffer's first 256
+ * bytes; checks the header (magic, version, offsets within `bytes`). */
+vdbc_status vdbc_grid_init(vdbc_grid* g, const void* device, uint64_t bytes,
+                           const void* host_header);
+
+/* ------------------------------------------------------------------------ */
+/* Sampling (Section 3.2.2)                                                  */
+/* ------------------------------------------------------------------------ */
+
+enum { VDBC_FILTER_NEAREST = 0u, VDBC_FILTER_TRILINEAR = 1u };
+
+/* out[i] = field value at pos[3i..3i+2] (device float32, AoS x,y,z), for
+ * i < n.  Trilinear = lerp along x, then y, then z of the 8 corner voxels,
+ * B for corners outside the volume or without a voxel; nearest = voxel
+ * floor(p) + (frac >= 0.5).  n == 0 is a no-op. */
+vdbc_status vdbc_sample(const vdbc_grid* g, const float* pos, uint64_t n, uint32_t filter,
+                        float* out, void* stream);
+/* The same on a plain dense device array (the "3D texture" baseline). */
+vdbc_status vdbc_sample_dense(const float* dense, vdbc_dims d, float background,
+                              const float* pos, uint64_t n, uint32_t filter, float* out,
+                              void* stream);
+/* Integer-coordinate lookups: out[i] = value of voxel ijk[3i..3i+2] (device
+ * int32; B outside the volume or where no voxel is stored). */
+vdbc_status vdbc_lookup(const vdbc_grid* g, const int32_t* ijk, uint64_t n, float* out,
+                        void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Rendering (Section 4)                                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t kind;          /* 0 orthographic, 1 pinhole */
+    uint32_t width, height;
+    float origin[3];        /* pinhole eye (index space) */
+    float lower_left[3];    /* pinhole: direction towards image point (0,0);
+                               orthographic: ray origin of image point (0,0) */
+    float du[3], dv[3];     /* step per pixel along x / y of the image */
+    float dir[3];           /* orthographic ray direction */
+} vdbc_camera;
+
+typedef struct {
+    float sigma_scale;      /* extinction at alpha = 1 per unit of the longest
+                               axis; per voxel: sigma_scale * alpha / max(n) */
+    float albedo;           /* single-scattering albedo (path tracer) */
+    uint32_t tf_n;          /* 2..64 RGBA control points spread evenly over */
+    float tf[64][4];        /* [tf_lo, tf_hi]; alpha = extinction (Section 4) */
+    float tf_lo, tf_hi;
+    float light_dir[3];     /* unit vector towards the directional light */
+    float light_E[3];       /* its irradiance */
+    float ambient[3];       /* constant ambient radiance added on escape */
+} vdbc_medium;
+
+enum { VDBC_MODE_EA = 0u, VDBC_MODE_PT = 1u };
+enum {
+    VDBC_RENDER_HDDA = 1u,        /* EA: skip lattice samples inside empty tree nodes
+                                     (result-preserving; needs alpha_TF(B) == 0) */
+    VDBC_RENDER_COUNT = 2u,       /* count trilinear samples into the workspace */
+    VDBC_RENDER_KEEP_MAJORANT = 4u /* PT: reuse the majorant grid already in ws */
+};
+
+typedef struct {
+    uint32_t mode;          /* VDBC_MODE_EA or VDBC_MODE_PT */
+    uint32_t spp;           /* PT samples per pixel (>= 1) */
+    uint32_t max_bounces;   /* PT scattering events per path (>= 1) */
+    uint32_t macrocell;     /* majorant cell edge in voxels (4..64) */
+    uint32_t flags;         /* VDBC_RENDER_* */
+    float step;             /* EA step in voxels (> 0) */
+    float t_terminate;      /* EA: stop when transmittance < this (0 = off) */
+    uint64_t seed;          /* PT Philox key material */
+    uint32_t frame;         /* PT counter word 3 */
+    uint32_t reserved[3];
+} vdbc_render_params;
+
+/* Workspace layout (caller-owned device memory, 256-B aligned):
+ *   [0, 8)    uint64 trilinear-sample counter (VDBC_RENDER_COUNT; zeroed by
+ *             the render call itself)
+ *   [256, ..) float32 majorant grid ceil(n/macrocell)^3, x-fastest */
+vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d, uint64_t* bytes);
+
+/* image: device float32 [height][width][4] (RGB radiance + opacity).  aov:
+ * NULL or device float32 [height][width][2] = (first-scatter depth fraction,
+ * primary transmittance), path tracer only.  The path tracer rebuilds the
+ * majorant grid in ws first unless VDBC_RENDER_KEEP_MAJORANT. */
+vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
+                        const vdbc_render_params* r, float* image, float* aov, void* ws,
+                        uint64_t ws_bytes, void* stream);
+vdbc_status vdbc_render_dense(const float* dense, vdbc_dims d, float background,
+                              const vdbc_camera* c, const vdbc_medium* m,
+                              const vdbc_render_params* r, float* image, float* aov,
+                              void* ws, uint64_t ws_bytes, void* stream);
+
+/* Majorant grid alone (Section 4 macrocells): out = device float32
+ * ceil(n/macrocell)^3, x-fastest; per cell the extinction maximum over the
+ * value range of voxels [C*c-1, C*c+C] (one-voxel dilation). */
+vdbc_status vdbc_majorant(const vdbc_grid* g, const vdbc_medium* m, uint32_t macrocell,
+                          float* out, void* stream);
+vdbc_status vdbc_majorant_dense(const float* dense, vdbc_dims d, float background,
+                                const vdbc_medium* m, uint32_t macrocell, float* out,
+                                void* stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) on the device: out[4i..4i+3] =
+ * Philox(ctr[4i..4i+3], key[2i..2i+1]) for i < n (device uint32 arrays). */
+vdbc_status vdbc_philox(const uint32_t* ctr, const uint32_t* key, uint64_t n, uint32_t* out,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,710 @@
+// HIP kernels for gfx950 and their C-ABI launchers: sampling (Section 3.2.2),
+// majorant macrocells, emission-absorption marching and the delta-tracking
+// path tracer (Section 4), each for the compressed VDB and for the dense
+// float32 baseline through the same templated code.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "device.h"
+#include "format.h"
+#include "host_header.h"
+
+namespace vdbc {
+
+constexpr int kTile = 16;          // 16x16 pixels per 256-thread workgroup
+constexpr int kBlock = 256;
+constexpr float kHddaEps = 1.0f / 64.0f;
+// Upper bound on density evaluations in one free-flight search; a flight that
+// reaches it is treated as escaping.  Only a majorant that exceeds the
+// sampled extinction by many orders of magnitude can get near it.
+constexpr uint32_t kMaxFlightSamples = 1u << 20;
+
+// ---------------------------------------------------------------- helpers
+
+// 256 threads = 4 waves of 8x8 pixels; returns false outside the image.
+__device__ __forceinline__ bool tile_pixel(int width, int height, int& px, int& py)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    px = blockIdx.x * kTile + (w & 1) * 8 + (lane & 7);
+    py = blockIdx.y * kTile + (w >> 1) * 8 + (lane >> 3);
+    return px < width && py < height;
+}
+
+// Adds a per-thread count to a global 64-bit counter, one atomic per block.
+__device__ __forceinline__ void block_count(uint32_t n, unsigned long long* counter)
+{
+    __shared__ unsigned int s;
+    if (threadIdx.x == 0) s = 0;
+    __syncthreads();
+    if (n) atomicAdd(&s, n);
+    __syncthreads();
+    if (threadIdx.x == 0 && s) atomicAdd(counter, (unsigned long long)s);
+}
+
+__global__ void zero_u64(unsigned long long* p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+// ---------------------------------------------------------------- sampling
+
+template <class Acc, class View>
+__global__ __launch_bounds__(kBlock) void sample_kernel(View view, const float* __restrict__ pos,
+                                                        uint64_t n, int filter,
+                                                        float* __restrict__ out)
+{
+    Acc acc{view};
+    acc.reset();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    out[i] = filter ? trilinear(acc, x, y, z) : nearest(acc, x, y, z);
+}
+
+__global__ __launch_bounds__(kBlock) void lookup_kernel(VdbView view, const int32_t* __restrict__ ijk,
+                                                        uint64_t n, float* __restrict__ out)
+{
+    VdbAcc acc{view};
+    acc.reset();
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int x = ijk[3 * i], y = ijk[3 * i + 1], z = ijk[3 * i + 2];
+    // voxels beyond the volume read B (edge leaves store B there, regions
+    // past the last leaf or outside the root table resolve to B)
+    out[i] = acc.voxel(x, y, z);
+}
+
+// ---------------------------------------------------------------- majorant
+
+template <class Acc, class View>
+__global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, int C, int gx,
+                                                          int gy, int gz, float* __restrict__ out)
+{
+    Acc acc{view};
+    acc.reset();
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= gx * gy * gz) return;
+    const int cx = cell % gx, cy = (cell / gx) % gy, cz = cell / (gx * gy);
+    float vmin = INFINITY, vmax = -INFINITY;
+    for (int k = C * cz - 1; k <= C * cz + C; ++k)
+        for (int j = C * cy - 1; j <= C * cy + C; ++j)
+            for (int i = C * cx - 1; i <= C * cx + C; ++i) {
+                const float v = acc.voxel(i, j, k);
+                vmin = fminf(vmin, v);
+                vmax = fmaxf(vmax, v);
+            }
+    // max of the piecewise-linear alpha over [vmin, vmax]: the two ends and
+    // every control point strictly inside
+    float a = fmaxf(tf_alpha(m, vmin), tf_alpha(m, vmax));
+    const float p0 = (vmin - m.tf_lo) * m.tf_inv, p1 = (vmax - m.tf_lo) * m.tf_inv;
+    for (int q = 0; q < m.tf_n; ++q)
+        if ((float)q > p0 && (float)q < p1) a = fmaxf(a, m.tf[q].w);
+    out[cell] = m.ds * a;
+}
+
+// ---------------------------------------------------------------- EA
+
+template <class Acc, class View, bool HDDA, bool COUNT>
+__global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, MediumK m, float step,
+                                                    float t_term, float* __restrict__ image,
+                                                    unsigned long long* counter)
+{
+    Acc acc{view};
+    acc.reset();
+    int px, py;
+    const bool live = tile_pixel(cam.width, cam.height, px, py);
+    uint32_t nsamp = 0;
+    if (live) {
+        float o[3], d[3], t0, t1;
+        camera_ray(cam, (float)px + 0.5f, (float)py + 0.5f, o, d);
+        float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, T = 1.0f;
+        if (box_clip(view.nx, view.ny, view.nz, o, d, t0, t1)) {
+            for (int k = 0;; ++k) {
+                const float t = fmaf((float)k + 0.5f, step, t0);
+                if (t >= t1) break;
+                const float x = fmaf(t, d[0], o[0]), y = fmaf(t, d[1], o[1]),
+                            z = fmaf(t, d[2], o[2]);
+                if (HDDA) {
+                    const int i = (int)floorf(fmaxf(x, -2.0f)), j = (int)floorf(fmaxf(y, -2.0f)),
+                              kk = (int)floorf(fmaxf(z, -2.0f));
+                    const int L = acc.empty_level(i, j, kk);
+                    if (L) {
+                        const int mask = (1 << L) - 1;
+                        if ((i & mask) != mask && (j & mask) != mask && (kk & mask) != mask) {
+                            // every sample whose footprint stays inside this
+                            // empty node reads B with alpha 0: jump past it
+                            const int lo[3] = {i & ~mask, j & ~mask, kk & ~mask};
+                            float te = INFINITY;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                if (d[a] > 0.0f)
+                                    te = fminf(te, ((float)(lo[a] + mask) - kHddaEps - o[a]) / d[a]);
+                                else if (d[a] < 0.0f)
+                                    te = fminf(te, ((float)lo[a] + kHddaEps - o[a]) / d[a]);
+                            }
+                            const int kn = (int)floorf(fminf((te - t0) / step - 0.5f, 2.0e9f));
+                            k = (kn > k + 1 ? kn : k + 1) - 1;
+                            continue;
+                        }
+                    }
+                }
+                const float s = trilinear(acc, x, y, z);
+                if (COUNT) ++nsamp;
+                const float4 c = tf_eval(m, s);
+                const float a = 1.0f - expf(-(m.ds * c.w) * step);
+                const float ta = T * a;
+                c0 = fmaf(ta, c.x, c0);
+                c1 = fmaf(ta, c.y, c1);
+                c2 = fmaf(ta, c.z, c2);
+                T *= 1.0f - a;
+                if (T < t_term) break;
+            }
+        }
+        float4* img = reinterpret_cast<float4*>(image);
+        img[(uint64_t)py * cam.width + px] = make_float4(c0, c1, c2, 1.0f - T);
+    }
+    if (COUNT) block_count(nsamp, counter);
+}
+
+// ---------------------------------------------------------------- PT
+
+struct PtArgs {
+    int spp, max_bounces, C, gx, gy, gz;
+    uint32_t seed_lo, seed_hi, frame;
+};
+
+// Free-flight distance by delta tracking inside the cells of the majorant
+// grid visited in order by a 3D-DDA (Section 4); empty cells are skipped and
+// a flight that overshoots a cell restarts at its exit.  Returns true with
+// the collision distance and the density sampled there.
+template <class Acc>
+__device__ bool free_flight(Acc& acc, const MediumK& m, const float* __restrict__ maj,
+                            const PtArgs& g, const float o[3], const float d[3], float t0,
+                            float t1, Rng& rng, float& t_hit, float& s_hit, uint32_t& nsamp)
+{
+    if (!(t0 < t1)) return false;
+    const float C = (float)g.C;
+    int cx = (int)floorf((fmaf(t0, d[0], o[0]) + 0.5f) / C);
+    int cy = (int)floorf((fmaf(t0, d[1], o[1]) + 0.5f) / C);
+    int cz = (int)floorf((fmaf(t0, d[2], o[2]) + 0.5f) / C);
+    cx = min(max(cx, 0), g.gx - 1);
+    cy = min(max(cy, 0), g.gy - 1);
+    cz = min(max(cz, 0), g.gz - 1);
+    const int sx = d[0] > 0.0f ? 1 : (d[0] < 0.0f ? -1 : 0);
+    const int sy = d[1] > 0.0f ? 1 : (d[1] < 0.0f ? -1 : 0);
+    const int sz = d[2] > 0.0f ? 1 : (d[2] < 0.0f ? -1 : 0);
+    const float ix = 1.0f / d[0], iy = 1.0f / d[1], iz = 1.0f / d[2];
+    float t = t0;
+    uint32_t budget = kMaxFlightSamples;
+    for (;;) {
+        float te = t1;
+        int axis = -1;
+        if (sx) {
+            const float ta = (C * (float)(cx + (sx > 0)) - 0.5f - o[0]) * ix;
+            if (ta < te) {
+                te = ta;
+                axis = 0;
+            }
+        }
+        if (sy) {
+            const float ta = (C * (float)(cy + (sy > 0)) - 0.5f - o[1]) * iy;
+            if (ta < te) {
+                te = ta;
+                axis = 1;
+            }
+        }
+        if (sz) {
+            const float ta = (C * (float)(cz + (sz > 0)) - 0.5f - o[2]) * iz;
+            if (ta < te) {
+                te = ta;
+                axis = 2;
+            }
+        }
+        const float mu = maj[cx + g.gx * (cy + g.gy * cz)];
+        if (mu > 0.0f && t < te) {
+            const float imu = 1.0f / mu;
+            for (;;) {
+                t = fmaf(-__logf(1.0f - rng.next()), imu, t);
+                if (t >= te) break;
+                if (--budget == 0) return false;
+                const float s = trilinear(acc, fmaf(t, d[0], o[0]), fmaf(t, d[1], o[1]),
+                                          fmaf(t, d[2], o[2]));
+                ++nsamp;
+                const float sig = m.ds * tf_alpha(m, s);
+                if (rng.next() * mu < sig) {
+                    t_hit = t;
+                    s_hit = s;
+                    return true;
+                }
+            }
+        }
+        if (axis < 0) return false;
+        t = te;
+        if (axis == 0) {
+            cx += sx;
+            if ((unsigned)cx >= (unsigned)g.gx) return false;
+        } else if (axis == 1) {
+            cy += sy;
+            if ((unsigned)cy >= (unsigned)g.gy) return false;
+        } else {
+            cz += sz;
+            if ((unsigned)cz >= (unsigned)g.gz) return false;
+        }
+    }
+}
+
+template <class Acc, class View, bool COUNT, bool AOV>
+__global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
+                                                    const float* __restrict__ maj,
+                                                    float* __restrict__ image,
+                                                    float* __restrict__ aov,
+                                                    unsigned long long* counter)
+{
+    Acc acc{view};
+    acc.reset();
+    int px, py;
+    const bool live = tile_pixel(cam.width, cam.height, px, py);
+    uint32_t nsamp = 0;
+    if (live) {
+        const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
+        const uint32_t k0 = g.seed_lo ^ pix, k1 = g.seed_hi;
+        const float inv4pi = 0.0795774715459476679f;
+        float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f, opac = 0.0f, depth = 0.0f, trans = 0.0f;
+        for (int s = 0; s < g.spp; ++s) {
+            Rng path;
+            path.init(k0, k1, (uint32_t)s, 0u, 0u, g.frame);
+            const float jx = path.next(), jy = path.next();
+            float o[3], d[3];
+            camera_ray(cam, (float)px + jx, (float)py + jy, o, d);
+            float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
+            for (int b = 0; b < g.max_bounces; ++b) {
+                if (b > 0) path.init(k0, k1, (uint32_t)s, (uint32_t)b, 0u, g.frame);
+                float t0, t1, th = 0.0f, sh = 0.0f;
+                const bool hit = box_clip(view.nx, view.ny, view.nz, o, d, t0, t1) &&
+                                 free_flight(acc, m, maj, g, o, d, t0, t1, path, th, sh, nsamp);
+                if (b == 0) {
+                    if (hit) {
+                        opac += 1.0f;
+                        depth += (th - t0) / (t1 - t0);
+                    } else {
+                        trans += 1.0f;
+                        depth += 1.0f;
+                    }
+                }
+                if (!hit) {
+                    L0 = fmaf(b0, m.ambient[0], L0);
+                    L1 = fmaf(b1, m.ambient[1], L1);
+                    L2 = fmaf(b2, m.ambient[2], L2);
+                    break;
+                }
+                const float x[3] = {fmaf(th, d[0], o[0]), fmaf(th, d[1], o[1]),
+                                    fmaf(th, d[2], o[2])};
+                const float4 c = tf_eval(m, sh);
+                b0 *= m.albedo * c.x;
+                b1 *= m.albedo * c.y;
+                b2 *= m.albedo * c.z;
+                Rng shadow;
+                shadow.init(k0, k1, (uint32_t)s, (uint32_t)b, 1u, g.frame);
+                float s0, s1, tsh, ssh;
+                const bool blocked =
+                    box_clip(view.nx, view.ny, view.nz, x, m.light, s0, s1) &&
+                    free_flight(acc, m, maj, g, x, m.light, s0, s1, shadow, tsh, ssh, nsamp);
+                if (!blocked) {
+                    L0 = fmaf(b0 * inv4pi, m.light_E[0], L0);
+                    L1 = fmaf(b1 * inv4pi, m.light_E[1], L1);
+                    L2 = fmaf(b2 * inv4pi, m.light_E[2], L2);
+                }
+                if (b + 1 == g.max_bounces) break;
+                const float u1 = path.next(), u2 = path.next();
+                const float z = 1.0f - 2.0f * u1;
+                const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+                float sp, cp;
+                sincosf(6.28318530717958647692f * u2, &sp, &cp);
+                o[0] = x[0];
+                o[1] = x[1];
+                o[2] = x[2];
+                d[0] = r * cp;
+                d[1] = r * sp;
+                d[2] = z;
+            }
+            r0 += L0;
+            r1 += L1;
+            r2 += L2;
+        }
+        const float inv = 1.0f / (float)g.spp;
+        float4* img = reinterpret_cast<float4*>(image);
+        img[pix] = make_float4(r0 * inv, r1 * inv, r2 * inv, opac * inv);
+        if (AOV) reinterpret_cast<float2*>(aov)[pix] = make_float2(depth * inv, trans * inv);
+    }
+    if (COUNT) block_count(nsamp, counter);
+}
+
+__global__ void philox_kernel(const uint32_t* __restrict__ ctr, const uint32_t* __restrict__ key,
+                              uint64_t n, uint32_t* __restrict__ out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c0 = ctr[4 * i], c1 = ctr[4 * i + 1], c2 = ctr[4 * i + 2], c3 = ctr[4 * i + 3];
+    philox4x32_10(c0, c1, c2, c3, key[2 * i], key[2 * i + 1]);
+    out[4 * i] = c0;
+    out[4 * i + 1] = c1;
+    out[4 * i + 2] = c2;
+    out[4 * i + 3] = c3;
+}
+
+// ---------------------------------------------------------------- host side
+
+static vdbc_status launch_check(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VDBC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return VDBC_OK;
+}
+
+static vdbc_status make_view(const vdbc_grid* g, VdbView* v)
+{
+    if (!g || !g->device) return fail(VDBC_E_INVALID, "null grid");
+    Header h;
+    vdbc_status s = parse_header(g->header, g->bytes, &h);
+    if (s) return s;
+    const uint8_t* b = static_cast<const uint8_t*>(g->device);
+    v->root = reinterpret_cast<const uint32_t*>(b + h.off_root);
+    v->upper = reinterpret_cast<const Word*>(b + h.off_upper);
+    v->lower = reinterpret_cast<const Word*>(b + h.off_lower);
+    v->upper_tiles = reinterpret_cast<const float*>(b + h.off_upper_tiles);
+    v->lower_tiles = reinterpret_cast<const float*>(b + h.off_lower_tiles);
+    v->leaf_values = reinterpret_cast<const float*>(b + h.off_leaf_values);
+    v->bg = reinterpret_cast<const float*>(b + hdr::background);
+    v->nx = (int)h.nx;
+    v->ny = (int)h.ny;
+    v->nz = (int)h.nz;
+    v->rnx = (int)h.root_nx;
+    v->rny = (int)h.root_ny;
+    v->rnz = (int)h.root_nz;
+    v->background = h.background;
+    return VDBC_OK;
+}
+
+static vdbc_status make_dense(const float* dense, vdbc_dims d, float background, DenseView* v)
+{
+    if (!dense) return fail(VDBC_E_INVALID, "null dense array");
+    if (d.nx == 0 || d.ny == 0 || d.nz == 0 || d.nx > 0x7FFFFFFFu || d.ny > 0x7FFFFFFFu ||
+        d.nz > 0x7FFFFFFFu)
+        return fail(VDBC_E_INVALID, "dims must be in [1, 2^31)");
+    if (!std::isfinite(background)) return fail(VDBC_E_INVALID, "background must be finite");
+    v->data = dense;
+    v->nx = (int)d.nx;
+    v->ny = (int)d.ny;
+    v->nz = (int)d.nz;
+    v->background = background;
+    return VDBC_OK;
+}
+
+static vdbc_status make_medium(const vdbc_medium* m, int nx, int ny, int nz, MediumK* k)
+{
+    if (!m) return fail(VDBC_E_INVALID, "null medium");
+    if (m->tf_n < 2 || m->tf_n > 64) return fail(VDBC_E_INVALID, "tf_n must be in [2, 64]");
+    if (!(m->tf_hi > m->tf_lo) || !std::isfinite(m->tf_lo) || !std::isfinite(m->tf_hi))
+        return fail(VDBC_E_INVALID, "need finite tf_lo < tf_hi");
+    if (!std::isfinite(m->sigma_scale) || m->sigma_scale < 0.0f)
+        return fail(VDBC_E_INVALID, "sigma_scale must be finite and >= 0");
+    std::memset(k, 0, sizeof *k);
+    const int nmax = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+    k->ds = m->sigma_scale / (float)nmax;
+    k->albedo = m->albedo;
+    k->tf_n = (int)m->tf_n;
+    k->tf_lo = m->tf_lo;
+    k->tf_inv = (float)(m->tf_n - 1) / (m->tf_hi - m->tf_lo);
+    for (uint32_t i = 0; i < m->tf_n; ++i) {
+        for (int c = 0; c < 4; ++c)
+            if (!std::isfinite(m->tf[i][c])) return fail(VDBC_E_INVALID, "non-finite TF entry");
+        if (m->tf[i][3] < 0.0f) return fail(VDBC_E_INVALID, "TF alpha must be >= 0");
+        k->tf[i] = make_float4(m->tf[i][0], m->tf[i][1], m->tf[i][2], m->tf[i][3]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        k->light[a] = m->light_dir[a];
+        k->light_E[a] = m->light_E[a];
+        k->ambient[a] = m->ambient[a];
+    }
+    return VDBC_OK;
+}
+
+// Host mirror of the device TF alpha (for the HDDA precondition alpha(B)=0).
+static float host_alpha(const MediumK& m, float s)
+{
+    float pos = (s - m.tf_lo) * m.tf_inv;
+    pos = std::fmin(std::fmax(pos, 0.0f), (float)(m.tf_n - 1));
+    int i = (int)pos;
+    i = i > m.tf_n - 2 ? m.tf_n - 2 : i;
+    const float fr = pos - (float)i;
+    return std::fma(fr, m.tf[i + 1].w - m.tf[i].w, m.tf[i].w);
+}
+
+static vdbc_status make_camera(const vdbc_camera* c, CameraK* k)
+{
+    if (!c) return fail(VDBC_E_INVALID, "null camera");
+    if (c->kind > 1) return fail(VDBC_E_INVALID, "camera kind must be 0 or 1");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(c->origin[a]) || !std::isfinite(c->lower_left[a]) ||
+            !std::isfinite(c->du[a]) || !std::isfinite(c->dv[a]) || !std::isfinite(c->dir[a]))
+            return fail(VDBC_E_INVALID, "non-finite camera vector");
+    if (c->kind == 0 && c->dir[0] == 0.0f && c->dir[1] == 0.0f && c->dir[2] == 0.0f)
+        return fail(VDBC_E_INVALID, "orthographic camera needs a non-zero direction");
+    if (c->width == 0 || c->height == 0 || c->width > 65536 * kTile || c->height > 65535u * kTile)
+        return fail(VDBC_E_INVALID, "bad image size");
+    k->kind = (int)c->kind;
+    k->width = (int)c->width;
+    k->height = (int)c->height;
+    for (int a = 0; a < 3; ++a) {
+        k->o[a] = c->origin[a];
+        k->ll[a] = c->lower_left[a];
+        k->du[a] = c->du[a];
+        k->dv[a] = c->dv[a];
+        k->dir[a] = c->dir[a];
+    }
+    return VDBC_OK;
+}
+
+static uint64_t majorant_bytes(uint32_t C, int nx, int ny, int nz)
+{
+    const uint64_t gx = (nx + C - 1) / C, gy = (ny + C - 1) / C, gz = (nz + C - 1) / C;
+    return gx * gy * gz * 4u;
+}
+
+static vdbc_status check_samples(const float* pos, uint64_t n, uint32_t filter, float* out)
+{
+    if (filter > 1) return fail(VDBC_E_INVALID, "filter must be 0 or 1");
+    if (n && (!pos || !out)) return fail(VDBC_E_INVALID, "null positions or output");
+    if (n > (uint64_t)0x7FFFFFFFull * kBlock) return fail(VDBC_E_INVALID, "too many samples");
+    return VDBC_OK;
+}
+
+template <class Acc, class View>
+static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, float* out,
+                                   hipStream_t st)
+{
+    const int gx = (v.nx + C - 1) / C, gy = (v.ny + C - 1) / C, gz = (v.nz + C - 1) / C;
+    const uint64_t cells = (uint64_t)gx * gy * gz;
+    hipLaunchKernelGGL((majorant_kernel<Acc, View>), dim3((unsigned)((cells + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, st, v, m, (int)C, gx, gy, gz, out);
+    return launch_check("majorant");
+}
+
+template <class Acc, class View>
+static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_medium* med,
+                               const vdbc_render_params* r, float* image, float* aov, void* ws,
+                               uint64_t ws_bytes, void* stream)
+{
+    if (!r || !image) return fail(VDBC_E_INVALID, "null params or image");
+    CameraK cam;
+    MediumK m;
+    vdbc_status s = make_camera(c, &cam);
+    if (s) return s;
+    s = make_medium(med, v.nx, v.ny, v.nz, &m);
+    if (s) return s;
+    if (r->mode > 1) return fail(VDBC_E_INVALID, "mode must be EA (0) or PT (1)");
+    const bool count = (r->flags & VDBC_RENDER_COUNT) != 0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned long long* counter = reinterpret_cast<unsigned long long*>(ws);
+    vdbc_dims d{(uint32_t)v.nx, (uint32_t)v.ny, (uint32_t)v.nz};
+    uint64_t need = 0;
+    s = vdbc_render_workspace(r, d, &need);
+    if (s) return s;
+    if (need && (!ws || ws_bytes < need))
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace needs %llu bytes", (unsigned long long)need);
+    if (ws && reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(VDBC_E_INVALID, "workspace must be 256-byte aligned");
+    dim3 grid((cam.width + kTile - 1) / kTile, (cam.height + kTile - 1) / kTile);
+    if (count) {
+        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
+        if ((s = launch_check("zero counter"))) return s;
+    }
+    if (r->mode == VDBC_MODE_EA) {
+        if (!(r->step > 0.0f) || !std::isfinite(r->step))
+            return fail(VDBC_E_INVALID, "EA step must be finite and > 0");
+        // bound the per-ray loop: box diagonal / step <= 2^24 samples
+        const double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
+        if (diag / r->step > 16777216.0)
+            return fail(VDBC_E_INVALID, "EA step too small for this volume (> 2^24 samples per ray)");
+        const bool hdda = (r->flags & VDBC_RENDER_HDDA) && host_alpha(m, v.background) == 0.0f;
+#define EA_LAUNCH(H, CNT)                                                                      \
+    hipLaunchKernelGGL((ea_kernel<Acc, View, H, CNT>), grid, dim3(kBlock), 0, st, v, cam, m, \
+                       r->step, r->t_terminate, image, counter)
+        if (hdda) {
+            if (count) EA_LAUNCH(true, true);
+            else EA_LAUNCH(true, false);
+        } else {
+            if (count) EA_LAUNCH(false, true);
+            else EA_LAUNCH(false, false);
+        }
+#undef EA_LAUNCH
+        return launch_check("ea render");
+    }
+    if (r->spp == 0 || r->max_bounces == 0) return fail(VDBC_E_INVALID, "spp and max_bounces must be >= 1");
+    {
+        const double l = std::sqrt((double)med->light_dir[0] * med->light_dir[0] +
+                                   (double)med->light_dir[1] * med->light_dir[1] +
+                                   (double)med->light_dir[2] * med->light_dir[2]);
+        if (!(std::fabs(l - 1.0) <= 1e-3)) return fail(VDBC_E_INVALID, "light_dir must be a unit vector");
+        if (!std::isfinite(med->albedo) || med->albedo < 0.0f)
+            return fail(VDBC_E_INVALID, "albedo must be finite and >= 0");
+    }
+    float* maj = reinterpret_cast<float*>(static_cast<uint8_t*>(ws) + 256);
+    if (!(r->flags & VDBC_RENDER_KEEP_MAJORANT)) {
+        s = launch_majorant<Acc>(v, m, r->macrocell, maj, st);
+        if (s) return s;
+    }
+    PtArgs g;
+    g.spp = (int)r->spp;
+    g.max_bounces = (int)r->max_bounces;
+    g.C = (int)r->macrocell;
+    g.gx = (v.nx + g.C - 1) / g.C;
+    g.gy = (v.ny + g.C - 1) / g.C;
+    g.gz = (v.nz + g.C - 1) / g.C;
+    g.seed_lo = (uint32_t)r->seed;
+    g.seed_hi = (uint32_t)(r->seed >> 32);
+    g.frame = r->frame;
+#define PT_LAUNCH(CNT, AO)                                                                     \
+    hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO>), grid, dim3(kBlock), 0, st, v, cam, m, g, \
+                       maj, image, aov, counter)
+    if (count) {
+        if (aov) PT_LAUNCH(true, true);
+        else PT_LAUNCH(true, false);
+    } else {
+        if (aov) PT_LAUNCH(false, true);
+        else PT_LAUNCH(false, false);
+    }
+#undef PT_LAUNCH
+    return launch_check("pt render");
+}
+
+}  // namespace vdbc
+
+using namespace vdbc;
+
+extern "C" vdbc_status vdbc_sample(const vdbc_grid* g, const float* pos, uint64_t n,
+                                   uint32_t filter, float* out, void* stream)
+{
+    clear_error();
+    VdbView v;
+    vdbc_status s = make_view(g, &v);
+    if (s) return s;
+    if ((s = check_samples(pos, n, filter, out))) return s;
+    if (n == 0) return VDBC_OK;
+    hipLaunchKernelGGL((sample_kernel<VdbAcc, VdbView>), dim3((unsigned)((n + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, static_cast<hipStream_t>(stream), v, pos, n, (int)filter, out);
+    return launch_check("vdbc_sample");
+}
+
+extern "C" vdbc_status vdbc_sample_dense(const float* dense, vdbc_dims d, float background,
+                                         const float* pos, uint64_t n, uint32_t filter, float* out,
+                                         void* stream)
+{
+    clear_error();
+    DenseView v;
+    vdbc_status s = make_dense(dense, d, background, &v);
+    if (s) return s;
+    if ((s = check_samples(pos, n, filter, out))) return s;
+    if (n == 0) return VDBC_OK;
+    hipLaunchKernelGGL((sample_kernel<DenseAcc, DenseView>),
+                       dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), v, pos, n, (int)filter, out);
+    return launch_check("vdbc_sample_dense");
+}
+
+extern "C" vdbc_status vdbc_lookup(const vdbc_grid* g, const int32_t* ijk, uint64_t n, float* out,
+                                   void* stream)
+{
+    clear_error();
+    VdbView v;
+    vdbc_status s = make_view(g, &v);
+    if (s) return s;
+    if (n && (!ijk || !out)) return fail(VDBC_E_INVALID, "null coordinates or output");
+    if (n > (uint64_t)0x7FFFFFFFull * kBlock) return fail(VDBC_E_INVALID, "too many lookups");
+    if (n == 0) return VDBC_OK;
+    hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), v, ijk, n, out);
+    return launch_check("vdbc_lookup");
+}
+
+extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d,
+                                             uint64_t* bytes)
+{
+    if (!r || !bytes) return fail(VDBC_E_INVALID, "null argument");
+    if (d.nx == 0 || d.ny == 0 || d.nz == 0) return fail(VDBC_E_INVALID, "zero dims");
+    if (r->mode == VDBC_MODE_PT) {
+        if (r->macrocell < 4 || r->macrocell > 64)
+            return fail(VDBC_E_INVALID, "macrocell must be in [4, 64]");
+        *bytes = 256 + align256(majorant_bytes(r->macrocell, (int)d.nx, (int)d.ny, (int)d.nz));
+    } else {
+        *bytes = (r->flags & VDBC_RENDER_COUNT) ? 256 : 0;
+    }
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
+                                   const vdbc_render_params* r, float* image, float* aov, void* ws,
+                                   uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    VdbView v;
+    vdbc_status s = make_view(g, &v);
+    if (s) return s;
+    return render_impl<VdbAcc>(v, c, m, r, image, aov, ws, ws_bytes, stream);
+}
+
+extern "C" vdbc_status vdbc_render_dense(const float* dense, vdbc_dims d, float background,
+                                         const vdbc_camera* c, const vdbc_medium* m,
+                                         const vdbc_render_params* r, float* image, float* aov,
+                                         void* ws, uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    DenseView v;
+    vdbc_status s = make_dense(dense, d, background, &v);
+    if (s) return s;
+    return render_impl<DenseAcc>(v, c, m, r, image, aov, ws, ws_bytes, stream);
+}
+
+extern "C" vdbc_status vdbc_majorant(const vdbc_grid* g, const vdbc_medium* med, uint32_t C,
+                                     float* out, void* stream)
+{
+    clear_error();
+    VdbView v;
+    vdbc_status s = make_view(g, &v);
+    if (s) return s;
+    if (!out) return fail(VDBC_E_INVALID, "null output");
+    if (C < 4 || C > 64) return fail(VDBC_E_INVALID, "macrocell must be in [4, 64]");
+    MediumK m;
+    if ((s = make_medium(med, v.nx, v.ny, v.nz, &m))) return s;
+    return launch_majorant<VdbAcc>(v, m, C, out, static_cast<hipStream_t>(stream));
+}
+
+extern "C" vdbc_status vdbc_majorant_dense(const float* dense, vdbc_dims d, float background,
+                                           const vdbc_medium* med, uint32_t C, float* out,
+                                           void* stream)
+{
+    clear_error();
+    DenseView v;
+    vdbc_status s = make_dense(dense, d, background, &v);
+    if (s) return s;
+    if (!out) return fail(VDBC_E_INVALID, "null output");
+    if (C < 4 || C > 64) return fail(VDBC_E_INVALID, "macrocell must be in [4, 64]");
+    MediumK m;
+    if ((s = make_medium(med, v.nx, v.ny, v.nz, &m))) return s;
+    return launch_majorant<DenseAcc>(v, m, C, out, static_cast<hipStream_t>(stream));
+}
+
+extern "C" vdbc_status vdbc_philox(const uint32_t* ctr, const uint32_t* key, uint64_t n,
+                                   uint32_t* out, void* stream)
+{
+    clear_error();
+    if (n && (!ctr || !key || !out)) return fail(VDBC_E_INVALID, "null argument");
+    if (n > (uint64_t)0x7FFFFFFFull * kBlock) return fail(VDBC_E_INVALID, "too many counters");
+    if (n == 0) return VDBC_OK;
+    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), ctr, key, n, out);
+    return launch_check("vdbc_philox");
+}

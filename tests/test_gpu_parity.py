@@ -1,0 +1,366 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Bars: bit-exact for lookups, nearest samples and Philox;
+trilinear |d| <= 1e-6 * max|corner|; emission-absorption pixels within 1e-5;
+path-traced images within relMSE 1e-4 at matched seeds."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from paper_2504_04564_amd import _build, vdbc
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    _build.ensure_built()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return vdbc.load()
+
+
+def relmse(x, y):
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    return float(np.mean((x - y) ** 2 / (y * y + 0.01)))
+
+
+def _rand(shape, seed, zero=0.6):
+    rng = np.random.default_rng(seed)
+    v = rng.random(shape, dtype=np.float32)
+    v[rng.random(shape) < zero] = 0.0
+    return v
+
+
+def _dense_t(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).cuda()
+
+
+def _cuda(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.cuda() if dtype is None else t.to(dtype).cuda()
+
+
+# ---------------------------------------------------------------- Philox
+
+def test_philox_bit_exact():
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2 ** 32, size=(65536 + 17, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(65536 + 17, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0], key[0] = 0, 0
+    ctr[1], key[1] = 0xFFFFFFFF, 0xFFFFFFFF
+    got = vdbc.philox(_cuda(ctr.view(np.int32)), _cuda(key.view(np.int32)))
+    got = got.cpu().numpy().view(np.uint32).reshape(-1, 4)
+    for i in range(len(ctr)):
+        assert np.array_equal(got[i], oracle.philox(ctr[i], key[i])), i
+
+
+# ---------------------------------------------------------------- lookups
+
+LOOKUP_CASES = [((64, 64, 64), 0.25, 2, 0), ((37, 50, 70), 0.3, 1, 0),
+                ((37, 50, 70), 0.3, 3, vdbc.NO_PRUNE), ((130, 20, 140), 0.5, 2, vdbc.NO_CORNERS),
+                ((1, 1, 1), 1.0, 2, 0), ((200, 9, 3), 0.6, 2, 0), ((129, 257, 33), 0.07, 2, 0)]
+
+
+def _all_ijk(shape, pad=2):
+    nz, ny, nx = shape
+    g = np.stack(np.meshgrid(np.arange(-pad, nx + pad), np.arange(-pad, ny + pad),
+                             np.arange(-pad, nz + pad), indexing="ij"), -1)
+    return g.reshape(-1, 3).astype(np.int32)
+
+
+@pytest.mark.parametrize("shape,q,metric,flags", LOOKUP_CASES)
+def test_lookup_every_voxel_bit_exact(shape, q, metric, flags):
+    v = _rand(shape, 41)
+    v[: shape[0] // 2, : shape[1] // 2, : shape[2] // 2] = np.float32(0.75)
+    buf, st = vdbc.encode(v, q, metric, flags)
+    g = vdbc.Grid(buf)
+    ijk = _all_ijk(shape)
+    got = vdbc.lookup(g, _cuda(ijk)).cpu().numpy()
+    want = oracle.lookup(oracle.VdbField(buf), ijk.astype(np.int64))
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    R = oracle.reconstruct(v, q, metric, flags)
+    inside = np.all((ijk >= 0) & (ijk < [shape[2], shape[1], shape[0]]), axis=1)
+    assert np.array_equal(got[inside], R[ijk[inside, 2], ijk[inside, 1], ijk[inside, 0]])
+    assert np.all(got[~inside] == np.float32(st["background"]))
+
+
+# ---------------------------------------------------------------- sampling
+
+def _positions(shape, n, seed, margin=2.0):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    p = rng.uniform([-margin] * 3, [nx + margin, ny + margin, nz + margin], size=(n, 3))
+    p = p.astype(np.float32)
+    # exact lattice points, half points, leaf and brick boundaries
+    k = min(n // 4, 4096)
+    p[:k] = np.floor(p[:k])
+    p[k:2 * k] = np.floor(p[k:2 * k]) + 0.5
+    p[2 * k:2 * k + 64, 0] = np.float32(7.0) + np.arange(64, dtype=np.float32) / 64
+    return p
+
+
+def _corner_scale(fld, p):
+    i0 = np.floor(p.astype(np.float64)).astype(np.int64)
+    m = np.zeros(len(p))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                c = oracle.lookup(fld, i0 + [dx, dy, dz])
+                m = np.maximum(m, np.abs(c))
+    return m
+
+
+@pytest.mark.parametrize("shape,q", [((64, 64, 64), 0.25), ((37, 50, 70), 0.5),
+                                     ((130, 20, 140), 0.1)])
+def test_trilinear_vdb_and_dense_within_1e6(shape, q):
+    v = _rand(shape, 43, zero=0.4)
+    buf, st = vdbc.encode(v, q)
+    g = vdbc.Grid(buf)
+    p = _positions(shape, 200_003, 44)
+    fv = oracle.VdbField(buf)
+    want = oracle.sample(fv, p)
+    got = vdbc.sample(g, _cuda(p)).cpu().numpy().astype(np.float64)
+    tol = 1e-6 * _corner_scale(fv, p) + 1e-30
+    assert np.all(np.abs(got - want) <= tol)
+    # dense baseline on the original grid
+    fd = oracle.DenseField(v, st["background"])
+    want_d = oracle.sample(fd, p)
+    got_d = vdbc.sample_dense(_dense_t(v), st["background"], _cuda(p)).cpu().numpy()
+    tol_d = 1e-6 * _corner_scale(fd, p) + 1e-30
+    assert np.all(np.abs(got_d.astype(np.float64) - want_d) <= tol_d)
+
+
+def test_nearest_bit_exact():
+    shape = (37, 50, 70)
+    v = _rand(shape, 45)
+    buf, st = vdbc.encode(v, 0.4)
+    g = vdbc.Grid(buf)
+    p = _positions(shape, 50_001, 46)
+    got = vdbc.sample(g, _cuda(p), filter=0).cpu().numpy()
+    want = oracle.sample(oracle.VdbField(buf), p, filter=0).astype(np.float32)
+    assert np.array_equal(got, want)
+    got_d = vdbc.sample_dense(_dense_t(v), st["background"], _cuda(p), filter=0).cpu().numpy()
+    want_d = oracle.sample(oracle.DenseField(v, st["background"]), p, filter=0).astype(np.float32)
+    assert np.array_equal(got_d, want_d)
+
+
+def test_lossless_vdb_sample_equals_dense_bitwise():
+    shape = (70, 33, 45)
+    v = _rand(shape, 47, zero=0.5)
+    buf, st = vdbc.encode(v, 1.0)
+    g = vdbc.Grid(buf)
+    p = _positions(shape, 100_000, 48)
+    a = vdbc.sample(g, _cuda(p)).cpu().numpy()
+    b = vdbc.sample_dense(_dense_t(v), st["background"], _cuda(p)).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_sample_edge_cases():
+    # empty input, a single voxel volume, one position
+    v = np.full((1, 1, 1), 0.5, np.float32)
+    buf, st = vdbc.encode(v, 1.0)
+    g = vdbc.Grid(buf)
+    empty = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    assert vdbc.sample(g, empty).numel() == 0
+    p = np.array([[0, 0, 0], [0.25, 0, 0], [-1, 0, 0], [5, 5, 5]], np.float32)
+    got = vdbc.sample(g, _cuda(p)).cpu().numpy()
+    want = oracle.sample(oracle.VdbField(buf), p)
+    assert np.allclose(got, want, atol=1e-7, rtol=0)
+    # far away positions read the background
+    far = np.array([[1e9, -1e9, 3e7], [-5e5, 0, 0]], np.float32)
+    assert np.all(vdbc.sample(g, _cuda(far)).cpu().numpy() == st["background"])
+
+
+def test_full_size_lookup_and_sample_mid_volume():
+    # the 512^3 cloud at 1:10 that the benchmark renders: sampled lookups,
+    # every voxel on brick/leaf boundary planes of a slab, random samples
+    v = synth.mid_volume()
+    buf, st = vdbc.encode(v, 0.10)
+    g = vdbc.Grid(buf)
+    fld = oracle.VdbField(buf)
+    rng = np.random.default_rng(49)
+    ijk = rng.integers(-1, 513, size=(1_000_000, 3)).astype(np.int32)
+    yy, zz = np.meshgrid(np.arange(512), np.arange(0, 512, 31), indexing="ij")
+    for x in (7, 8, 31, 32, 127, 128, 255, 256, 511):
+        ijk = np.concatenate([ijk, np.stack([np.full(yy.size, x), yy.ravel(), zz.ravel()],
+                                            1).astype(np.int32)])
+    got = vdbc.lookup(g, _cuda(ijk)).cpu().numpy()
+    want = oracle.lookup(fld, ijk.astype(np.int64))
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    p = _positions(v.shape, 500_000, 50)
+    got = vdbc.sample(g, _cuda(p)).cpu().numpy().astype(np.float64)
+    want = oracle.sample(fld, p)
+    assert np.all(np.abs(got - want) <= 1e-6 * _corner_scale(fld, p) + 1e-30)
+
+
+# ---------------------------------------------------------------- majorant
+
+TF5 = dict(tf=[(0.2, 0.3, 0.9, 0.0), (0.9, 0.1, 0.2, 0.8), (0.4, 0.4, 0.4, 0.3),
+               (1.0, 1.0, 0.0, 1.0), (0.0, 1.0, 1.0, 0.5)], tf_range=(0.1, 0.9))
+
+
+@pytest.mark.parametrize("C", [4, 8, 16])
+def test_majorant_vs_oracle(C):
+    shape = (45, 37, 70)
+    v = _rand(shape, 51, zero=0.5)
+    buf, st = vdbc.encode(v, 0.4)
+    med = dict(sigma_scale=6.0, **TF5)
+    got = vdbc.majorant(vdbc.Grid(buf), med, C).cpu().numpy()
+    want = oracle.majorant(oracle.VdbField(buf), med, C)
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-12)
+    got_d = vdbc.majorant(_dense_t(v), med, C, background=st["background"]).cpu().numpy()
+    want_d = oracle.majorant(oracle.DenseField(v, st["background"]), med, C)
+    np.testing.assert_allclose(got_d, want_d, rtol=2e-6, atol=1e-12)
+
+
+# ---------------------------------------------------------------- EA
+
+def _tiny():
+    v = synth.tiny_volume()
+    buf, st = vdbc.encode(v, synth.scenes.TINY["rate"])
+    return v, buf, st
+
+
+def test_ea_tiny_config_within_1e5():
+    # 64^3 sphere cloud at 1:4, 128x128 orthographic, step 0.5, sigma_t = 8 density
+    v, buf, st = _tiny()
+    cam = scenes.ortho_z_camera(64, 64, 128, 128)
+    med = scenes.ea_medium(8.0)
+    prm = dict(step=0.5)
+    want = oracle.render_ea(oracle.VdbField(buf), cam, med, prm)
+    got = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_EA).cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-5
+    want_d = oracle.render_ea(oracle.DenseField(v, 0.0), cam, med, prm)
+    got_d = vdbc.render(_dense_t(v), cam, med, prm, vdbc.MODE_EA, background=0.0).cpu().numpy()
+    assert np.max(np.abs(got_d - want_d)) <= 1e-5
+
+
+def test_ea_pinhole_and_hdda_bitwise():
+    v, buf, st = _tiny()
+    g = vdbc.Grid(buf)
+    cam = scenes.orbit_camera((64, 64, 64), 96, 80)
+    med = scenes.ea_medium(8.0)
+    prm = dict(step=0.5)
+    want = oracle.render_ea(oracle.VdbField(buf), cam, med, prm)
+    off = vdbc.render(g, cam, med, prm, vdbc.MODE_EA).cpu().numpy()
+    on = vdbc.render(g, cam, med, dict(step=0.5, flags=vdbc.RENDER_HDDA), vdbc.MODE_EA)
+    on = on.cpu().numpy()
+    assert np.max(np.abs(off - want)) <= 1e-5
+    assert np.array_equal(on.view(np.uint32), off.view(np.uint32))
+    # HDDA also skips on a sparse 1:20 grid with big empty nodes
+    big = synth.mid_volume(n=256)
+    b2, _ = vdbc.encode(big, 0.05)
+    g2 = vdbc.Grid(b2)
+    cam2 = scenes.orbit_camera((256, 256, 256), 64, 64)
+    a = vdbc.render(g2, cam2, med, prm, vdbc.MODE_EA).cpu().numpy()
+    b = vdbc.render(g2, cam2, med, dict(step=0.5, flags=vdbc.RENDER_HDDA), vdbc.MODE_EA)
+    assert np.array_equal(a.view(np.uint32), b.cpu().numpy().view(np.uint32))
+
+
+def test_ea_lossless_vdb_equals_dense_bitwise():
+    v = synth.tiny_volume()
+    buf, st = vdbc.encode(v, 1.0)
+    cam = scenes.orbit_camera((64, 64, 64), 64, 48)
+    med = scenes.ea_medium(8.0)
+    a = vdbc.render(vdbc.Grid(buf), cam, med, dict(step=0.5), vdbc.MODE_EA).cpu().numpy()
+    b = vdbc.render(_dense_t(v), cam, med, dict(step=0.5), vdbc.MODE_EA, background=0.0)
+    assert np.array_equal(a.view(np.uint32), b.cpu().numpy().view(np.uint32))
+
+
+def test_ea_sample_count():
+    v, buf, st = _tiny()
+    cam = scenes.ortho_z_camera(64, 64, 128, 128)
+    med = scenes.ea_medium(8.0)
+    r = vdbc.Renderer(vdbc.Grid(buf), cam, med, dict(step=0.5, flags=vdbc.RENDER_COUNT),
+                      vdbc.MODE_EA)
+    r.launch()
+    torch.cuda.synchronize()
+    assert r.sample_count() == 128 * 128 * 128   # 64 voxels / 0.5 per ray
+
+
+# ---------------------------------------------------------------- PT
+
+def _pt_scene(n, w, h, spp, seed=0x5EED, bounces=8):
+    cam = scenes.orbit_camera((n, n, n), w, h)
+    med = scenes.pt_medium(64.0)
+    prm = dict(spp=spp, max_bounces=bounces, seed=seed, macrocell=8)
+    return cam, med, prm
+
+
+@pytest.mark.parametrize("q", [0.25, 0.10])
+def test_pt_small_relmse(q):
+    v = synth.mid_volume(n=96)
+    buf, st = vdbc.encode(v, q)
+    cam, med, prm = _pt_scene(96, 52, 44, 4)
+    want, want_aov = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, aov=True)
+    img, aov = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT, aov=True)
+    got = img.cpu().numpy().reshape(-1, 4)
+    assert relmse(got, want) <= 1e-4
+    assert relmse(aov.cpu().numpy().reshape(-1, 2), want_aov) <= 1e-4
+    want_d = oracle.render_pt(oracle.DenseField(v, 0.0), cam, med, prm)
+    got_d = vdbc.render(_dense_t(v), cam, med, prm, vdbc.MODE_PT, background=0.0)
+    assert relmse(got_d.cpu().numpy().reshape(-1, 4), want_d) <= 1e-4
+
+
+def test_pt_lossless_vdb_equals_dense_bitwise_and_deterministic():
+    v = synth.mid_volume(n=64)
+    buf, _ = vdbc.encode(v, 1.0)
+    cam, med, prm = _pt_scene(64, 40, 36, 3)
+    g = vdbc.Grid(buf)
+    a = vdbc.render(g, cam, med, prm, vdbc.MODE_PT).cpu().numpy()
+    a2 = vdbc.render(g, cam, med, prm, vdbc.MODE_PT).cpu().numpy()
+    b = vdbc.render(_dense_t(v), cam, med, prm, vdbc.MODE_PT, background=0.0).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), a2.view(np.uint32))
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_pt_white_furnace_and_zero_density():
+    n = 32
+    v = np.full((n, n, n), 1.0, np.float32)
+    buf, _ = vdbc.encode(v, 1.0)
+    cam = scenes.orbit_camera((n, n, n), 24, 24)
+    med = dict(sigma_scale=40.0, albedo=1.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(0.25, 0.5, 1.0))
+    img = vdbc.render(vdbc.Grid(buf), cam, med, dict(spp=4, max_bounces=100000, seed=3),
+                      vdbc.MODE_PT).cpu().numpy()
+    np.testing.assert_allclose(img[..., :3], np.broadcast_to([0.25, 0.5, 1.0], img[..., :3].shape),
+                               rtol=1e-6)
+    z = np.zeros((n, n, n), np.float32)
+    img = vdbc.render(_dense_t(z), cam, scenes.pt_medium(), dict(spp=2, seed=3), vdbc.MODE_PT,
+                      background=0.0).cpu().numpy()
+    amb = np.asarray(scenes.pt_medium()["ambient"], np.float32)
+    assert np.all(img[..., :3] == amb) and np.all(img[..., 3] == 0)
+
+
+def test_pt_sample_count_and_ragged_image():
+    v = synth.mid_volume(n=64)
+    buf, _ = vdbc.encode(v, 0.25)
+    cam, med, prm = _pt_scene(64, 17, 5, 2)
+    prm["flags"] = vdbc.RENDER_COUNT
+    r = vdbc.Renderer(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT)
+    img = r.launch().cpu().numpy()
+    want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm)
+    assert relmse(img.reshape(-1, 4), want) <= 1e-4
+    assert r.sample_count() > 17 * 5 * 2
+
+
+def test_pt_mid_config_sampled_pixels():
+    # the benchmark's launch: 512^3 cloud at 1:10, 1024x1024, 16 spp, 8 bounces;
+    # the oracle renders a sample of the pixels one by one
+    v = synth.mid_volume()
+    buf, st = vdbc.encode(v, 0.10)
+    M = scenes.MID
+    cam = scenes.orbit_camera((512, 512, 512), M["width"], M["height"])
+    med = scenes.pt_medium(64.0)
+    prm = dict(spp=M["spp"], max_bounces=M["max_bounces"], seed=M["seed"], macrocell=8)
+    img = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
+    rng = np.random.default_rng(52)
+    pix = np.sort(rng.choice(M["width"] * M["height"], 192, replace=False)).astype(np.uint32)
+    want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, pixels=pix)
+    assert relmse(img[pix], want) <= 1e-4
+    assert np.all(np.isfinite(img))

@@ -1,0 +1,193 @@
+"""Host-side checks of libvdbc.so that need no GPU: the C ABI exports every
+declared symbol, the host encoder writes the oracle's canonical bytes, the
+validator, and argument errors reported before any device work."""
+import ctypes as C
+import os
+from collections import Counter
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2504_04564_amd import _build, vdbc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    _build.ensure_built()
+    return vdbc.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    hdr = open(os.path.join(ROOT, "include", "vdbc.h")).read()
+    names = set(re.findall(r"\b(vdbc_[a-z_0-9]+)\s*\(", hdr))
+    assert len(names) >= 18
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert lib.vdbc_abi_version() == 1
+
+
+def _rand(shape, seed, zero=0.6):
+    rng = np.random.default_rng(seed)
+    v = rng.random(shape, dtype=np.float32)
+    v[rng.random(shape) < zero] = 0.0
+    return v
+
+
+ENC_CASES = [
+    ((64, 64, 64), 0.25, 2, 0), ((37, 50, 70), 0.3, 1, 0), ((37, 50, 70), 0.3, 3, 4),
+    ((130, 20, 140), 0.5, 2, 2), ((8, 8, 8), 1.0, 2, 0), ((200, 9, 3), 0.6, 2, 0),
+    ((1, 1, 1), 1.0, 2, 0), ((1, 1, 1), 0.1, 2, 0), ((40, 40, 40), 0.01, 2, 1),
+    ((129, 257, 33), 0.07, 2, 0), ((16, 300, 16), 1.0, 3, 0),
+]
+
+
+@pytest.mark.parametrize("shape,q,metric,flags", ENC_CASES)
+def test_encoder_bytes_equal_oracle(shape, q, metric, flags):
+    v = _rand(shape, 31)
+    v[: shape[0] // 2, : shape[1] // 2, : shape[2] // 2] = np.float32(0.75)
+    bg = 0.5 if flags & 1 else 0.0
+    b1, s1 = vdbc.encode(v, q, metric, flags, bg)
+    b2, s2 = oracle.encode(v, q, metric, flags, bg)
+    assert b1.size == b2.size
+    assert np.array_equal(b1, b2)
+    assert s1 == s2
+    assert vdbc.validate(b1)["n_leaf"] == s2["n_leaf"]
+
+
+def test_encoder_bytes_equal_oracle_clouds():
+    for v, q in ((synth.tiny_volume(), 0.25), (synth.mid_volume(n=160), 0.1),
+                 (synth.mid_volume(n=128), 0.05)):
+        for threads in (1, 3, 0):
+            b1, _ = vdbc.encode(v, q, threads=threads)
+            b2, _ = oracle.encode(v, q)
+            assert np.array_equal(b1, b2)
+
+
+def test_encoder_background_without_dominant_value():
+    # dense noise: no bucket dominates, the exact mode falls back to sorting
+    v = synth.dense_noise(40, seed=5)
+    v.ravel()[::97] = np.float32(0.3125)     # a clear mode
+    b1, s1 = vdbc.encode(v, 1.0)
+    assert s1["background"] == np.float32(0.3125)
+    assert s1["background"] == oracle.background(v)
+    w = synth.dense_noise(24, seed=6)         # a few duplicates: smallest of them wins
+    _, s2 = vdbc.encode(w, 0.5)
+    c = Counter(float(x) for x in w.ravel())
+    top = max(c.values())
+    assert s2["background"] == oracle.background(w) == min(x for x, k in c.items() if k == top)
+
+
+def test_encoder_negative_zero_background():
+    v = np.zeros((16, 16, 16), np.float32)
+    v[::2] = -0.0
+    v[0, 0, :3] = 1.0
+    _, s = vdbc.encode(v, 0.5)
+    assert s["background"] == 0.0 and not np.signbit(s["background"])
+
+
+def test_encoder_rejects_bad_input():
+    v = np.zeros((4, 4, 4), np.float32)
+    for q in (0.0, -0.5, 1.01, float("nan")):
+        with pytest.raises(vdbc.VdbcError) as e:
+            vdbc.encode(v, q)
+        assert e.value.status == vdbc.E_INVALID
+    w = v.copy()
+    w[3, 2, 1] = np.inf
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.encode(w, 0.5)
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.encode(v, 0.5, metric=0)
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.encode(v, 0.5, flags=vdbc.BG_EXPLICIT, background=float("nan"))
+
+
+def test_one_shot_encode_size_query(lib):
+    v = _rand((20, 20, 20), 3)
+    d = vdbc.Dims(20, 20, 20)
+    p = vdbc.EncodeParams(0.5, 2, 0, 0.0, 0)
+    need = C.c_uint64(0)
+    st = lib.vdbc_encode(v.ctypes.data, d, C.byref(p), None, 0, C.byref(need), None)
+    assert st == vdbc.E_BUFFER_TOO_SMALL and need.value > 0
+    raw = np.zeros(need.value + 256, np.uint8)
+    off = (-raw.ctypes.data) % 256
+    out = raw[off:off + need.value]
+    st = lib.vdbc_encode(v.ctypes.data, d, C.byref(p), out.ctypes.data, need.value - 1,
+                         C.byref(need), None)
+    assert st == vdbc.E_BUFFER_TOO_SMALL
+    st = lib.vdbc_encode(v.ctypes.data, d, C.byref(p), out.ctypes.data, need.value,
+                         C.byref(need), None)
+    assert st == vdbc.OK
+    assert np.array_equal(out, oracle.encode(v, 0.5)[0])
+
+
+def test_validator_rejects_corruption():
+    v = _rand((40, 40, 40), 9)
+    buf, _ = vdbc.encode(v, 0.5)
+    vdbc.validate(buf)
+    for off, val in ((0, 0x58), (4, 2), (36, 1), (152, 1), (104, 1)):
+        bad = buf.copy()
+        bad[off] = val
+        with pytest.raises(vdbc.VdbcError) as e:
+            vdbc.validate(bad)
+        assert e.value.status == vdbc.E_FORMAT
+    # a prefix word in the upper node
+    bad = buf.copy()
+    h = np.frombuffer(buf[:256].tobytes(), np.uint8)
+    off_upper = int(np.frombuffer(h[104:112].tobytes(), "<u8")[0])
+    bad[off_upper + 32 + 8] ^= 1
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.validate(bad)
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.validate(buf[:-256])
+
+
+def test_device_calls_reject_bad_arguments_before_launch(lib):
+    # every check below fails before any HIP call, so it runs without a GPU
+    g = vdbc.GridC()
+    assert lib.vdbc_grid_init(C.byref(g), None, 0, None) == vdbc.E_INVALID
+    buf, _ = vdbc.encode(_rand((16, 16, 16), 1), 0.5)
+    assert lib.vdbc_grid_init(C.byref(g), 256, 16, buf.ctypes.data) == vdbc.E_FORMAT
+    assert lib.vdbc_grid_init(C.byref(g), 257, buf.size, buf.ctypes.data) == vdbc.E_INVALID
+    assert lib.vdbc_grid_init(C.byref(g), 512, buf.size, buf.ctypes.data) == vdbc.OK
+    assert lib.vdbc_sample(C.byref(g), 1024, 10, 2, 2048, None) == vdbc.E_INVALID
+    assert lib.vdbc_sample(C.byref(g), None, 10, 1, 2048, None) == vdbc.E_INVALID
+    assert lib.vdbc_sample(C.byref(g), None, 0, 1, None, None) == vdbc.OK   # empty
+    d = vdbc.Dims(0, 4, 4)
+    assert lib.vdbc_sample_dense(1024, d, 0.0, 2048, 4, 1, 4096, None) == vdbc.E_INVALID
+    cam = vdbc.camera_c(dict(kind=0, width=0, height=4))
+    med = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)]))
+    prm = vdbc.params_c(dict(), vdbc.MODE_EA)
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(prm), 4096, None,
+                           None, 0, None) == vdbc.E_INVALID
+    cam = vdbc.camera_c(dict(kind=0, width=4, height=4, dir=(0, 0, 1)))
+    bad = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0)]))
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(bad), C.byref(prm), 4096, None,
+                           None, 0, None) == vdbc.E_INVALID
+    pt = vdbc.params_c(dict(spp=1), vdbc.MODE_PT)
+    ws = C.c_uint64(0)
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
+    assert ws.value == 256 + 256
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(pt), 4096, None,
+                           8192, ws.value - 1, None) == vdbc.E_BUFFER_TOO_SMALL
+    pt.macrocell = 3
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == \
+        vdbc.E_INVALID
+    assert lib.vdbc_status_string(3) == b"buffer too small"
+    # degenerate scenes are refused before launch
+    zero_dir = vdbc.camera_c(dict(kind=0, width=4, height=4))
+    assert lib.vdbc_render(C.byref(g), C.byref(zero_dir), C.byref(med), C.byref(prm), 4096,
+                           None, None, 0, None) == vdbc.E_INVALID
+    pt.macrocell = 8
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
+    no_light = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)],
+                                  light_dir=(0, 0, 0)))
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(no_light), C.byref(pt), 4096,
+                           None, 8192, ws.value, None) == vdbc.E_INVALID
+    tiny_step = vdbc.params_c(dict(step=1e-6), vdbc.MODE_EA)
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(tiny_step), 4096,
+                           None, None, 0, None) == vdbc.E_INVALID

@@ -89,6 +89,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the dense renderer and the random-sample microbenchmark")
+    ap.add_argument("--macrocell", type=int, default=16, help="majorant cell edge in voxels")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -108,6 +111,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                          "launches": 3}))
+        return
     M = scenes.MID
     n = args.size
     W, H, spp, bounces = M["width"], M["height"], M["spp"], M["max_bounces"]
@@ -125,7 +138,8 @@ def main():
     dense = torch.from_numpy(vol).cuda()
     cam = scenes.orbit_camera((n, n, n), W, H)
     med = scenes.pt_medium(64.0)
-    prm = dict(spp=spp, max_bounces=bounces, seed=M["seed"], macrocell=8,
+    C = args.macrocell
+    prm = dict(spp=spp, max_bounces=bounces, seed=M["seed"], macrocell=C,
                flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
     rays = W * H * spp
 
@@ -180,11 +194,11 @@ def main():
         pix = np.sort(rng.choice(W * H, args.cpu_pixels, replace=False)).astype(np.uint32)
         fld = oracle.VdbField(buf)
         t = time.time()
-        oracle.majorant(fld, med, 8)
+        oracle.majorant(fld, med, C)
         t_maj = time.time() - t
         t = time.time()
         ref = oracle.render_pt(fld, cam, med, dict(spp=spp, max_bounces=bounces,
-                                                   seed=M["seed"], macrocell=8), pixels=pix)
+                                                   seed=M["seed"], macrocell=C), pixels=pix)
         t_all = time.time() - t
         t_paths = max(t_all - t_maj, 1e-9)
         frame_s = t_maj + t_paths * (W * H / len(pix))
@@ -215,7 +229,7 @@ def main():
             "workload": f"fbm-cloud-{n}^3-vdb-1:{round(1 / args.rate)}-pt-{W}x{H}x{spp}spp-"
                         f"{bounces}bounces",
             "dims": [n, n, n], "rate": args.rate, "width": W, "height": H, "spp": spp,
-            "max_bounces": bounces, "macrocell": 8,
+            "max_bounces": bounces, "macrocell": C,
             "vdb_bytes": int(buf.size), "dense_bytes": int(vol.nbytes),
             "achieved_rate": round(st["achieved_rate"], 5),
         },

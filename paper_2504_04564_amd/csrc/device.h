@@ -50,6 +50,18 @@ struct Rng {
         frame = f;
         d = 0;
     }
+    // Positions the stream at draw `pos` (regenerating its block if needed).
+    __device__ __forceinline__ void seek(uint32_t pos)
+    {
+        d = pos;
+        if (pos & 3u) {
+            w0 = pos >> 2;
+            w1 = sample;
+            w2 = tag;
+            w3 = frame;
+            philox4x32_10(w0, w1, w2, w3, k0, k1);
+        }
+    }
     __device__ __forceinline__ float next()
     {
         const uint32_t q = d & 3u;

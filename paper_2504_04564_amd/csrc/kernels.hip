@@ -46,7 +46,7 @@ __device__ __forceinline__ void block_count(uint32_t n, unsigned long long* coun
 
 __global__ void zero_u64(unsigned long long* p)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+    if (threadIdx.x < 2 && blockIdx.x == 0) p[threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------- sampling
@@ -173,173 +173,330 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
 
 struct PtArgs {
     int spp, max_bounces, C, gx, gy, gz;
+    int lf, cgx, cgy, cgz, cwords;   // coarse blocks of 2^lf macrocells per axis, bit words
     uint32_t seed_lo, seed_hi, frame;
 };
 
-// Free-flight distance by delta tracking inside the cells of the majorant
-// grid visited in order by a 3D-DDA (Section 4); empty cells are skipped and
-// a flight that overshoots a cell restarts at its exit.  Returns true with
-// the collision distance and the density sampled there.
-template <class Acc>
-__device__ bool free_flight(Acc& acc, const MediumK& m, const float* __restrict__ maj,
-                            const PtArgs& g, const float o[3], const float d[3], float t0,
-                            float t1, Rng& rng, float& t_hit, float& s_hit, uint32_t& nsamp)
+// Occupancy of the coarse blocks: bit set iff some macrocell of the block has
+// a non-zero majorant.  One thread per block; a wave ballot assembles two
+// 32-bit words per wave.
+__global__ __launch_bounds__(kBlock) void coarse_bits_kernel(const float* __restrict__ maj,
+                                                             PtArgs g, uint32_t* __restrict__ bits)
 {
-    if (!(t0 < t1)) return false;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncoarse = g.cgx * g.cgy * g.cgz;
+    const int F = 1 << g.lf;
+    bool occ = false;
+    if (cell < ncoarse) {
+        const int bx = cell % g.cgx, by = (cell / g.cgx) % g.cgy, bz = cell / (g.cgx * g.cgy);
+        for (int z = bz * F; z < min(bz * F + F, g.gz) && !occ; ++z)
+            for (int y = by * F; y < min(by * F + F, g.gy) && !occ; ++y)
+                for (int x = bx * F; x < min(bx * F + F, g.gx); ++x)
+                    if (maj[x + g.gx * (y + g.gy * z)] > 0.0f) {
+                        occ = true;
+                        break;
+                    }
+    }
+    const uint64_t ballot = __ballot(occ);
+    const int lane = threadIdx.x & 63;
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x - lane) >> 5;   // first word of the wave
+    if (lane == 0 && w < g.cwords) bits[w] = (uint32_t)ballot;
+    if (lane == 0 && w + 1 < g.cwords) bits[w + 1] = (uint32_t)(ballot >> 32);
+}
+
+// One ray segment being tracked through the majorant grid (Section 4): a 3D
+// DDA over macrocells, hierarchical over coarse blocks of macrocells whose
+// occupancy bits live in LDS, and delta tracking inside non-empty cells.
+struct Flight {
+    float o[3], d[3], id[3];
+    float t, t1, te, mu, imu;
+    int cx, cy, cz, axis;
+    bool incell, ok;
+    uint32_t budget;
+};
+
+// Starts a segment: clip to the box and find the first macrocell.
+__device__ __forceinline__ void flight_begin(Flight& f, const PtArgs& g, int nx, int ny, int nz,
+                                             const float o[3], const float d[3], float& t0)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f.o[a] = o[a];
+        f.d[a] = d[a];
+        f.id[a] = 1.0f / d[a];
+    }
+    f.incell = false;
+    f.budget = kMaxFlightSamples;
+    f.ok = box_clip(nx, ny, nz, o, d, t0, f.t1);
+    f.t = t0;
+    if (!f.ok) return;
     const float C = (float)g.C;
-    int cx = (int)floorf((fmaf(t0, d[0], o[0]) + 0.5f) / C);
-    int cy = (int)floorf((fmaf(t0, d[1], o[1]) + 0.5f) / C);
-    int cz = (int)floorf((fmaf(t0, d[2], o[2]) + 0.5f) / C);
-    cx = min(max(cx, 0), g.gx - 1);
-    cy = min(max(cy, 0), g.gy - 1);
-    cz = min(max(cz, 0), g.gz - 1);
-    const int sx = d[0] > 0.0f ? 1 : (d[0] < 0.0f ? -1 : 0);
-    const int sy = d[1] > 0.0f ? 1 : (d[1] < 0.0f ? -1 : 0);
-    const int sz = d[2] > 0.0f ? 1 : (d[2] < 0.0f ? -1 : 0);
-    const float ix = 1.0f / d[0], iy = 1.0f / d[1], iz = 1.0f / d[2];
-    float t = t0;
-    uint32_t budget = kMaxFlightSamples;
+    f.cx = min(max((int)floorf((fmaf(t0, d[0], o[0]) + 0.5f) / C), 0), g.gx - 1);
+    f.cy = min(max((int)floorf((fmaf(t0, d[1], o[1]) + 0.5f) / C), 0), g.gy - 1);
+    f.cz = min(max((int)floorf((fmaf(t0, d[2], o[2]) + 0.5f) / C), 0), g.gz - 1);
+}
+
+__device__ __forceinline__ bool coarse_occupied(const uint32_t* bits, const PtArgs& g, int bx,
+                                                int by, int bz)
+{
+    const uint32_t i = (uint32_t)(bx + g.cgx * (by + g.cgy * bz));
+    return (bits[i >> 5] >> (i & 31u)) & 1u;
+}
+
+// Exit distance through the faces of an axis-aligned cell of edge `edge`
+// (index c along each axis); returns the crossing axis or -1 if t1 is closer.
+__device__ __forceinline__ int cell_exit(const Flight& f, float edge, int cx, int cy, int cz,
+                                         float& te)
+{
+    te = f.t1;
+    int axis = -1;
+    if (f.d[0] != 0.0f) {
+        const float ta = (edge * (float)(cx + (f.d[0] > 0.0f)) - 0.5f - f.o[0]) * f.id[0];
+        if (ta < te) {
+            te = ta;
+            axis = 0;
+        }
+    }
+    if (f.d[1] != 0.0f) {
+        const float ta = (edge * (float)(cy + (f.d[1] > 0.0f)) - 0.5f - f.o[1]) * f.id[1];
+        if (ta < te) {
+            te = ta;
+            axis = 1;
+        }
+    }
+    if (f.d[2] != 0.0f) {
+        const float ta = (edge * (float)(cz + (f.d[2] > 0.0f)) - 0.5f - f.o[2]) * f.id[2];
+        if (ta < te) {
+            te = ta;
+            axis = 2;
+        }
+    }
+    return axis;
+}
+
+// Advances the flight to its next tentative collision: returns 1 with the
+// density `sv` sampled there (the caller makes the accept test), or 0 when
+// the segment leaves the grid without one.  Empty cells draw no random
+// numbers and coarse-block faces are macrocell faces, so the tentative
+// collisions are those of a uniform walk over every macrocell; a flight that
+// overshoots a cell restarts at its exit (memorylessness).
+template <class Acc>
+__device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK& m,
+                                              const float* __restrict__ maj,
+                                              const uint32_t* cbits, const PtArgs& g, Rng& rng,
+                                              float& sv, uint32_t& nsamp, uint32_t& ncell)
+{
+    if (!f.ok) return 0;
+    const float C = (float)g.C;
+    const float CF = (float)(g.C << g.lf);
     for (;;) {
-        float te = t1;
-        int axis = -1;
-        if (sx) {
-            const float ta = (C * (float)(cx + (sx > 0)) - 0.5f - o[0]) * ix;
-            if (ta < te) {
-                te = ta;
-                axis = 0;
-            }
-        }
-        if (sy) {
-            const float ta = (C * (float)(cy + (sy > 0)) - 0.5f - o[1]) * iy;
-            if (ta < te) {
-                te = ta;
-                axis = 1;
-            }
-        }
-        if (sz) {
-            const float ta = (C * (float)(cz + (sz > 0)) - 0.5f - o[2]) * iz;
-            if (ta < te) {
-                te = ta;
-                axis = 2;
-            }
-        }
-        const float mu = maj[cx + g.gx * (cy + g.gy * cz)];
-        if (mu > 0.0f && t < te) {
-            const float imu = 1.0f / mu;
-            for (;;) {
-                t = fmaf(-__logf(1.0f - rng.next()), imu, t);
-                if (t >= te) break;
-                if (--budget == 0) return false;
-                const float s = trilinear(acc, fmaf(t, d[0], o[0]), fmaf(t, d[1], o[1]),
-                                          fmaf(t, d[2], o[2]));
+        if (f.incell) {
+            f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
+            if (f.t < f.te) {
+                if (--f.budget == 0) return 0;
+                sv = trilinear(acc, fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
+                               fmaf(f.t, f.d[2], f.o[2]));
                 ++nsamp;
-                const float sig = m.ds * tf_alpha(m, s);
-                if (rng.next() * mu < sig) {
-                    t_hit = t;
-                    s_hit = s;
-                    return true;
-                }
+                return 1;
+            }
+            f.incell = false;
+            if (f.axis < 0) return 0;
+            f.t = f.te;
+            if (f.axis == 0) {
+                f.cx += f.d[0] > 0.0f ? 1 : -1;
+                if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
+            } else if (f.axis == 1) {
+                f.cy += f.d[1] > 0.0f ? 1 : -1;
+                if ((unsigned)f.cy >= (unsigned)g.gy) return 0;
+            } else {
+                f.cz += f.d[2] > 0.0f ? 1 : -1;
+                if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
             }
         }
-        if (axis < 0) return false;
-        t = te;
-        if (axis == 0) {
-            cx += sx;
-            if ((unsigned)cx >= (unsigned)g.gx) return false;
-        } else if (axis == 1) {
-            cy += sy;
-            if ((unsigned)cy >= (unsigned)g.gy) return false;
+        const int bx = f.cx >> g.lf, by = f.cy >> g.lf, bz = f.cz >> g.lf;
+        ++ncell;
+        if (!coarse_occupied(cbits, g, bx, by, bz)) {
+            // cross the empty block in one step
+            float te;
+            const int axis = cell_exit(f, CF, bx, by, bz, te);
+            if (axis < 0) return 0;
+            f.t = te;
+            const int F = 1 << g.lf;
+            const float px = (fmaf(te, f.d[0], f.o[0]) + 0.5f) / C;
+            const float py = (fmaf(te, f.d[1], f.o[1]) + 0.5f) / C;
+            const float pz = (fmaf(te, f.d[2], f.o[2]) + 0.5f) / C;
+            if (axis == 0) {
+                f.cx = f.d[0] > 0.0f ? (bx + 1) * F : bx * F - 1;
+                if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
+            } else {
+                f.cx = min(max((int)floorf(px), bx * F), min(bx * F + F, g.gx) - 1);
+            }
+            if (axis == 1) {
+                f.cy = f.d[1] > 0.0f ? (by + 1) * F : by * F - 1;
+                if ((unsigned)f.cy >= (unsigned)g.gy) return 0;
+            } else {
+                f.cy = min(max((int)floorf(py), by * F), min(by * F + F, g.gy) - 1);
+            }
+            if (axis == 2) {
+                f.cz = f.d[2] > 0.0f ? (bz + 1) * F : bz * F - 1;
+                if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
+            } else {
+                f.cz = min(max((int)floorf(pz), bz * F), min(bz * F + F, g.gz) - 1);
+            }
+            continue;
+        }
+        f.axis = cell_exit(f, C, f.cx, f.cy, f.cz, f.te);
+        f.mu = maj[f.cx + g.gx * (f.cy + g.gy * f.cz)];
+        if (f.mu > 0.0f && f.t < f.te) {
+            f.incell = true;
+            f.imu = 1.0f / f.mu;
+            continue;
+        }
+        if (f.axis < 0) return 0;
+        f.t = f.te;
+        if (f.axis == 0) {
+            f.cx += f.d[0] > 0.0f ? 1 : -1;
+            if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
+        } else if (f.axis == 1) {
+            f.cy += f.d[1] > 0.0f ? 1 : -1;
+            if ((unsigned)f.cy >= (unsigned)g.gy) return 0;
         } else {
-            cz += sz;
-            if ((unsigned)cz >= (unsigned)g.gz) return false;
+            f.cz += f.d[2] > 0.0f ? 1 : -1;
+            if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
         }
     }
 }
 
+// Delta-tracking path tracer (Section 4), one thread per pixel running that
+// pixel's paths one after another.  The loop is flat: every iteration moves
+// each lane to its next tentative collision and handles whatever event the
+// lane reached (collision, escape, end of a shadow ray, start of a new path),
+// so lanes never wait for each other at bounce or sample boundaries.  The
+// arithmetic and the random draws of each path are those of a recursive
+// implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
+// stream << 16 | bounce, frame); stream 0 = jitter, free flights and the
+// scattering direction; stream 1 = the shadow ray of that bounce.
 template <class Acc, class View, bool COUNT, bool AOV>
 __global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
                                                     const float* __restrict__ maj,
+                                                    const uint32_t* __restrict__ coarse,
                                                     float* __restrict__ image,
                                                     float* __restrict__ aov,
                                                     unsigned long long* counter)
 {
+    extern __shared__ uint32_t cbits[];
+    for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = coarse[i];
+    __syncthreads();
     Acc acc{view};
     acc.reset();
     int px, py;
     const bool live = tile_pixel(cam.width, cam.height, px, py);
-    uint32_t nsamp = 0;
-    if (live) {
-        const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
-        const uint32_t k0 = g.seed_lo ^ pix, k1 = g.seed_hi;
-        const float inv4pi = 0.0795774715459476679f;
-        float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f, opac = 0.0f, depth = 0.0f, trans = 0.0f;
-        for (int s = 0; s < g.spp; ++s) {
-            Rng path;
-            path.init(k0, k1, (uint32_t)s, 0u, 0u, g.frame);
-            const float jx = path.next(), jy = path.next();
+    uint32_t nsamp = 0, ncell = 0;
+    const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
+    const uint32_t k0 = g.seed_lo ^ pix;
+    const float inv4pi = 0.0795774715459476679f;
+    float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f, opac = 0.0f, depth = 0.0f, trans = 0.0f;
+    float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
+    float t0p = 0.0f;
+    int s = live ? 0 : g.spp;   // current sample of this lane's pixel
+    int b = 0;                  // bounce
+    bool shadow = false, fresh = true;
+    uint32_t path_d = 0;
+    Rng rng;
+    Flight f;
+    while (s < g.spp) {
+        if (fresh) {
+            fresh = false;
+            rng.init(k0, g.seed_hi, (uint32_t)s, 0u, 0u, g.frame);
+            const float jx = rng.next(), jy = rng.next();
             float o[3], d[3];
             camera_ray(cam, (float)px + jx, (float)py + jy, o, d);
-            float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
-            for (int b = 0; b < g.max_bounces; ++b) {
-                if (b > 0) path.init(k0, k1, (uint32_t)s, (uint32_t)b, 0u, g.frame);
-                float t0, t1, th = 0.0f, sh = 0.0f;
-                const bool hit = box_clip(view.nx, view.ny, view.nz, o, d, t0, t1) &&
-                                 free_flight(acc, m, maj, g, o, d, t0, t1, path, th, sh, nsamp);
-                if (b == 0) {
-                    if (hit) {
-                        opac += 1.0f;
-                        depth += (th - t0) / (t1 - t0);
-                    } else {
-                        trans += 1.0f;
-                        depth += 1.0f;
-                    }
+            b = 0;
+            shadow = false;
+            L0 = L1 = L2 = 0.0f;
+            b0 = b1 = b2 = 1.0f;
+            flight_begin(f, g, view.nx, view.ny, view.nz, o, d, t0p);
+        }
+        float sv = 0.0f;
+        const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
+        const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha(m, sv);
+        if (tentative && !hit) continue;    // null collision: keep tracking
+        bool path_done = false, next_bounce = false;
+        if (!shadow) {
+            if (b == 0) {
+                if (hit) {
+                    opac += 1.0f;
+                    depth += (f.t - t0p) / (f.t1 - t0p);
+                } else {
+                    trans += 1.0f;
+                    depth += 1.0f;
                 }
-                if (!hit) {
-                    L0 = fmaf(b0, m.ambient[0], L0);
-                    L1 = fmaf(b1, m.ambient[1], L1);
-                    L2 = fmaf(b2, m.ambient[2], L2);
-                    break;
-                }
-                const float x[3] = {fmaf(th, d[0], o[0]), fmaf(th, d[1], o[1]),
-                                    fmaf(th, d[2], o[2])};
-                const float4 c = tf_eval(m, sh);
+            }
+            if (hit) {
+                // real collision: weight by albedo and colour, then the
+                // shadow ray towards the light from the collision point
+                const float4 c = tf_eval(m, sv);
                 b0 *= m.albedo * c.x;
                 b1 *= m.albedo * c.y;
                 b2 *= m.albedo * c.z;
-                Rng shadow;
-                shadow.init(k0, k1, (uint32_t)s, (uint32_t)b, 1u, g.frame);
-                float s0, s1, tsh, ssh;
-                const bool blocked =
-                    box_clip(view.nx, view.ny, view.nz, x, m.light, s0, s1) &&
-                    free_flight(acc, m, maj, g, x, m.light, s0, s1, shadow, tsh, ssh, nsamp);
-                if (!blocked) {
-                    L0 = fmaf(b0 * inv4pi, m.light_E[0], L0);
-                    L1 = fmaf(b1 * inv4pi, m.light_E[1], L1);
-                    L2 = fmaf(b2 * inv4pi, m.light_E[2], L2);
-                }
-                if (b + 1 == g.max_bounces) break;
-                const float u1 = path.next(), u2 = path.next();
-                const float z = 1.0f - 2.0f * u1;
-                const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-                float sp, cp;
-                sincosf(6.28318530717958647692f * u2, &sp, &cp);
-                o[0] = x[0];
-                o[1] = x[1];
-                o[2] = x[2];
-                d[0] = r * cp;
-                d[1] = r * sp;
-                d[2] = z;
+                const float x[3] = {fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
+                                    fmaf(f.t, f.d[2], f.o[2])};
+                path_d = rng.d;
+                rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 1u, g.frame);
+                float t0s;
+                flight_begin(f, g, view.nx, view.ny, view.nz, x, m.light, t0s);
+                shadow = true;
+            } else {
+                L0 = fmaf(b0, m.ambient[0], L0);
+                L1 = fmaf(b1, m.ambient[1], L1);
+                L2 = fmaf(b2, m.ambient[2], L2);
+                path_done = true;
             }
+        } else {
+            if (!hit) {
+                L0 = fmaf(b0 * inv4pi, m.light_E[0], L0);
+                L1 = fmaf(b1 * inv4pi, m.light_E[1], L1);
+                L2 = fmaf(b2 * inv4pi, m.light_E[2], L2);
+            }
+            shadow = false;
+            if (b + 1 == g.max_bounces) path_done = true;
+            else next_bounce = true;
+        }
+        if (next_bounce) {
+            // isotropic scattering from the collision point (the shadow ray's
+            // origin), drawn from the path stream of this bounce
+            rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 0u, g.frame);
+            rng.seek(path_d);
+            const float u1 = rng.next(), u2 = rng.next();
+            const float z = 1.0f - 2.0f * u1;
+            const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+            float sp, cp;
+            sincosf(6.28318530717958647692f * u2, &sp, &cp);
+            const float o[3] = {f.o[0], f.o[1], f.o[2]};
+            const float d[3] = {r * cp, r * sp, z};
+            ++b;
+            rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 0u, g.frame);
+            float t0n;
+            flight_begin(f, g, view.nx, view.ny, view.nz, o, d, t0n);
+        }
+        if (path_done) {
             r0 += L0;
             r1 += L1;
             r2 += L2;
+            ++s;
+            fresh = true;
         }
+    }
+    if (live) {
         const float inv = 1.0f / (float)g.spp;
         float4* img = reinterpret_cast<float4*>(image);
         img[pix] = make_float4(r0 * inv, r1 * inv, r2 * inv, opac * inv);
         if (AOV) reinterpret_cast<float2*>(aov)[pix] = make_float2(depth * inv, trans * inv);
     }
-    if (COUNT) block_count(nsamp, counter);
+    if (COUNT) {
+        block_count(nsamp, counter);
+        block_count(ncell, counter + 1);
+    }
 }
 
 __global__ void philox_kernel(const uint32_t* __restrict__ ctr, const uint32_t* __restrict__ key,
@@ -474,6 +631,37 @@ static uint64_t majorant_bytes(uint32_t C, int nx, int ny, int nz)
     return gx * gy * gz * 4u;
 }
 
+// Majorant grid and coarse occupancy geometry.  Coarse blocks are 2^lf
+// macrocells per axis, the largest power of two spanning at most 32 voxels (one
+// brick), doubled until the bit mask fits in 32 KB of LDS.
+static void pt_geometry(uint32_t C, int nx, int ny, int nz, PtArgs* g)
+{
+    g->C = (int)C;
+    g->gx = (nx + g->C - 1) / g->C;
+    g->gy = (ny + g->C - 1) / g->C;
+    g->gz = (nz + g->C - 1) / g->C;
+    int lf = 0;
+    while ((C << (lf + 1)) <= 32) ++lf;      // block edge C * 2^lf <= 32 voxels
+    for (;;) {
+        const int F = 1 << lf;
+        g->lf = lf;
+        g->cgx = (g->gx + F - 1) / F;
+        g->cgy = (g->gy + F - 1) / F;
+        g->cgz = (g->gz + F - 1) / F;
+        const uint64_t cells = (uint64_t)g->cgx * g->cgy * g->cgz;
+        g->cwords = (int)((cells + 31) / 32);
+        if (g->cwords <= 8192) break;
+        ++lf;
+    }
+}
+
+static uint64_t pt_workspace(uint32_t C, int nx, int ny, int nz)
+{
+    PtArgs g;
+    pt_geometry(C, nx, ny, nz, &g);
+    return 256 + align256(majorant_bytes(C, nx, ny, nz)) + align256(4ull * g.cwords);
+}
+
 static vdbc_status check_samples(const float* pos, uint64_t n, uint32_t filter, float* out)
 {
     if (filter > 1) return fail(VDBC_E_INVALID, "filter must be 0 or 1");
@@ -558,18 +746,24 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
         if (s) return s;
     }
     PtArgs g;
+    pt_geometry(r->macrocell, v.nx, v.ny, v.nz, &g);
     g.spp = (int)r->spp;
     g.max_bounces = (int)r->max_bounces;
-    g.C = (int)r->macrocell;
-    g.gx = (v.nx + g.C - 1) / g.C;
-    g.gy = (v.ny + g.C - 1) / g.C;
-    g.gz = (v.nz + g.C - 1) / g.C;
     g.seed_lo = (uint32_t)r->seed;
     g.seed_hi = (uint32_t)(r->seed >> 32);
     g.frame = r->frame;
+    uint32_t* coarse = reinterpret_cast<uint32_t*>(
+        static_cast<uint8_t*>(ws) + 256 + align256(majorant_bytes(r->macrocell, v.nx, v.ny, v.nz)));
+    {
+        const uint64_t ncoarse = (uint64_t)g.cgx * g.cgy * g.cgz;
+        hipLaunchKernelGGL(coarse_bits_kernel, dim3((unsigned)((ncoarse + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, maj, g, coarse);
+        if ((s = launch_check("coarse occupancy"))) return s;
+    }
+    const size_t lds = 4u * (size_t)g.cwords;
 #define PT_LAUNCH(CNT, AO)                                                                     \
-    hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO>), grid, dim3(kBlock), 0, st, v, cam, m, g, \
-                       maj, image, aov, counter)
+    hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO>), grid, dim3(kBlock), lds, st, v, cam, m, \
+                       g, maj, coarse, image, aov, counter)
     if (count) {
         if (aov) PT_LAUNCH(true, true);
         else PT_LAUNCH(true, false);
@@ -638,7 +832,7 @@ extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_d
     if (r->mode == VDBC_MODE_PT) {
         if (r->macrocell < 4 || r->macrocell > 64)
             return fail(VDBC_E_INVALID, "macrocell must be in [4, 64]");
-        *bytes = 256 + align256(majorant_bytes(r->macrocell, (int)d.nx, (int)d.ny, (int)d.nz));
+        *bytes = pt_workspace(r->macrocell, (int)d.nx, (int)d.ny, (int)d.nz);
     } else {
         *bytes = (r->flags & VDBC_RENDER_COUNT) ? 256 : 0;
     }

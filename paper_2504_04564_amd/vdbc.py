@@ -333,6 +333,10 @@ class Renderer:
         torch = _torch()
         return int(self.ws[self.ws_off:self.ws_off + 8].view(torch.int64).item())
 
+    def cell_count(self) -> int:
+        torch = _torch()
+        return int(self.ws[self.ws_off + 8:self.ws_off + 16].view(torch.int64).item())
+
     def majorant(self):
         torch = _torch()
         C_ = self.prm.macrocell

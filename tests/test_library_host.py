@@ -171,7 +171,7 @@ def test_device_calls_reject_bad_arguments_before_launch(lib):
     pt = vdbc.params_c(dict(spp=1), vdbc.MODE_PT)
     ws = C.c_uint64(0)
     assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
-    assert ws.value == 256 + 256
+    assert ws.value == 256 + 256 + 256   # counters | 2^3 majorants | coarse bits
     assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(pt), 4096, None,
                            8192, ws.value - 1, None) == vdbc.E_BUFFER_TOO_SMALL
     pt.macrocell = 3

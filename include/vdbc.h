@@ -190,7 +190,9 @@ typedef struct {
     float t_terminate;      /* EA: stop when transmittance < this (0 = off) */
     uint64_t seed;          /* PT Philox key material */
     uint32_t frame;         /* PT counter word 3 */
-    uint32_t reserved[3];
+    uint32_t tile_w;        /* PT pixels per wave row: 8 (default; 0 = 8), 16, 32, 64;
+                               the image does not depend on it */
+    uint32_t reserved[2];
 } vdbc_render_params;
 
 /* Workspace layout (caller-owned device memory, 256-B aligned):
@@ -221,10 +223,112 @@ vdbc_status vdbc_majorant_dense(const float* dense, vdbc_dims d, float backgroun
                                 const vdbc_medium* m, uint32_t macrocell, float* out,
                                 void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched rendering of many volumes (this project's extension)              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    vdbc_grid grid;          /* the volume (device buffer + host header copy) */
+    vdbc_camera camera;
+    vdbc_medium medium;
+    uint32_t spp, max_bounces;
+    uint64_t seed;
+    uint32_t frame;
+    float* image;            /* device float32 [height][width][4] */
+} vdbc_batch_item;
+
+typedef struct {
+    uint32_t macrocell;      /* majorant cell edge in voxels, 4..64 (default 16) */
+    uint32_t tile_w;         /* pixels per wave row: 8, 16, 32, 64 (default 8) */
+    uint32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4) */
+    uint32_t persistent;     /* 1: one persistent launch over all (volume, tile)
+                                items; 0: one launch per volume */
+} vdbc_tuning;
+
+typedef struct vdbc_batch vdbc_batch;
+
+/* Workspace bytes for a batch (counter, descriptor table, work list, and per
+ * volume a majorant grid and coarse occupancy bits).  tuning may be NULL. */
+vdbc_status vdbc_batch_workspace(const vdbc_batch_item* items, uint32_t n,
+                                 const vdbc_tuning* tuning, uint64_t* bytes);
+/* Validates the items, uploads the descriptor table and the work list (tiles
+ * ordered by estimated cost, largest first) into ws (synchronises `stream`),
+ * and returns a plan.  Buffers and images must outlive the plan.  Each image
+ * is bit-identical to vdbc_render of that item with the same tuning. */
+vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t n,
+                              const vdbc_tuning* tuning, void* ws, uint64_t ws_bytes,
+                              void* stream, vdbc_batch** plan);
+/* Enqueues majorant builds and the render(s) on `stream`. */
+vdbc_status vdbc_batch_launch(vdbc_batch* plan, void* stream);
+/* Captures the launch sequence once into a HIP graph held by the plan
+ * (`stream` must be a non-default, idle stream); replay it with
+ * vdbc_batch_graph_launch.  No memset nodes are recorded. */
+vdbc_status vdbc_batch_capture(vdbc_batch* plan, void* stream);
+vdbc_status vdbc_batch_graph_launch(vdbc_batch* plan, void* stream);
+void vdbc_batch_destroy(vdbc_batch* plan);
+
 /* Philox4x32-10 (Salmon et al., SC'11) on the device: out[4i..4i+3] =
  * Philox(ctr[4i..4i+3], key[2i..2i+1]) for i < n (device uint32 arrays). */
 vdbc_status vdbc_philox(const uint32_t* ctr, const uint32_t* key, uint64_t n, uint32_t* out,
                         void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Learned denoiser (this project's extension; not part of the paper)        */
+/* ------------------------------------------------------------------------ */
+/* A 6-layer 3x3 convolutional U-Net on NHWC tensors, BF16 weights and
+ * activations, FP32 accumulation on BF16 matrix cores:
+ *   c1 = relu(conv(x, 8->32)); c2 = relu(conv(c1, 32->64, stride 2));
+ *   c3 = relu(conv(c2, 64->64)); c4 = relu(conv(up2(c3), 64->32));
+ *   c5 = relu(conv(concat(c1, c4), 64->32)); out = x.rgb + conv(c5, 32->3).
+ * x: BF16 [n][h][w][8] = (r, g, b, first-scatter depth fraction, primary
+ * transmittance, 0, 0, 0) of a low-sample-count render; out: FP32 [n][h][w][3].
+ * Parameters: one flat FP32 vector, per layer W[co][ky][kx][ci] then b[co];
+ * `wbf16` is a BF16 copy of the whole vector (same indices).  h and w even. */
+vdbc_status vdbc_nn_param_count(uint64_t* count);
+/* wbf16[i] = bf16(params[i]) (round to nearest even), device arrays. */
+vdbc_status vdbc_nn_to_bf16(const float* params, uint16_t* wbf16, void* stream);
+/* Workspace bytes for inference (training = 0) or one training step. */
+vdbc_status vdbc_denoise_workspace(uint32_t n, uint32_t h, uint32_t w, uint32_t training,
+                                   uint64_t* bytes);
+/* x[p] = (rgba[p].rgb, aov[p].depth, aov[p].transmittance, 0, 0, 0) as BF16,
+ * from vdbc_render's image and AOV outputs (pixels = n*h*w). */
+vdbc_status vdbc_denoise_pack(const float* rgba, const float* aov, uint64_t pixels, uint16_t* x,
+                              void* stream);
+/* Inference: out = network(x).  ws 256-byte aligned, x and wbf16 16-byte. */
+vdbc_status vdbc_denoise(const float* params, const uint16_t* wbf16, const uint16_t* x, uint32_t n,
+                         uint32_t h, uint32_t w, float* out, void* ws, uint64_t ws_bytes,
+                         void* stream);
+/* One training step on a batch: forward, loss = mean over pixels and RGB of
+ * (out - t)^2 / (t^2 + 0.01) written to *loss (device float), backward, and
+ * (lr > 0) one Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected with
+ * `step` >= 1) on the FP32 master params with refreshed BF16 copy.  grad_out
+ * (device float[param_count] or NULL) receives the gradient. */
+vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, float* adam_m, float* adam_v,
+                                    uint32_t step, float lr, const uint16_t* x, const float* target,
+                                    uint32_t n, uint32_t h, uint32_t w, float* loss,
+                                    float* grad_out, void* ws, uint64_t ws_bytes, void* stream);
+/* Single 3x3 convolution layer (zero padding 1): input channels [0, ca) from
+ * a and [ca, ca+cb) from b (NHWC, hs x ws_, nearest x2 upsampled if
+ * `upsample`), weights BF16 [cout][3][3][ca+cb], bias FP32; output BF16 or
+ * FP32 (exactly one non-NULL), ReLU if `relu`.  Channels multiples of 8 up
+ * to 64, cout 1..64, stride 1 or 2. */
+vdbc_status vdbc_conv3x3(const uint16_t* a, uint32_t ca, const uint16_t* b, uint32_t cb,
+                         uint32_t upsample, uint32_t n, uint32_t hs, uint32_t ws_, uint32_t stride,
+                         const uint16_t* w, const float* bias, uint32_t cout, uint32_t relu,
+                         uint16_t* out_bf16, float* out_f32, void* stream);
+vdbc_status vdbc_conv3x3_grad_workspace(uint32_t cin, uint32_t cout, uint32_t n, uint32_t ho,
+                                        uint32_t wo, uint64_t* bytes);
+/* Data gradient: dx (FP32 [n][hv][wv][cin]) from dz (BF16 [n][ho][wo][coutp],
+ * channels >= cout zero) and the layer's weights. */
+vdbc_status vdbc_conv3x3_dgrad(const uint16_t* dz, uint32_t coutp, uint32_t cout, uint32_t n,
+                               uint32_t ho, uint32_t wo, const uint16_t* w, uint32_t cin,
+                               uint32_t stride, uint32_t hv, uint32_t wv, float* dx, void* ws,
+                               uint64_t ws_bytes, void* stream);
+/* Weight and bias gradients (FP32 dw[cout][3][3][cin], db[cout]) of the
+ * layer whose input is described as in vdbc_conv3x3. */
+vdbc_status vdbc_conv3x3_wgrad(const uint16_t* a, uint32_t ca, const uint16_t* b, uint32_t cb,
+                               uint32_t upsample, uint32_t n, uint32_t hs, uint32_t ws_,
+                               uint32_t stride, const uint16_t* dz, uint32_t coutp, uint32_t cout,
+                               float* dw, float* db, void* ws, uint64_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

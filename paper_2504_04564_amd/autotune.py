@@ -1,0 +1,102 @@
+"""Autotuner for the path tracer and the batched launch.
+
+Times every candidate of a small search space on the device (one warm-up,
+median of `reps` HIP-event timings) and keeps the fastest; choices are
+persisted to a JSON file keyed by workload class so later runs reuse them.
+Candidates only change launch geometry (wave tile shape, persistent grid
+size) or the majorant cell size; the first two leave every image
+bit-identical, the cell size changes the estimator's random stream but not
+its expectation.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+from . import vdbc
+
+RENDER_SPACE = {"macrocell": (8, 16, 32), "tile_w": (8, 16, 32)}
+BATCH_SPACE = {"macrocell": (8, 16), "tile_w": (8, 16), "blocks_per_cu": (2, 4, 8),
+               "persistent": (1,)}
+
+
+def _median_ms(fn, reps: int) -> float:
+    torch = vdbc._torch()
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def workload_key(kind: str, dims, rate: float, spp: int) -> str:
+    """Class of a workload: field kind, log2 bucket of the largest side,
+    rate rounded to 1/100, samples per pixel."""
+    return f"{kind}/n{int(round(math.log2(max(dims))))}/q{rate:.2f}/spp{spp}"
+
+
+def load(path: str) -> dict:
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save(path: str, table: dict):
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune_render(field, camera: dict, medium: dict, params: dict, background=None,
+                space: dict | None = None, reps: int = 5):
+    """Best (macrocell, tile_w) for a path-traced frame; returns (best, all)."""
+    space = space or RENDER_SPACE
+    results = []
+    for C_ in space["macrocell"]:
+        for tw in space["tile_w"]:
+            p = dict(params, macrocell=C_, tile_w=tw)
+            r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
+            ms = _median_ms(r.launch, reps)
+            results.append({"macrocell": C_, "tile_w": tw, "ms": ms})
+    best = min(results, key=lambda x: x["ms"])
+    return best, results
+
+
+def tune_batch(items: list, space: dict | None = None, reps: int = 5):
+    """Best batched-launch tuning for a list of batch items."""
+    space = space or BATCH_SPACE
+    results = []
+    for C_ in space["macrocell"]:
+        for tw in space["tile_w"]:
+            for bpc in space["blocks_per_cu"]:
+                for pers in space["persistent"]:
+                    t = dict(macrocell=C_, tile_w=tw, blocks_per_cu=bpc, persistent=pers)
+                    b = vdbc.Batch(items, t)
+                    ms = _median_ms(b.launch, reps)
+                    b.close()
+                    results.append(dict(t, ms=ms))
+    best = min(results, key=lambda x: x["ms"])
+    return best, results
+
+
+def cached_render_tuning(path: str, key: str, tune_fn):
+    """Tuned choice for `key` from the JSON table at `path`, tuning (and
+    persisting) it on first use."""
+    table = load(path)
+    if key not in table:
+        best, _ = tune_fn()
+        table[key] = best
+        save(path, table)
+    return table[key]

@@ -1,0 +1,796 @@
+// Learned denoiser on gfx950: implicit-GEMM 3x3 convolutions (forward, data
+// gradient, weight gradient) on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation, the relative-MSE loss, ReLU/upsample backward, and Adam with
+// FP32 master weights and BF16 copies.
+//
+// MFMA 16x16x32 BF16 operand layout (lane l, g = l / 16, r = l % 16):
+// A[r][8g + j] and B[8g + j][r] for j < 8; the accumulator holds
+// D[4g + i][r] for i < 4.  Every GEMM below puts its contraction index on K
+// in chunks of 32 so that a lane's 8 K values are 8 consecutive channels of
+// one 3x3 tap: one 16-byte load from an NHWC tensor.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+#include "format.h"
+#include "nn.h"
+
+namespace vdbc {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kWgradChunk = 2048;   // output pixels per weight-gradient partial
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+__device__ __forceinline__ f4 mfma(bf16x8 a, bf16x8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Input of a convolution: channels [0, ca) from `a`, [ca, ca + cb) from `b`
+// (a channel concat), both NHWC of spatial size hs x ws; with `up` they are
+// read through a nearest-neighbour x2 upsample.
+struct ConvIn {
+    const uint16_t* a;
+    const uint16_t* b;
+    int ca, cb, up, n, hs, ws;
+};
+
+__device__ __forceinline__ bf16x8 gather8(const ConvIn& in, int n, int iy, int ix, int c0)
+{
+    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
+    if ((unsigned)iy >= (unsigned)hv || (unsigned)ix >= (unsigned)wv) return zero8();
+    const int sy = in.up ? iy >> 1 : iy, sx = in.up ? ix >> 1 : ix;
+    const int64_t pix = ((int64_t)n * in.hs + sy) * in.ws + sx;
+    return c0 < in.ca ? load8(in.a + pix * in.ca + c0) : load8(in.b + pix * in.cb + (c0 - in.ca));
+}
+
+// ---------------------------------------------------------------- forward
+// out[p][co] = act(bias[co] + sum_k A[p][k] W[co][k]), k = tap * cin + ci;
+// 64 output pixels per workgroup, 16 per wave, NT tiles of 16 channels.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uint16_t* __restrict__ w,
+                                                            const float* __restrict__ bias, int cout,
+                                                            int stride, int ho, int wo, int relu,
+                                                            uint16_t* __restrict__ out_bf,
+                                                            float* __restrict__ out_f,
+                                                            const uint16_t* __restrict__ resid)
+{
+    const int cin = in.ca + in.cb, K = 9 * cin;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+    const int64_t P = (int64_t)in.n * ho * wo;
+    const int64_t p = (int64_t)blockIdx.x * 64 + wave * 16 + r;
+    const bool pv = p < P;
+    int n = 0, oy = 0, ox = 0;
+    if (pv) {
+        ox = (int)(p % wo);
+        const int64_t q = p / wo;
+        oy = (int)(q % ho);
+        n = (int)(q / ho);
+    }
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kb = 0; kb < K; kb += 32) {
+        const int k = kb + 8 * g;
+        const int tap = k / cin, c0 = k - tap * cin;
+        bf16x8 A = zero8();
+        if (pv && tap < 9) A = gather8(in, n, oy * stride + tap / 3 - 1, ox * stride + tap % 3 - 1, c0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + r;
+            const bf16x8 B = (co < cout && tap < 9) ? load8(w + (int64_t)co * K + k) : zero8();
+            acc[t] = mfma(A, B, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + r;
+        if (co >= cout) continue;
+        const float bb = bias[co];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t pp = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * g + i;
+            if (pp >= P) continue;
+            float v = acc[t][i] + bb;
+            if (relu) v = fmaxf(v, 0.0f);
+            if (out_f) {
+                if (resid) v += bf2f(resid[pp * 8 + co]);
+                out_f[pp * cout + co] = v;
+            } else {
+                out_bf[pp * cout + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- data gradient
+// dx[q][c] (+)= sum_{tap, co} dz[p(q, tap)][co] Wt[c][tap][co] over the input
+// pixels q of the (virtual) input; p = ((y+1-ky)/s, (x+1-kx)/s) when that is
+// an integer output position.  dz has channel stride coutp (multiple of 8),
+// Wt is the transposed weight [cin][9][coutp].
+template <int NT>
+__global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __restrict__ dz, int coutp,
+                                                              int n_img, int ho, int wo,
+                                                              const uint16_t* __restrict__ wt, int cin,
+                                                              int stride, int hv, int wv,
+                                                              float* __restrict__ dx, int accumulate)
+{
+    const int K = 9 * coutp;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+    const int64_t Q = (int64_t)n_img * hv * wv;
+    const int64_t q = (int64_t)blockIdx.x * 64 + wave * 16 + r;
+    const bool qv = q < Q;
+    int n = 0, iy = 0, ix = 0;
+    if (qv) {
+        ix = (int)(q % wv);
+        const int64_t t = q / wv;
+        iy = (int)(t % hv);
+        n = (int)(t / hv);
+    }
+    f4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kb = 0; kb < K; kb += 32) {
+        const int k = kb + 8 * g;
+        const int tap = k / coutp, co0 = k - tap * coutp;
+        bf16x8 A = zero8();
+        if (qv && tap < 9) {
+            const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
+            if (ty >= 0 && tx >= 0 && ty % stride == 0 && tx % stride == 0) {
+                const int oy = ty / stride, ox = tx / stride;
+                if (oy < ho && ox < wo) A = load8(dz + (((int64_t)n * ho + oy) * wo + ox) * coutp + co0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = t * 16 + r;
+            const bf16x8 B = (c < cin && tap < 9) ? load8(wt + (int64_t)c * K + k) : zero8();
+            acc[t] = mfma(A, B, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = t * 16 + r;
+        if (c >= cin) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t qq = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * g + i;
+            if (qq >= Q) continue;
+            float* o = dx + qq * cin + c;
+            *o = accumulate ? *o + acc[t][i] : acc[t][i];
+        }
+    }
+}
+
+// Wt[c][tap][co] = W[co][tap][c] (zero for co >= cout), BF16.
+__global__ void transpose_weights_kernel(const uint16_t* __restrict__ w, int cin, int cout, int coutp,
+                                         uint16_t* __restrict__ wt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cin * 9 * coutp) return;
+    const int co = i % coutp, tap = (i / coutp) % 9, c = i / (9 * coutp);
+    wt[i] = co < cout ? w[((int64_t)co * 9 + tap) * cin + c] : (uint16_t)0;
+}
+
+// ---------------------------------------------------------------- weight gradient
+// partial[chunk][co][k] = sum over the chunk's output pixels p of
+// dz[p][co] * A[p][k] with A the forward operand (k = tap * cin + ci).
+// M = co (MT tiles of 16), N = k (64 per workgroup, 16 per wave), K = pixels
+// staged 32 at a time through LDS (dz rows and im2col rows, both contiguous).
+template <int MT>
+__global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int stride, int ho, int wo,
+                                                              const uint16_t* __restrict__ dz, int coutp,
+                                                              float* __restrict__ partial)
+{
+    __shared__ uint16_t sA[32][64 + 8];
+    __shared__ uint16_t sB[32][64 + 8];
+    const int cin = in.ca + in.cb, K = 9 * cin;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
+    const int kbase = blockIdx.y * 64;
+    const int64_t P = (int64_t)in.n * ho * wo;
+    const int64_t p0 = (int64_t)blockIdx.x * kWgradChunk;
+    const int64_t p1 = p0 + kWgradChunk < P ? p0 + kWgradChunk : P;
+    f4 acc[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int cg = coutp / 8;
+    for (int64_t pb = p0; pb < p1; pb += 32) {
+        // dz rows: 32 pixels x coutp channels
+        for (int idx = tid; idx < 32 * cg; idx += kThreads) {
+            const int px = idx / cg, c8 = (idx - px * cg) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (pb + px < p1) v = *reinterpret_cast<const uint4*>(dz + (pb + px) * coutp + c8);
+            *reinterpret_cast<uint4*>(&sA[px][c8]) = v;
+        }
+        // im2col rows: 32 pixels x 64 values of k
+        {
+            const int px = tid >> 3, kg = tid & 7;
+            const int k = kbase + kg * 8;
+            bf16x8 v = zero8();
+            const int64_t p = pb + px;
+            if (p < p1 && k < K) {
+                const int tap = k / cin, c0 = k - tap * cin;
+                const int ox = (int)(p % wo);
+                const int64_t q = p / wo;
+                const int oy = (int)(q % ho), n = (int)(q / ho);
+                v = gather8(in, n, oy * stride + tap / 3 - 1, ox * stride + tap % 3 - 1, c0);
+            }
+            *reinterpret_cast<uint4*>(&sB[px][kg * 8]) = __builtin_bit_cast(uint4, v);
+        }
+        __syncthreads();
+        bf16x8 B;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) B[j] = __builtin_bit_cast(__bf16, sB[8 * g + j][16 * wave + r]);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            bf16x8 A;
+            const int co = t * 16 + r;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                A[j] = co < coutp ? __builtin_bit_cast(__bf16, sA[8 * g + j][co]) : (__bf16)0.0f;
+            acc[t] = mfma(A, B, acc[t]);
+        }
+        __syncthreads();
+    }
+    const int k = kbase + 16 * wave + r;
+    if (k >= K) return;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = t * 16 + 4 * g + i;
+            partial[((int64_t)blockIdx.x * (MT * 16) + co) * K + k] = acc[t][i];
+        }
+}
+
+// grad[co][k] = sum over chunks (in order) of partial[chunk][co][k].
+__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks, int mpad, int cout,
+                                    int K, float* __restrict__ grad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cout * K) return;
+    const int co = i / K, k = i - co * K;
+    float s = 0.0f;
+    for (int c = 0; c < chunks; ++c) s += partial[((int64_t)c * mpad + co) * K + k];
+    grad[i] = s;
+}
+
+// db[co] = sum_p dz[p][co]; one workgroup per channel, fixed-order tree sum.
+__global__ __launch_bounds__(kThreads) void bias_grad_kernel(const uint16_t* __restrict__ dz, int coutp,
+                                                             int64_t P, float* __restrict__ db)
+{
+    __shared__ float s[kThreads];
+    const int co = blockIdx.x;
+    float a = 0.0f;
+    for (int64_t p = threadIdx.x; p < P; p += kThreads) a += bf2f(dz[p * coutp + co]);
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] = s[0];
+}
+
+// ---------------------------------------------------------------- elementwise
+
+// dz[p][c] = (src1 + src2)[p][c] * (y[p][c] > 0) as BF16, zero-padded to
+// coutp channels.  With `pool`, src1 is read at full resolution (2h x 2w)
+// and summed over the 2x2 block of destination pixel (n, y, x): the backward
+// of the nearest x2 upsample.
+struct ReluBack {
+    const float* s1;
+    int s1_stride, s1_off;
+    const float* s2;
+    int s2_stride, s2_off;
+    const uint16_t* y;
+    int C, coutp, pool, n, h, w;
+};
+
+__global__ void relu_back_kernel(ReluBack a, uint16_t* __restrict__ dz)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t P = (int64_t)a.n * a.h * a.w;
+    if (i >= P * a.coutp) return;
+    const int c = (int)(i % a.coutp);
+    const int64_t p = i / a.coutp;
+    float v = 0.0f;
+    if (c < a.C) {
+        if (a.pool) {
+            const int x = (int)(p % a.w);
+            const int64_t t = p / a.w;
+            const int y = (int)(t % a.h), n = (int)(t / a.h);
+            const int W2 = 2 * a.w;
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dxx = 0; dxx < 2; ++dxx) {
+                    const int64_t q = ((int64_t)n * 2 * a.h + 2 * y + dy) * W2 + 2 * x + dxx;
+                    v += a.s1[q * a.s1_stride + a.s1_off + c];
+                }
+        } else {
+            v = a.s1[p * a.s1_stride + a.s1_off + c];
+            if (a.s2) v += a.s2[p * a.s2_stride + a.s2_off + c];
+        }
+        if (a.y && !(bf2f(a.y[p * a.C + c]) > 0.0f)) v = 0.0f;
+    }
+    dz[i] = f2bf(v);
+}
+
+// Relative-MSE loss over RGB: per-block partial sums of (o-t)^2/(t^2+0.01)
+// and the gradient 2(o-t)/(t^2+0.01)/(3P) written as BF16 with 8 channels.
+__global__ __launch_bounds__(kThreads) void loss_kernel(const float* __restrict__ out,
+                                                        const float* __restrict__ target, int64_t P,
+                                                        uint16_t* __restrict__ dz, float* __restrict__ partial)
+{
+    __shared__ float s[kThreads];
+    const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    float l = 0.0f;
+    if (p < P) {
+        const float scale = 2.0f / (3.0f * (float)P);
+        uint16_t g8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < 3; ++c) {
+            const float t = target[p * 3 + c], d = out[p * 3 + c] - t;
+            const float inv = 1.0f / (t * t + 0.01f);
+            l = fmaf(d * d, inv, l);
+            g8[c] = f2bf(scale * d * inv);
+        }
+        uint4 v;
+        v.x = g8[0] | ((uint32_t)g8[1] << 16);
+        v.y = g8[2];
+        v.z = 0;
+        v.w = 0;
+        *reinterpret_cast<uint4*>(dz + p * 8) = v;
+    }
+    s[threadIdx.x] = l;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(kThreads) void loss_final_kernel(const float* __restrict__ partial, int nb,
+                                                              int64_t P, float* __restrict__ loss)
+{
+    __shared__ float s[kThreads];
+    float a = 0.0f;
+    for (int i = threadIdx.x; i < nb; i += kThreads) a += partial[i];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = s[0] / (3.0f * (float)P);
+}
+
+// Adam (Kingma & Ba): FP32 master weights, first and second moments,
+// bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t; writes the BF16 copy.
+__global__ void adam_kernel(float* __restrict__ p, uint16_t* __restrict__ pb, float* __restrict__ m,
+                            float* __restrict__ v, const float* __restrict__ grad, uint64_t n, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * g;
+    const float vi = b2 * v[i] + (1.0f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    const float x = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = x;
+    pb[i] = f2bf(x);
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ p, uint16_t* __restrict__ pb, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pb[i] = f2bf(p[i]);
+}
+
+// Network input from a render: (r, g, b, depth fraction, transmittance, 0, 0, 0).
+__global__ void pack_kernel(const float* __restrict__ rgba, const float* __restrict__ aov, uint64_t P,
+                            uint16_t* __restrict__ x)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    uint4 v;
+    v.x = f2bf(rgba[4 * p]) | ((uint32_t)f2bf(rgba[4 * p + 1]) << 16);
+    v.y = f2bf(rgba[4 * p + 2]) | ((uint32_t)f2bf(aov[2 * p]) << 16);
+    v.z = f2bf(aov[2 * p + 1]);
+    v.w = 0;
+    *reinterpret_cast<uint4*>(x + 8 * p) = v;
+}
+
+// ---------------------------------------------------------------- host side
+
+inline unsigned blocks(uint64_t n, unsigned t = kThreads) { return (unsigned)((n + t - 1) / t); }
+
+vdbc_status check(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(VDBC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    return VDBC_OK;
+}
+
+bool aligned16(const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const float* bias, int cout,
+                     int relu, uint16_t* out_bf, float* out_f, const uint16_t* resid, hipStream_t st)
+{
+    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
+    const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
+    const uint64_t P = (uint64_t)in.n * ho * wo;
+    const unsigned gb = blocks(P, 64);
+    if (cout <= 16)
+        hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout, stride, ho,
+                           wo, relu, out_bf, out_f, resid);
+    else if (cout <= 32)
+        hipLaunchKernelGGL(conv_fwd_kernel<2>, dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout, stride, ho,
+                           wo, relu, out_bf, out_f, resid);
+    else
+        hipLaunchKernelGGL(conv_fwd_kernel<4>, dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout, stride, ho,
+                           wo, relu, out_bf, out_f, resid);
+    return check("conv3x3 forward");
+}
+
+vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, int wo, const uint16_t* w,
+                       int cin, int stride, int hv, int wv, float* dx, int accumulate, uint16_t* wt,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks((uint64_t)cin * 9 * coutp)), dim3(kThreads), 0, st,
+                       w, cin, cout, coutp, wt);
+    const uint64_t Q = (uint64_t)n * hv * wv;
+    const unsigned gb = blocks(Q, 64);
+    if (cin <= 16)
+        hipLaunchKernelGGL(conv_dgrad_kernel<1>, dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho, wo, wt, cin,
+                           stride, hv, wv, dx, accumulate);
+    else if (cin <= 32)
+        hipLaunchKernelGGL(conv_dgrad_kernel<2>, dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho, wo, wt, cin,
+                           stride, hv, wv, dx, accumulate);
+    else
+        hipLaunchKernelGGL(conv_dgrad_kernel<4>, dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho, wo, wt, cin,
+                           stride, hv, wv, dx, accumulate);
+    return check("conv3x3 data gradient");
+}
+
+uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
+{
+    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
+    const uint64_t P = (uint64_t)in.n * ((hv - 1) / stride + 1) * ((wv - 1) / stride + 1);
+    const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
+    const int mpad = (cout + 15) / 16 * 16;
+    return chunks * mpad * 9ull * (in.ca + in.cb);
+}
+
+vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int coutp, int cout, float* dw,
+                       float* db, float* partial, hipStream_t st)
+{
+    const int cin = in.ca + in.cb, K = 9 * cin;
+    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
+    const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
+    const int64_t P = (int64_t)in.n * ho * wo;
+    const unsigned chunks = (unsigned)((P + kWgradChunk - 1) / kWgradChunk);
+    const int mt = (cout + 15) / 16;
+    dim3 grid(chunks, (K + 63) / 64);
+    if (mt == 1)
+        hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
+    else if (mt == 2)
+        hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
+    else
+        hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks((uint64_t)cout * K)), dim3(kThreads), 0, st, partial,
+                       (int)chunks, mt * 16, cout, K, dw);
+    hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(kThreads), 0, st, dz, coutp, P, db);
+    return check("conv3x3 weight gradient");
+}
+
+vdbc_status relu_back(const ReluBack& a, uint16_t* dz, hipStream_t st)
+{
+    hipLaunchKernelGGL(relu_back_kernel, dim3(blocks((uint64_t)a.n * a.h * a.w * a.coutp)), dim3(kThreads), 0,
+                       st, a, dz);
+    return check("relu backward");
+}
+
+// Workspace carving for the whole network at n x h x w.
+struct NetLayout {
+    uint64_t c1, c2, c3, c4, c5, out, dz6, dy5, dz5, dcat, dz4, du, dz3, dy2, dz2, dy1, dz1, wt, partial,
+        lpart, grad, total;
+};
+
+uint64_t al(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
+
+NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
+{
+    const uint64_t P = (uint64_t)n * h * w, Ph = P / 4;
+    NetLayout L{};
+    uint64_t o = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = o;
+        o += al(bytes);
+        return at;
+    };
+    L.c1 = take(P * 32 * 2);
+    L.c2 = take(Ph * 64 * 2);
+    L.c3 = take(Ph * 64 * 2);
+    L.c4 = take(P * 32 * 2);
+    L.c5 = take(P * 32 * 2);
+    if (training) {
+        L.out = take(P * 3 * 4);
+        L.dz6 = take(P * 8 * 2);
+        L.dy5 = take(P * 32 * 4);
+        L.dz5 = take(P * 32 * 2);
+        L.dcat = take(P * 64 * 4);
+        L.dz4 = take(P * 32 * 2);
+        L.du = take(P * 64 * 4);
+        L.dz3 = take(Ph * 64 * 2);
+        L.dy2 = take(Ph * 64 * 4);
+        L.dz2 = take(Ph * 64 * 2);
+        L.dy1 = take(P * 32 * 4);
+        L.dz1 = take(P * 32 * 2);
+        L.wt = take(64 * 9 * 64 * 2);
+        const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
+        L.partial = take(chunks * 64 * 9 * 64 * 4);
+        L.lpart = take((P + kThreads - 1) / kThreads * 4 + 16);
+        L.grad = take(nn::param_count() * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+vdbc_status check_net_args(uint32_t n, uint32_t h, uint32_t w)
+{
+    if (n == 0 || h == 0 || w == 0 || (h & 1u) || (w & 1u))
+        return fail(VDBC_E_INVALID, "denoiser needs n >= 1 and even h, w >= 2");
+    if ((uint64_t)n * h * w > (1ull << 31)) return fail(VDBC_E_INVALID, "too many pixels");
+    return VDBC_OK;
+}
+
+// Forward pass into the workspace; `out` gets the FP32 RGB result.
+vdbc_status net_forward(const float* params, const uint16_t* wb, const uint16_t* x, uint32_t n, uint32_t h,
+                        uint32_t w, float* out, uint8_t* ws, const NetLayout& L, hipStream_t st)
+{
+    using namespace nn;
+    auto Wl = [&](int l) { return wb + weight_offset(l); };
+    auto Bl = [&](int l) { return params + bias_offset(l); };
+    uint16_t* c1 = reinterpret_cast<uint16_t*>(ws + L.c1);
+    uint16_t* c2 = reinterpret_cast<uint16_t*>(ws + L.c2);
+    uint16_t* c3 = reinterpret_cast<uint16_t*>(ws + L.c3);
+    uint16_t* c4 = reinterpret_cast<uint16_t*>(ws + L.c4);
+    uint16_t* c5 = reinterpret_cast<uint16_t*>(ws + L.c5);
+    const int H = (int)h, W = (int)w, N = (int)n;
+    vdbc_status s;
+    if ((s = conv_fwd(ConvIn{x, nullptr, 8, 0, 0, N, H, W}, 1, Wl(0), Bl(0), 32, 1, c1, nullptr, nullptr, st)))
+        return s;
+    if ((s = conv_fwd(ConvIn{c1, nullptr, 32, 0, 0, N, H, W}, 2, Wl(1), Bl(1), 64, 1, c2, nullptr, nullptr, st)))
+        return s;
+    if ((s = conv_fwd(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, Wl(2), Bl(2), 64, 1, c3, nullptr,
+                      nullptr, st)))
+        return s;
+    if ((s = conv_fwd(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, Wl(3), Bl(3), 32, 1, c4, nullptr,
+                      nullptr, st)))
+        return s;
+    if ((s = conv_fwd(ConvIn{c1, c4, 32, 32, 0, N, H, W}, 1, Wl(4), Bl(4), 32, 1, c5, nullptr, nullptr, st)))
+        return s;
+    return conv_fwd(ConvIn{c5, nullptr, 32, 0, 0, N, H, W}, 1, Wl(5), Bl(5), 3, 0, nullptr, out, x, st);
+}
+
+}  // namespace
+}  // namespace vdbc
+
+using namespace vdbc;
+
+extern "C" vdbc_status vdbc_nn_param_count(uint64_t* count)
+{
+    clear_error();
+    if (!count) return fail(VDBC_E_INVALID, "null argument");
+    *count = nn::param_count();
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_nn_to_bf16(const float* params, uint16_t* wbf16, void* stream)
+{
+    clear_error();
+    if (!params || !wbf16) return fail(VDBC_E_INVALID, "null argument");
+    const uint64_t n = nn::param_count();
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(n)), dim3(kThreads), 0, static_cast<hipStream_t>(stream),
+                       params, wbf16, n);
+    return check("vdbc_nn_to_bf16");
+}
+
+extern "C" vdbc_status vdbc_denoise_workspace(uint32_t n, uint32_t h, uint32_t w, uint32_t training,
+                                              uint64_t* bytes)
+{
+    clear_error();
+    if (!bytes) return fail(VDBC_E_INVALID, "null argument");
+    vdbc_status s = check_net_args(n, h, w);
+    if (s) return s;
+    *bytes = net_layout(n, h, w, training != 0).total;
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_denoise_pack(const float* rgba, const float* aov, uint64_t pixels, uint16_t* x,
+                                         void* stream)
+{
+    clear_error();
+    if (pixels && (!rgba || !aov || !x)) return fail(VDBC_E_INVALID, "null argument");
+    if (!aligned16(x)) return fail(VDBC_E_INVALID, "x must be 16-byte aligned");
+    if (pixels == 0) return VDBC_OK;
+    hipLaunchKernelGGL(pack_kernel, dim3(blocks(pixels)), dim3(kThreads), 0, static_cast<hipStream_t>(stream),
+                       rgba, aov, pixels, x);
+    return check("vdbc_denoise_pack");
+}
+
+extern "C" vdbc_status vdbc_denoise(const float* params, const uint16_t* wbf16, const uint16_t* x, uint32_t n,
+                                    uint32_t h, uint32_t w, float* out, void* ws, uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    vdbc_status s = check_net_args(n, h, w);
+    if (s) return s;
+    if (!params || !wbf16 || !x || !out || !ws) return fail(VDBC_E_INVALID, "null argument");
+    if (!aligned16(wbf16) || !aligned16(x) || (reinterpret_cast<uintptr_t>(ws) & 255u))
+        return fail(VDBC_E_INVALID, "wbf16 and x must be 16-byte aligned, ws 256-byte aligned");
+    const NetLayout L = net_layout(n, h, w, false);
+    if (ws_bytes < L.total)
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "denoise workspace needs %llu bytes", (unsigned long long)L.total);
+    return net_forward(params, wbf16, x, n, h, w, out, static_cast<uint8_t*>(ws), L,
+                       static_cast<hipStream_t>(stream));
+}
+
+extern "C" vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, float* adam_m, float* adam_v,
+                                               uint32_t step, float lr, const uint16_t* x, const float* target,
+                                               uint32_t n, uint32_t h, uint32_t w, float* loss, float* grad_out,
+                                               void* ws, uint64_t ws_bytes, void* stream)
+{
+    using namespace nn;
+    clear_error();
+    vdbc_status s = check_net_args(n, h, w);
+    if (s) return s;
+    if (!params || !wbf16 || !x || !target || !loss || !ws) return fail(VDBC_E_INVALID, "null argument");
+    if (step == 0 || !(lr >= 0.0f) || !std::isfinite(lr)) return fail(VDBC_E_INVALID, "step >= 1, finite lr >= 0");
+    if (lr > 0.0f && (!adam_m || !adam_v)) return fail(VDBC_E_INVALID, "null Adam state");
+    if (!aligned16(wbf16) || !aligned16(x) || (reinterpret_cast<uintptr_t>(ws) & 255u))
+        return fail(VDBC_E_INVALID, "wbf16 and x must be 16-byte aligned, ws 256-byte aligned");
+    const NetLayout L = net_layout(n, h, w, true);
+    if (ws_bytes < L.total)
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "training workspace needs %llu bytes", (unsigned long long)L.total);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t* b = static_cast<uint8_t*>(ws);
+    auto U = [&](uint64_t off) { return reinterpret_cast<uint16_t*>(b + off); };
+    auto F = [&](uint64_t off) { return reinterpret_cast<float*>(b + off); };
+    const int H = (int)h, W = (int)w, N = (int)n;
+    const int64_t P = (int64_t)n * h * w;
+    float* out = F(L.out);
+    float* grad = grad_out ? grad_out : F(L.grad);
+    if ((s = net_forward(params, wbf16, x, n, h, w, out, b, L, st))) return s;
+    // loss and dL/dout
+    const unsigned nb = blocks((uint64_t)P);
+    hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(kThreads), 0, st, out, target, P, U(L.dz6), F(L.lpart));
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(kThreads), 0, st, F(L.lpart), (int)nb, P, loss);
+    if ((s = check("loss"))) return s;
+    auto Wl = [&](int l) { return wbf16 + weight_offset(l); };
+    auto gW = [&](int l) { return grad + weight_offset(l); };
+    auto gB = [&](int l) { return grad + bias_offset(l); };
+    uint16_t *c1 = U(L.c1), *c2 = U(L.c2), *c3 = U(L.c3), *c4 = U(L.c4), *c5 = U(L.c5);
+    float* part = F(L.partial);
+    uint16_t* wt = U(L.wt);
+    // c6: 32 -> 3 (dz6 padded to 8 channels)
+    if ((s = conv_wgrad(ConvIn{c5, nullptr, 32, 0, 0, N, H, W}, 1, U(L.dz6), 8, 3, gW(5), gB(5), part, st))) return s;
+    if ((s = conv_dgrad(U(L.dz6), 8, 3, N, H, W, Wl(5), 32, 1, H, W, F(L.dy5), 0, wt, st))) return s;
+    if ((s = relu_back(ReluBack{F(L.dy5), 32, 0, nullptr, 0, 0, c5, 32, 32, 0, N, H, W}, U(L.dz5), st))) return s;
+    // c5: concat(c1, c4) 64 -> 32
+    if ((s = conv_wgrad(ConvIn{c1, c4, 32, 32, 0, N, H, W}, 1, U(L.dz5), 32, 32, gW(4), gB(4), part, st))) return s;
+    if ((s = conv_dgrad(U(L.dz5), 32, 32, N, H, W, Wl(4), 64, 1, H, W, F(L.dcat), 0, wt, st))) return s;
+    if ((s = relu_back(ReluBack{F(L.dcat), 64, 32, nullptr, 0, 0, c4, 32, 32, 0, N, H, W}, U(L.dz4), st))) return s;
+    // c4: up2(c3) 64 -> 32
+    if ((s = conv_wgrad(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, U(L.dz4), 32, 32, gW(3), gB(3), part,
+                        st)))
+        return s;
+    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, F(L.du), 0, wt, st))) return s;
+    if ((s = relu_back(ReluBack{F(L.du), 64, 0, nullptr, 0, 0, c3, 64, 64, 1, N, H / 2, W / 2}, U(L.dz3), st)))
+        return s;
+    // c3: 64 -> 64 at half resolution
+    if ((s = conv_wgrad(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, U(L.dz3), 64, 64, gW(2), gB(2), part,
+                        st)))
+        return s;
+    if ((s = conv_dgrad(U(L.dz3), 64, 64, N, H / 2, W / 2, Wl(2), 64, 1, H / 2, W / 2, F(L.dy2), 0, wt, st)))
+        return s;
+    if ((s = relu_back(ReluBack{F(L.dy2), 64, 0, nullptr, 0, 0, c2, 64, 64, 0, N, H / 2, W / 2}, U(L.dz2), st)))
+        return s;
+    // c2: 32 -> 64, stride 2
+    if ((s = conv_wgrad(ConvIn{c1, nullptr, 32, 0, 0, N, H, W}, 2, U(L.dz2), 64, 64, gW(1), gB(1), part, st)))
+        return s;
+    if ((s = conv_dgrad(U(L.dz2), 64, 64, N, H / 2, W / 2, Wl(1), 32, 2, H, W, F(L.dy1), 0, wt, st))) return s;
+    if ((s = relu_back(ReluBack{F(L.dcat), 64, 0, F(L.dy1), 32, 0, c1, 32, 32, 0, N, H, W}, U(L.dz1), st)))
+        return s;
+    // c1: 8 -> 32 (no data gradient needed)
+    if ((s = conv_wgrad(ConvIn{x, nullptr, 8, 0, 0, N, H, W}, 1, U(L.dz1), 32, 32, gW(0), gB(0), part, st)))
+        return s;
+    if (lr > 0.0f) {
+        const double c1d = 1.0 - std::pow(0.9, (double)step), c2d = 1.0 - std::pow(0.999, (double)step);
+        const uint64_t np = param_count();
+        hipLaunchKernelGGL(adam_kernel, dim3(blocks(np)), dim3(kThreads), 0, st, params, wbf16, adam_m, adam_v,
+                           grad, np, lr, 0.9f, 0.999f, 1e-8f, (float)c1d, (float)c2d);
+        if ((s = check("adam"))) return s;
+    }
+    return VDBC_OK;
+}
+
+// ---- single-layer building blocks (parity tests) ----
+
+extern "C" vdbc_status vdbc_conv3x3(const uint16_t* a, uint32_t ca, const uint16_t* b, uint32_t cb,
+                                    uint32_t upsample, uint32_t n, uint32_t hs, uint32_t ws_, uint32_t stride,
+                                    const uint16_t* w, const float* bias, uint32_t cout, uint32_t relu,
+                                    uint16_t* out_bf16, float* out_f32, void* stream)
+{
+    clear_error();
+    if (!a || !w || !bias || (!out_bf16 && !out_f32) || (cb && !b)) return fail(VDBC_E_INVALID, "null argument");
+    if (ca % 8 || cb % 8 || ca + cb == 0 || ca + cb > 64 || cout == 0 || cout > 64 || (stride != 1 && stride != 2) ||
+        n == 0 || hs == 0 || ws_ == 0)
+        return fail(VDBC_E_INVALID, "channels must be multiples of 8 up to 64, cout 1..64, stride 1 or 2");
+    if (!aligned16(a) || !aligned16(b) || !aligned16(w)) return fail(VDBC_E_INVALID, "operands must be 16-byte aligned");
+    return conv_fwd(ConvIn{a, b, (int)ca, (int)cb, (int)(upsample != 0), (int)n, (int)hs, (int)ws_}, (int)stride, w,
+                    bias, (int)cout, (int)relu, out_bf16, out_f32, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" vdbc_status vdbc_conv3x3_grad_workspace(uint32_t cin, uint32_t cout, uint32_t n, uint32_t ho,
+                                                   uint32_t wo, uint64_t* bytes)
+{
+    clear_error();
+    if (!bytes || cin == 0 || cin > 64 || cout == 0 || cout > 64) return fail(VDBC_E_INVALID, "bad argument");
+    const uint64_t P = (uint64_t)n * ho * wo;
+    const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
+    *bytes = al(64ull * 9 * 64 * 2) + al(chunks * 64ull * 9 * cin * 4);
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_conv3x3_dgrad(const uint16_t* dz, uint32_t coutp, uint32_t cout, uint32_t n,
+                                          uint32_t ho, uint32_t wo, const uint16_t* w, uint32_t cin,
+                                          uint32_t stride, uint32_t hv, uint32_t wv, float* dx, void* ws,
+                                          uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    if (!dz || !w || !dx || !ws) return fail(VDBC_E_INVALID, "null argument");
+    if (coutp % 8 || coutp < cout || coutp > 64 || cin % 8 || cin == 0 || cin > 64 || (stride != 1 && stride != 2))
+        return fail(VDBC_E_INVALID, "bad channel counts or stride");
+    if ((hv - 1) / stride + 1 != ho || (wv - 1) / stride + 1 != wo) return fail(VDBC_E_INVALID, "shape mismatch");
+    if (ws_bytes < 64ull * 9 * 64 * 2) return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace too small");
+    if (!aligned16(dz) || !aligned16(w) || !aligned16(ws)) return fail(VDBC_E_INVALID, "operands must be 16-byte aligned");
+    return conv_dgrad(dz, (int)coutp, (int)cout, (int)n, (int)ho, (int)wo, w, (int)cin, (int)stride, (int)hv,
+                      (int)wv, dx, 0, static_cast<uint16_t*>(ws), static_cast<hipStream_t>(stream));
+}
+
+extern "C" vdbc_status vdbc_conv3x3_wgrad(const uint16_t* a, uint32_t ca, const uint16_t* b, uint32_t cb,
+                                          uint32_t upsample, uint32_t n, uint32_t hs, uint32_t ws_, uint32_t stride,
+                                          const uint16_t* dz, uint32_t coutp, uint32_t cout, float* dw, float* db,
+                                          void* ws, uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    if (!a || !dz || !dw || !db || !ws || (cb && !b)) return fail(VDBC_E_INVALID, "null argument");
+    if (ca % 8 || cb % 8 || ca + cb == 0 || ca + cb > 64 || coutp % 8 || coutp < cout || coutp > 64 || cout == 0 ||
+        (stride != 1 && stride != 2))
+        return fail(VDBC_E_INVALID, "bad channel counts or stride");
+    ConvIn in{a, b, (int)ca, (int)cb, (int)(upsample != 0), (int)n, (int)hs, (int)ws_};
+    const uint64_t need = al(64ull * 9 * 64 * 2) + al(wgrad_partial_floats(in, (int)stride, (int)cout) * 4);
+    if (ws_bytes < need) return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace needs %llu bytes", (unsigned long long)need);
+    if (!aligned16(a) || !aligned16(b) || !aligned16(dz)) return fail(VDBC_E_INVALID, "operands must be 16-byte aligned");
+    float* part = reinterpret_cast<float*>(static_cast<uint8_t*>(ws) + al(64ull * 9 * 64 * 2));
+    return conv_wgrad(in, (int)stride, dz, (int)coutp, (int)cout, dw, db, part, static_cast<hipStream_t>(stream));
+}

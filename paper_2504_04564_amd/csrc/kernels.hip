@@ -4,8 +4,12 @@
 // float32 baseline through the same templated code.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
 
 #include "common.h"
 #include "device.h"
@@ -24,12 +28,15 @@ constexpr uint32_t kMaxFlightSamples = 1u << 20;
 
 // ---------------------------------------------------------------- helpers
 
-// 256 threads = 4 waves of 8x8 pixels; returns false outside the image.
-__device__ __forceinline__ bool tile_pixel(int width, int height, int& px, int& py)
+// 256 threads = 4 waves in a 2x2 arrangement, each wave a tw x (64/tw) pixel
+// tile (tw = 8, 16, 32 or 64); workgroup (bx, by) covers a (2 tw) x (128/tw)
+// block.  Returns false outside the image.
+__device__ __forceinline__ bool tile_pixel(int width, int height, int tw, int bx, int by, int& px,
+                                           int& py)
 {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    px = blockIdx.x * kTile + (w & 1) * 8 + (lane & 7);
-    py = blockIdx.y * kTile + (w >> 1) * 8 + (lane >> 3);
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, th = 64 / tw;
+    px = bx * 2 * tw + (w & 1) * tw + (lane % tw);
+    py = by * 2 * th + (w >> 1) * th + (lane / tw);
     return px < width && py < height;
 }
 
@@ -115,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
     Acc acc{view};
     acc.reset();
     int px, py;
-    const bool live = tile_pixel(cam.width, cam.height, px, py);
+    const bool live = tile_pixel(cam.width, cam.height, 8, blockIdx.x, blockIdx.y, px, py);
     uint32_t nsamp = 0;
     if (live) {
         float o[3], d[3], t0, t1;
@@ -172,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
 // ---------------------------------------------------------------- PT
 
 struct PtArgs {
-    int spp, max_bounces, C, gx, gy, gz;
+    int spp, max_bounces, C, gx, gy, gz, tw;
     int lf, cgx, cgy, cgz, cwords;   // coarse blocks of 2^lf macrocells per axis, bit words
     uint32_t seed_lo, seed_hi, frame;
 };
@@ -376,22 +383,23 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
 // implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
 // stream << 16 | bounce, frame); stream 0 = jitter, free flights and the
 // scattering direction; stream 1 = the shadow ray of that bounce.
-template <class Acc, class View, bool COUNT, bool AOV>
-__global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
-                                                    const float* __restrict__ maj,
-                                                    const uint32_t* __restrict__ coarse,
-                                                    float* __restrict__ image,
-                                                    float* __restrict__ aov,
-                                                    unsigned long long* counter)
+// Delta-tracking path tracer (Section 4) for one pixel: that pixel's paths one
+// after another in a flat loop.  Every iteration moves the lane to its next
+// tentative collision and handles whatever event the lane reached (collision,
+// escape, end of a shadow ray, start of a new path), so the lanes of a wave
+// never wait for each other at bounce or sample boundaries.  The arithmetic
+// and the random draws of each path are those of a recursive implementation:
+// key (seed_lo ^ pixel, seed_hi), counter (block, sample, stream << 16 |
+// bounce, frame); stream 0 = jitter, free flights and the scattering
+// direction; stream 1 = the shadow ray of that bounce.  Results depend only
+// on the pixel, not on which thread or launch shape renders it.
+template <class Acc>
+__device__ __forceinline__ void pt_pixel(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
+                                         const MediumK& m, const PtArgs& g,
+                                         const float* __restrict__ maj, const uint32_t* cbits,
+                                         int px, int py, bool live, float4& rgba, float2& aovv,
+                                         uint32_t& nsamp, uint32_t& ncell)
 {
-    extern __shared__ uint32_t cbits[];
-    for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = coarse[i];
-    __syncthreads();
-    Acc acc{view};
-    acc.reset();
-    int px, py;
-    const bool live = tile_pixel(cam.width, cam.height, px, py);
-    uint32_t nsamp = 0, ncell = 0;
     const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
     const uint32_t k0 = g.seed_lo ^ pix;
     const float inv4pi = 0.0795774715459476679f;
@@ -415,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, Medi
             shadow = false;
             L0 = L1 = L2 = 0.0f;
             b0 = b1 = b2 = 1.0f;
-            flight_begin(f, g, view.nx, view.ny, view.nz, o, d, t0p);
+            flight_begin(f, g, nx, ny, nz, o, d, t0p);
         }
         float sv = 0.0f;
         const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
@@ -444,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, Medi
                 path_d = rng.d;
                 rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 1u, g.frame);
                 float t0s;
-                flight_begin(f, g, view.nx, view.ny, view.nz, x, m.light, t0s);
+                flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
                 shadow = true;
             } else {
                 L0 = fmaf(b0, m.ambient[0], L0);
@@ -477,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, Medi
             ++b;
             rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 0u, g.frame);
             float t0n;
-            flight_begin(f, g, view.nx, view.ny, view.nz, o, d, t0n);
+            flight_begin(f, g, nx, ny, nz, o, d, t0n);
         }
         if (path_done) {
             r0 += L0;
@@ -487,15 +495,93 @@ __global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, Medi
             fresh = true;
         }
     }
+    const float inv = 1.0f / (float)g.spp;
+    rgba = make_float4(r0 * inv, r1 * inv, r2 * inv, opac * inv);
+    aovv = make_float2(depth * inv, trans * inv);
+}
+
+template <class Acc, class View, bool COUNT, bool AOV>
+__global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
+                                                    const float* __restrict__ maj,
+                                                    const uint32_t* __restrict__ coarse,
+                                                    float* __restrict__ image,
+                                                    float* __restrict__ aov,
+                                                    unsigned long long* counter)
+{
+    extern __shared__ uint32_t cbits[];
+    for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = coarse[i];
+    __syncthreads();
+    Acc acc{view};
+    acc.reset();
+    int px, py;
+    const bool live = tile_pixel(cam.width, cam.height, g.tw, blockIdx.x, blockIdx.y, px, py);
+    uint32_t nsamp = 0, ncell = 0;
+    float4 rgba;
+    float2 aovv;
+    pt_pixel(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, px, py, live, rgba, aovv, nsamp,
+             ncell);
     if (live) {
-        const float inv = 1.0f / (float)g.spp;
-        float4* img = reinterpret_cast<float4*>(image);
-        img[pix] = make_float4(r0 * inv, r1 * inv, r2 * inv, opac * inv);
-        if (AOV) reinterpret_cast<float2*>(aov)[pix] = make_float2(depth * inv, trans * inv);
+        const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
+        reinterpret_cast<float4*>(image)[pix] = rgba;
+        if (AOV) reinterpret_cast<float2*>(aov)[pix] = aovv;
     }
     if (COUNT) {
         block_count(nsamp, counter);
         block_count(ncell, counter + 1);
+    }
+}
+
+// ---------------------------------------------------------------- batched PT
+// Many volumes in one persistent launch: workgroups pull (volume, tile) items
+// from an atomic counter over a list ordered by estimated cost (largest
+// first) and render each tile with the per-pixel code of pt_kernel, so every
+// image is bit-identical to its own launch.
+struct BatchDesc {
+    VdbView view;
+    CameraK cam;
+    MediumK med;
+    PtArgs g;
+    const float* maj;
+    const uint32_t* coarse;
+    float* image;
+    int tiles_x;
+};
+
+__global__ void zero_u32(uint32_t* p)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void pt_batch_kernel(const BatchDesc* __restrict__ descs,
+                                                          const uint32_t* __restrict__ items,
+                                                          uint32_t n_items, uint32_t* counter)
+{
+    extern __shared__ uint32_t cbits[];
+    __shared__ uint32_t s_item;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
+        if (it >= n_items) break;
+        const uint32_t code = __builtin_amdgcn_readfirstlane(items[it]);
+        const BatchDesc* D = descs + (code >> 20);
+        const uint32_t tile = code & 0xFFFFFu;
+        const PtArgs g = D->g;
+        const CameraK cam = D->cam;
+        for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = D->coarse[i];
+        __syncthreads();
+        VdbAcc acc{D->view};
+        acc.reset();
+        int px, py;
+        const bool live = tile_pixel(cam.width, cam.height, g.tw, (int)(tile % (uint32_t)D->tiles_x),
+                                     (int)(tile / (uint32_t)D->tiles_x), px, py);
+        float4 rgba;
+        float2 aovv;
+        uint32_t ns = 0, nc = 0;
+        pt_pixel(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits, px, py, live,
+                 rgba, aovv, ns, nc);
+        if (live) reinterpret_cast<float4*>(D->image)[(uint32_t)py * (uint32_t)cam.width + (uint32_t)px] = rgba;
     }
 }
 
@@ -749,6 +835,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     pt_geometry(r->macrocell, v.nx, v.ny, v.nz, &g);
     g.spp = (int)r->spp;
     g.max_bounces = (int)r->max_bounces;
+    g.tw = (r->tile_w == 16 || r->tile_w == 32 || r->tile_w == 64) ? (int)r->tile_w : 8;
     g.seed_lo = (uint32_t)r->seed;
     g.seed_hi = (uint32_t)(r->seed >> 32);
     g.frame = r->frame;
@@ -761,6 +848,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
         if ((s = launch_check("coarse occupancy"))) return s;
     }
     const size_t lds = 4u * (size_t)g.cwords;
+    grid = dim3((cam.width + 2 * g.tw - 1) / (2 * g.tw), (cam.height + 128 / g.tw - 1) / (128 / g.tw));
 #define PT_LAUNCH(CNT, AO)                                                                     \
     hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO>), grid, dim3(kBlock), lds, st, v, cam, m, \
                        g, maj, coarse, image, aov, counter)
@@ -901,4 +989,256 @@ extern "C" vdbc_status vdbc_philox(const uint32_t* ctr, const uint32_t* key, uin
     hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        static_cast<hipStream_t>(stream), ctr, key, n, out);
     return launch_check("vdbc_philox");
+}
+
+// ---------------------------------------------------------------- batched PT (host)
+
+struct vdbc_batch {
+    uint32_t n = 0;
+    vdbc_tuning t{};
+    std::vector<VdbView> views;
+    std::vector<CameraK> cams;
+    std::vector<MediumK> meds;
+    std::vector<PtArgs> gs;
+    std::vector<float*> majs;
+    std::vector<uint32_t*> coarse;
+    std::vector<float*> images;
+    std::vector<int> tiles_x, tiles_y;
+    BatchDesc* d_descs = nullptr;
+    uint32_t* d_items = nullptr;
+    uint32_t* d_counter = nullptr;
+    uint32_t n_items = 0;
+    int max_cwords = 0;
+    int grid_blocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace vdbc {
+
+static vdbc_status batch_tuning(const vdbc_tuning* t, vdbc_tuning* out)
+{
+    vdbc_tuning d{16, 8, 4, 1};
+    if (t) d = *t;
+    if (d.macrocell < 4 || d.macrocell > 64) return fail(VDBC_E_INVALID, "tuning.macrocell must be in [4, 64]");
+    if (d.tile_w == 0) d.tile_w = 8;
+    if (d.tile_w != 8 && d.tile_w != 16 && d.tile_w != 32 && d.tile_w != 64)
+        return fail(VDBC_E_INVALID, "tuning.tile_w must be 8, 16, 32 or 64");
+    if (d.blocks_per_cu == 0) d.blocks_per_cu = 4;
+    if (d.blocks_per_cu > 32) return fail(VDBC_E_INVALID, "tuning.blocks_per_cu must be <= 32");
+    *out = d;
+    return VDBC_OK;
+}
+
+// Validates the items and fills the per-volume launch state; `layout`
+// receives the workspace offsets (counter, descriptors, item list, then per
+// volume majorant and coarse bits) and the total size.
+static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vdbc_tuning& t, vdbc_batch* b,
+                              std::vector<uint64_t>* maj_off, std::vector<uint64_t>* coarse_off,
+                              uint64_t* items_off, uint64_t* total)
+{
+    if (!items || n == 0 || n > 4096) return fail(VDBC_E_INVALID, "need 1..4096 batch items");
+    b->n = n;
+    b->t = t;
+    uint64_t tiles_total = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const vdbc_batch_item& it = items[i];
+        VdbView v;
+        CameraK cam;
+        MediumK m;
+        vdbc_status s = make_view(&it.grid, &v);
+        if (!s) s = make_camera(&it.camera, &cam);
+        if (!s) s = make_medium(&it.medium, v.nx, v.ny, v.nz, &m);
+        if (s) return fail(s, "batch item %u: %s", i, vdbc_last_error());
+        if (it.spp == 0 || it.max_bounces == 0 || !it.image)
+            return fail(VDBC_E_INVALID, "batch item %u: spp, max_bounces >= 1 and an image are required", i);
+        const double l = std::sqrt((double)it.medium.light_dir[0] * it.medium.light_dir[0] +
+                                   (double)it.medium.light_dir[1] * it.medium.light_dir[1] +
+                                   (double)it.medium.light_dir[2] * it.medium.light_dir[2]);
+        if (!(std::fabs(l - 1.0) <= 1e-3)) return fail(VDBC_E_INVALID, "batch item %u: light_dir not unit", i);
+        PtArgs g;
+        pt_geometry(t.macrocell, v.nx, v.ny, v.nz, &g);
+        g.spp = (int)it.spp;
+        g.max_bounces = (int)it.max_bounces;
+        g.tw = (int)t.tile_w;
+        g.seed_lo = (uint32_t)it.seed;
+        g.seed_hi = (uint32_t)(it.seed >> 32);
+        g.frame = it.frame;
+        const int tx = (cam.width + 2 * g.tw - 1) / (2 * g.tw), ty = (cam.height + 128 / g.tw - 1) / (128 / g.tw);
+        if ((uint64_t)tx * ty > 0xFFFFFu) return fail(VDBC_E_INVALID, "batch item %u: image too large", i);
+        b->views.push_back(v);
+        b->cams.push_back(cam);
+        b->meds.push_back(m);
+        b->gs.push_back(g);
+        b->images.push_back(it.image);
+        b->tiles_x.push_back(tx);
+        b->tiles_y.push_back(ty);
+        tiles_total += (uint64_t)tx * ty;
+        b->max_cwords = std::max(b->max_cwords, g.cwords);
+    }
+    uint64_t o = 256;                                   // counter
+    const uint64_t descs_off = o;
+    o += align256((uint64_t)n * sizeof(BatchDesc));
+    *items_off = o;
+    o += align256(tiles_total * 4);
+    for (uint32_t i = 0; i < n; ++i) {
+        maj_off->push_back(o);
+        o += align256(majorant_bytes(t.macrocell, b->views[i].nx, b->views[i].ny, b->views[i].nz));
+        coarse_off->push_back(o);
+        o += align256(4ull * b->gs[i].cwords);
+    }
+    (void)descs_off;
+    b->n_items = (uint32_t)tiles_total;
+    *total = o;
+    return VDBC_OK;
+}
+
+static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
+{
+    vdbc_status s;
+    for (uint32_t i = 0; i < b->n; ++i) {
+        if ((s = launch_majorant<VdbAcc>(b->views[i], b->meds[i], (uint32_t)b->gs[i].C, b->majs[i], st))) return s;
+        const PtArgs& g = b->gs[i];
+        const uint64_t ncoarse = (uint64_t)g.cgx * g.cgy * g.cgz;
+        hipLaunchKernelGGL(coarse_bits_kernel, dim3((unsigned)((ncoarse + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           st, b->majs[i], g, b->coarse[i]);
+        if ((s = launch_check("batch coarse occupancy"))) return s;
+    }
+    if (b->t.persistent) {
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, b->d_counter);
+        hipLaunchKernelGGL(pt_batch_kernel, dim3(b->grid_blocks), dim3(kBlock), 4u * (size_t)b->max_cwords, st,
+                           b->d_descs, b->d_items, b->n_items, b->d_counter);
+        return launch_check("batched render");
+    }
+    for (uint32_t i = 0; i < b->n; ++i) {
+        const PtArgs& g = b->gs[i];
+        hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false>), dim3(b->tiles_x[i], b->tiles_y[i]),
+                           dim3(kBlock), 4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g,
+                           b->majs[i], b->coarse[i], b->images[i], nullptr, nullptr);
+        if ((s = launch_check("per-volume render"))) return s;
+    }
+    return VDBC_OK;
+}
+
+}  // namespace vdbc
+
+extern "C" vdbc_status vdbc_batch_workspace(const vdbc_batch_item* items, uint32_t n, const vdbc_tuning* t,
+                                            uint64_t* bytes)
+{
+    clear_error();
+    if (!bytes) return fail(VDBC_E_INVALID, "null argument");
+    vdbc_tuning tt;
+    vdbc_status s = batch_tuning(t, &tt);
+    if (s) return s;
+    vdbc_batch b;
+    std::vector<uint64_t> mo, co;
+    uint64_t io, total;
+    if ((s = batch_plan(items, n, tt, &b, &mo, &co, &io, &total))) return s;
+    *bytes = total;
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t n, const vdbc_tuning* t, void* ws,
+                                         uint64_t ws_bytes, void* stream, vdbc_batch** out)
+{
+    clear_error();
+    if (!out || !ws) return fail(VDBC_E_INVALID, "null argument");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(VDBC_E_INVALID, "workspace must be 256-byte aligned");
+    *out = nullptr;
+    vdbc_tuning tt;
+    vdbc_status s = batch_tuning(t, &tt);
+    if (s) return s;
+    std::unique_ptr<vdbc_batch> b(new (std::nothrow) vdbc_batch());
+    if (!b) return fail(VDBC_E_NOMEM, "no memory");
+    std::vector<uint64_t> mo, co;
+    uint64_t io, total;
+    if ((s = batch_plan(items, n, tt, b.get(), &mo, &co, &io, &total))) return s;
+    if (ws_bytes < total)
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "batch workspace needs %llu bytes", (unsigned long long)total);
+    uint8_t* w = static_cast<uint8_t*>(ws);
+    b->d_counter = reinterpret_cast<uint32_t*>(w);
+    b->d_descs = reinterpret_cast<BatchDesc*>(w + 256);
+    b->d_items = reinterpret_cast<uint32_t*>(w + io);
+    for (uint32_t i = 0; i < n; ++i) {
+        b->majs.push_back(reinterpret_cast<float*>(w + mo[i]));
+        b->coarse.push_back(reinterpret_cast<uint32_t*>(w + co[i]));
+    }
+    // descriptors and the cost-ordered work list (largest estimated cost first:
+    // samples per pixel x ray length through the volume)
+    std::vector<BatchDesc> descs(n);
+    std::vector<uint32_t> order(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        descs[i] = BatchDesc{b->views[i], b->cams[i], b->meds[i], b->gs[i], b->majs[i], b->coarse[i], b->images[i],
+                             b->tiles_x[i]};
+        order[i] = i;
+    }
+    auto cost = [&](uint32_t i) {
+        return (double)b->gs[i].spp * (double)(b->views[i].nx + b->views[i].ny + b->views[i].nz);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return cost(a) > cost(c); });
+    std::vector<uint32_t> list;
+    list.reserve(b->n_items);
+    for (uint32_t i : order)
+        for (uint32_t tl = 0; tl < (uint32_t)(b->tiles_x[i] * b->tiles_y[i]); ++tl) list.push_back((i << 20) | tl);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(b->d_descs, descs.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->d_items, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(VDBC_E_DEVICE, "batch descriptor upload: %s", hipGetErrorString(hipGetLastError()));
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->grid_blocks = std::max(1, cus) * (int)tt.blocks_per_cu;
+    *out = b.release();
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_batch_launch(vdbc_batch* b, void* stream)
+{
+    clear_error();
+    if (!b) return fail(VDBC_E_INVALID, "null batch");
+    return batch_enqueue(b, static_cast<hipStream_t>(stream));
+}
+
+extern "C" vdbc_status vdbc_batch_capture(vdbc_batch* b, void* stream)
+{
+    clear_error();
+    if (!b) return fail(VDBC_E_INVALID, "null batch");
+    if (!stream) return fail(VDBC_E_INVALID, "capture needs a non-default stream");
+    if (b->exec) return VDBC_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(VDBC_E_DEVICE, "begin capture: %s", hipGetErrorString(hipGetLastError()));
+    vdbc_status s = batch_enqueue(b, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s) {
+        if (g) hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess || !g) return fail(VDBC_E_DEVICE, "end capture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(VDBC_E_DEVICE, "graph instantiate failed");
+    }
+    b->graph = g;
+    b->exec = ex;
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_batch_graph_launch(vdbc_batch* b, void* stream)
+{
+    clear_error();
+    if (!b || !b->exec) return fail(VDBC_E_INVALID, "batch has no captured graph");
+    if (hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(VDBC_E_DEVICE, "graph launch: %s", hipGetErrorString(hipGetLastError()));
+    return VDBC_OK;
+}
+
+extern "C" void vdbc_batch_destroy(vdbc_batch* b)
+{
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    delete b;
 }

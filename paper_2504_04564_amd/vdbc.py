@@ -66,7 +66,7 @@ class RenderParamsC(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("spp", C.c_uint32), ("max_bounces", C.c_uint32),
                 ("macrocell", C.c_uint32), ("flags", C.c_uint32), ("step", C.c_float),
                 ("t_terminate", C.c_float), ("seed", C.c_uint64), ("frame", C.c_uint32),
-                ("reserved", C.c_uint32 * 3)]
+                ("tile_w", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 SYMBOLS = [
@@ -268,6 +268,7 @@ def params_c(p: dict, mode: int) -> RenderParamsC:
     r.t_terminate = p.get("t_terminate", 0.0)
     r.seed = p.get("seed", 0)
     r.frame = p.get("frame", 0)
+    r.tile_w = p.get("tile_w", 8)
     return r
 
 
@@ -379,3 +380,276 @@ def philox(ctr, key):
     out = torch.empty_like(c)
     _check(load().vdbc_philox(_dptr(c), _dptr(k), n, _dptr(out), _stream()))
     return out
+
+
+# ------------------------------------------------------------------ denoiser
+
+def _nn_signatures(L):
+    P, u32, u64, f32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_float
+    L.vdbc_nn_param_count.argtypes = [C.POINTER(u64)]
+    L.vdbc_nn_to_bf16.argtypes = [P, P, P]
+    L.vdbc_denoise_workspace.argtypes = [u32, u32, u32, u32, C.POINTER(u64)]
+    L.vdbc_denoise_pack.argtypes = [P, P, u64, P, P]
+    L.vdbc_denoise.argtypes = [P, P, P, u32, u32, u32, P, P, u64, P]
+    L.vdbc_denoise_train_step.argtypes = [P, P, P, P, u32, f32, P, P, u32, u32, u32, P, P, P,
+                                          u64, P]
+    L.vdbc_conv3x3.argtypes = [P, u32, P, u32, u32, u32, u32, u32, u32, P, P, u32, u32, P, P, P]
+    L.vdbc_conv3x3_grad_workspace.argtypes = [u32, u32, u32, u32, u32, C.POINTER(u64)]
+    L.vdbc_conv3x3_dgrad.argtypes = [P, u32, u32, u32, u32, u32, P, u32, u32, u32, u32, P, P,
+                                     u64, P]
+    L.vdbc_conv3x3_wgrad.argtypes = [P, u32, P, u32, u32, u32, u32, u32, u32, P, u32, u32, P, P,
+                                     P, u64, P]
+    for name in ["vdbc_nn_param_count", "vdbc_nn_to_bf16", "vdbc_denoise_workspace",
+                 "vdbc_denoise_pack", "vdbc_denoise", "vdbc_denoise_train_step", "vdbc_conv3x3",
+                 "vdbc_conv3x3_grad_workspace", "vdbc_conv3x3_dgrad", "vdbc_conv3x3_wgrad"]:
+        getattr(L, name).restype = C.c_int
+
+
+def _nn():
+    L = load()
+    if not getattr(L, "_nn_ready", False):
+        _nn_signatures(L)
+        L._nn_ready = True
+    return L
+
+
+def nn_param_count() -> int:
+    n = C.c_uint64(0)
+    _check(_nn().vdbc_nn_param_count(C.byref(n)))
+    return int(n.value)
+
+
+def _aligned_empty(nbytes: int, device="cuda"):
+    torch = _torch()
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t, t.data_ptr() + off
+
+
+def conv3x3(a, b, upsample, stride, w_bf16, bias, cout, relu, out_f32=False):
+    """One 3x3 conv layer on NHWC BF16 tensors (a: (n, hs, ws, ca), b: None or
+    (n, hs, ws, cb)); returns NHWC BF16 (or FP32) output."""
+    torch = _torch()
+    n, hs, ws_, ca = a.shape
+    cb = 0 if b is None else b.shape[-1]
+    hv, wv = (2 * hs, 2 * ws_) if upsample else (hs, ws_)
+    ho, wo = (hv - 1) // stride + 1, (wv - 1) // stride + 1
+    out = torch.empty((n, ho, wo, cout), dtype=torch.float32 if out_f32 else torch.bfloat16,
+                      device=a.device)
+    _check(_nn().vdbc_conv3x3(_dptr(a), ca, _dptr(b) if b is not None else None, cb,
+                              int(bool(upsample)), n, hs, ws_, stride, _dptr(w_bf16), _dptr(bias),
+                              cout, int(bool(relu)), None if out_f32 else _dptr(out),
+                              _dptr(out) if out_f32 else None, _stream()))
+    return out
+
+
+def conv3x3_dgrad(dz, cout, w_bf16, cin, stride, hv, wv):
+    torch = _torch()
+    n, ho, wo, coutp = dz.shape
+    ws = C.c_uint64(0)
+    _check(_nn().vdbc_conv3x3_grad_workspace(cin, cout, n, ho, wo, C.byref(ws)))
+    buf, ptr = _aligned_empty(int(ws.value), dz.device)
+    dx = torch.empty((n, hv, wv, cin), dtype=torch.float32, device=dz.device)
+    _check(_nn().vdbc_conv3x3_dgrad(_dptr(dz), coutp, cout, n, ho, wo, _dptr(w_bf16), cin, stride,
+                                    hv, wv, _dptr(dx), ptr, int(ws.value), _stream()))
+    torch.cuda.synchronize()
+    del buf
+    return dx
+
+
+def conv3x3_wgrad(a, b, upsample, stride, dz, cout):
+    torch = _torch()
+    n, hs, ws_, ca = a.shape
+    cb = 0 if b is None else b.shape[-1]
+    _, ho, wo, coutp = dz.shape
+    ws = C.c_uint64(0)
+    _check(_nn().vdbc_conv3x3_grad_workspace(ca + cb, cout, n, ho, wo, C.byref(ws)))
+    buf, ptr = _aligned_empty(int(ws.value), a.device)
+    dw = torch.empty((cout, 3, 3, ca + cb), dtype=torch.float32, device=a.device)
+    db = torch.empty(cout, dtype=torch.float32, device=a.device)
+    _check(_nn().vdbc_conv3x3_wgrad(_dptr(a), ca, _dptr(b) if b is not None else None, cb,
+                                    int(bool(upsample)), n, hs, ws_, stride, _dptr(dz), coutp,
+                                    cout, _dptr(dw), _dptr(db), ptr, int(ws.value), _stream()))
+    torch.cuda.synchronize()
+    del buf
+    return dw, db
+
+
+def init_denoiser_params(seed: int) -> np.ndarray:
+    """He-normal weights (std sqrt(2 / fan_in)), zero biases; the three zero
+    input channels of the first layer get zero weights; last layer x0.1."""
+    layers = [(8, 32), (32, 64), (64, 64), (64, 32), (64, 32), (32, 3)]
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (cin, cout) in enumerate(layers):
+        fan = 9 * (5 if i == 0 else cin)
+        w = rng.normal(0.0, np.sqrt(2.0 / fan), size=(cout, 3, 3, cin)).astype(np.float32)
+        if i == 0:
+            w[..., 5:] = 0.0
+        if i == len(layers) - 1:
+            w *= 0.1
+        out += [w.ravel(), np.zeros(cout, np.float32)]
+    return np.concatenate(out)
+
+
+class Denoiser:
+    """Device state of the denoiser: FP32 master parameters, BF16 copy, Adam
+    moments and a step counter."""
+
+    def __init__(self, params: np.ndarray | None = None, seed: int = 0, device="cuda"):
+        torch = _torch()
+        n = nn_param_count()
+        p = init_denoiser_params(seed) if params is None else np.asarray(params, np.float32)
+        if p.size != n:
+            raise ValueError(f"expected {n} parameters, got {p.size}")
+        self.params = torch.from_numpy(p.copy()).to(device)
+        self.wbf16 = torch.empty(n, dtype=torch.bfloat16, device=device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self._ws = {}
+        _check(_nn().vdbc_nn_to_bf16(_dptr(self.params), _dptr(self.wbf16), _stream()))
+
+    def _workspace(self, n, h, w, training):
+        key = (n, h, w, training)
+        if key not in self._ws:
+            b = C.c_uint64(0)
+            _check(_nn().vdbc_denoise_workspace(n, h, w, int(training), C.byref(b)))
+            self._ws[key] = (_aligned_empty(int(b.value)), int(b.value))
+        (buf, ptr), nb = self._ws[key]
+        return ptr, nb
+
+    def train_step(self, x, target, lr: float, grad_out=None):
+        n, h, w, _ = x.shape
+        ptr, nb = self._workspace(n, h, w, True)
+        self.step += 1
+        _check(_nn().vdbc_denoise_train_step(
+            _dptr(self.params), _dptr(self.wbf16), _dptr(self.m), _dptr(self.v), self.step,
+            float(lr), _dptr(x), _dptr(target), n, h, w, _dptr(self.loss),
+            _dptr(grad_out) if grad_out is not None else None, ptr, nb, _stream()))
+        return self.loss
+
+    def __call__(self, x, out=None):
+        torch = _torch()
+        n, h, w, _ = x.shape
+        ptr, nb = self._workspace(n, h, w, False)
+        if out is None:
+            out = torch.empty((n, h, w, 3), dtype=torch.float32, device=x.device)
+        _check(_nn().vdbc_denoise(_dptr(self.params), _dptr(self.wbf16), _dptr(x), n, h, w,
+                                  _dptr(out), ptr, nb, _stream()))
+        return out
+
+
+def denoise_pack(rgba, aov, out=None):
+    """Network input (BF16 [..., 8]) from render image and AOV tensors."""
+    torch = _torch()
+    shape = rgba.shape[:-1]
+    if out is None:
+        out = torch.empty(tuple(shape) + (8,), dtype=torch.bfloat16, device=rgba.device)
+    pixels = rgba.numel() // 4
+    _check(_nn().vdbc_denoise_pack(_dptr(rgba), _dptr(aov), pixels, _dptr(out), _stream()))
+    return out
+
+
+# ------------------------------------------------------------------ batches
+
+class BatchItemC(C.Structure):
+    _fields_ = [("grid", GridC), ("camera", CameraC), ("medium", MediumC),
+                ("spp", C.c_uint32), ("max_bounces", C.c_uint32), ("seed", C.c_uint64),
+                ("frame", C.c_uint32), ("image", C.c_void_p)]
+
+
+class TuningC(C.Structure):
+    _fields_ = [("macrocell", C.c_uint32), ("tile_w", C.c_uint32),
+                ("blocks_per_cu", C.c_uint32), ("persistent", C.c_uint32)]
+
+
+def _batch_signatures(L):
+    P, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+    L.vdbc_batch_workspace.argtypes = [P, u32, P, C.POINTER(u64)]
+    L.vdbc_batch_create.argtypes = [P, u32, P, P, u64, P, C.POINTER(P)]
+    L.vdbc_batch_launch.argtypes = [P, P]
+    L.vdbc_batch_capture.argtypes = [P, P]
+    L.vdbc_batch_graph_launch.argtypes = [P, P]
+    L.vdbc_batch_destroy.argtypes = [P]
+    L.vdbc_batch_destroy.restype = None
+    for name in ["vdbc_batch_workspace", "vdbc_batch_create", "vdbc_batch_launch",
+                 "vdbc_batch_capture", "vdbc_batch_graph_launch"]:
+        getattr(L, name).restype = C.c_int
+
+
+def _bt():
+    L = load()
+    if not getattr(L, "_batch_ready", False):
+        _batch_signatures(L)
+        L._batch_ready = True
+    return L
+
+
+def tuning_c(t: dict | None) -> TuningC:
+    t = t or {}
+    return TuningC(t.get("macrocell", 16), t.get("tile_w", 8), t.get("blocks_per_cu", 4),
+                   int(t.get("persistent", 1)))
+
+
+class Batch:
+    """Many volumes rendered by one persistent launch (or one launch per
+    volume with persistent=0), optionally replayed from a captured graph.
+
+    items: list of dicts with grid (Grid), camera, medium, spp, max_bounces,
+    seed, frame; every item gets its own image tensor (h, w, 4)."""
+
+    def __init__(self, items: list, tuning: dict | None = None, device="cuda"):
+        torch = _torch()
+        L = _bt()
+        self.items = items
+        self.images = []
+        arr = (BatchItemC * len(items))()
+        for i, it in enumerate(items):
+            cam = it["camera"]
+            img = torch.empty((cam["height"], cam["width"], 4), dtype=torch.float32, device=device)
+            self.images.append(img)
+            a = arr[i]
+            a.grid = it["grid"].c
+            a.camera = camera_c(cam)
+            a.medium = medium_c(it["medium"])
+            a.spp = it.get("spp", 1)
+            a.max_bounces = it.get("max_bounces", 8)
+            a.seed = it.get("seed", 0)
+            a.frame = it.get("frame", 0)
+            a.image = _dptr(img)
+        self._arr = arr
+        self.tuning = tuning_c(tuning)
+        nb = C.c_uint64(0)
+        _check(L.vdbc_batch_workspace(C.cast(arr, C.c_void_p), len(items), C.byref(self.tuning),
+                                      C.byref(nb)))
+        self.ws, self.ws_ptr = _aligned_empty(int(nb.value), device)
+        self.ws_bytes = int(nb.value)
+        self.plan = C.c_void_p()
+        _check(L.vdbc_batch_create(C.cast(arr, C.c_void_p), len(items), C.byref(self.tuning),
+                                   self.ws_ptr, self.ws_bytes, _stream(), C.byref(self.plan)))
+        self.captured = False
+
+    def launch(self, stream=None):
+        _check(_bt().vdbc_batch_launch(self.plan, stream if stream is not None else _stream()))
+
+    def capture(self, stream):
+        """Capture the launch sequence on a non-default torch stream."""
+        _check(_bt().vdbc_batch_capture(self.plan, C.c_void_p(stream.cuda_stream)))
+        self.captured = True
+
+    def replay(self, stream=None):
+        _check(_bt().vdbc_batch_graph_launch(self.plan,
+                                             stream if stream is not None else _stream()))
+
+    def close(self):
+        if self.plan:
+            _bt().vdbc_batch_destroy(self.plan)
+            self.plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,96 @@
+"""Batched multi-volume rendering: the persistent launch, the per-volume
+launches and the replays of the captured graph all give images bit-identical
+to one vdbc_render call per volume (same random keys)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2504_04564_amd import _build, autotune, vdbc
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def lib():
+    _build.ensure_built()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return vdbc.load()
+
+
+def _items(count=10, seed=3):
+    specs = synth.batch_sizes(count, seed=seed, lo=24, hi=96)
+    grids, items = [], []
+    for i, (side, q, spp) in enumerate(specs):
+        v = synth.cloud_volume((side, side + 3 * (i % 3), side), seed=100 + i)
+        buf, _ = vdbc.encode(v, q)
+        g = vdbc.Grid(buf)
+        grids.append(g)
+        w, h = 40 + 8 * (i % 4), 36 + 5 * (i % 3)
+        items.append(dict(grid=g, camera=scenes.orbit_camera(g.dims, w, h, azimuth_deg=20 * i),
+                          medium=scenes.pt_medium(48.0), spp=min(spp, 4), max_bounces=6,
+                          seed=0x1234 + i, frame=i))
+    return items
+
+
+def _single(it, macrocell, tile_w=8):
+    prm = dict(spp=it["spp"], max_bounces=it["max_bounces"], seed=it["seed"], frame=it["frame"],
+               macrocell=macrocell, tile_w=tile_w)
+    return vdbc.render(it["grid"], it["camera"], it["medium"], prm, vdbc.MODE_PT).clone()
+
+
+def _same(a, b):
+    return torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+@pytest.mark.parametrize("tuning", [dict(macrocell=16, tile_w=8, blocks_per_cu=4, persistent=1),
+                                    dict(macrocell=8, tile_w=16, blocks_per_cu=2, persistent=1),
+                                    dict(macrocell=16, tile_w=32, blocks_per_cu=1, persistent=0)])
+def test_batch_equals_single_launches(tuning):
+    items = _items()
+    ref = [_single(it, tuning["macrocell"]) for it in items]
+    b = vdbc.Batch(items, tuning)
+    b.launch()
+    torch.cuda.synchronize()
+    for img, r in zip(b.images, ref):
+        assert _same(img, r)
+    b.close()
+
+
+def test_graph_replays_match_eager():
+    items = _items(8, seed=5)
+    ref = [_single(it, 16) for it in items]
+    b = vdbc.Batch(items, dict(macrocell=16))
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    b.capture(s)
+    for rep in range(3):
+        for img in b.images:
+            img.zero_()
+        # eager work in between replays
+        _ = _single(items[rep], 16)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            b.replay()
+        s.synchronize()
+        for img, r in zip(b.images, ref):
+            assert _same(img, r), rep
+    b.close()
+
+
+def test_autotuner_picks_a_measured_candidate(tmp_path):
+    items = _items(4, seed=9)
+    best, allr = autotune.tune_batch(items, dict(macrocell=(16,), tile_w=(8, 16),
+                                                 blocks_per_cu=(2, 4), persistent=(0, 1)), reps=2)
+    assert best in allr and len(allr) == 8
+    assert best["ms"] == min(r["ms"] for r in allr)
+    it = items[0]
+    prm = dict(spp=it["spp"], max_bounces=it["max_bounces"], seed=it["seed"])
+    path = str(tmp_path / "tune.json")
+    key = autotune.workload_key("vdb", it["grid"].dims, 0.1, it["spp"])
+    choice = autotune.cached_render_tuning(
+        path, key, lambda: autotune.tune_render(it["grid"], it["camera"], it["medium"], prm,
+                                                space=dict(macrocell=(8, 16), tile_w=(8, 32)),
+                                                reps=2))
+    assert autotune.load(path)[key] == choice

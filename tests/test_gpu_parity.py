@@ -364,3 +364,16 @@ def test_pt_mid_config_sampled_pixels():
     want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, pixels=pix)
     assert relmse(img[pix], want) <= 1e-4
     assert np.all(np.isfinite(img))
+
+
+def test_pt_image_independent_of_wave_tile_shape():
+    v = synth.mid_volume(n=64)
+    buf, _ = vdbc.encode(v, 0.25)
+    g = vdbc.Grid(buf)
+    cam, med, prm = _pt_scene(64, 70, 33, 2)
+    imgs = []
+    for tw in (8, 16, 32, 64):
+        p = dict(prm, tile_w=tw)
+        imgs.append(vdbc.render(g, cam, med, p, vdbc.MODE_PT).cpu().numpy())
+    for im in imgs[1:]:
+        assert np.array_equal(im.view(np.uint32), imgs[0].view(np.uint32))

@@ -92,6 +92,10 @@ def main():
     ap.add_argument("--macrocell", type=int, default=16, help="majorant cell edge in voxels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
+    ap.add_argument("--train-steps", type=int, default=1500, help="denoiser workload: Adam steps")
+    ap.add_argument("--workload", default="mid", choices=("mid", "paper", "denoiser", "batch"),
+                    help="mid: the headline 512^3 frame; paper: 1987x1351x2449 rate sweep; "
+                         "denoiser: train and evaluate the learned denoiser; batch: 64 volumes")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -120,6 +124,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
                           "launches": 3}))
+        return
+    if args.workload != "mid":
+        import bench_workloads
+        line = getattr(bench_workloads, args.workload)(args, torch, vdbc, synth, scenes, log)
+        print(json.dumps(line), flush=True)
         return
     M = scenes.MID
     n = args.size

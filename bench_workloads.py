@@ -1,0 +1,191 @@
+"""Secondary measurements of bench.py: the paper-scale rate sweep, the
+learned denoiser and the batched multi-volume launch.  Each returns one JSON
+object (printed by bench.py)."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _median_ms(torch, fn, reps, warmup=1):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def paper(args, torch, vdbc, synth, scenes, log):
+    """1987x1351x2449 billowed cloud (26.3 GB): encode at 1:20..1:4, path
+    trace 1920x1080 at 64 spp with <= 16 bounces from every VDB and from the
+    dense array on the same GPU."""
+    P = scenes.PAPER
+    nx, ny, nz = P["dims"]
+    t = time.time()
+    vol = synth.paper_volume(dims=P["dims"])
+    log(f"[paper] volume {vol.nbytes / 1e9:.1f} GB in {time.time() - t:.0f}s")
+    W, H, spp, bounces = P["width"], P["height"], P["spp"], P["max_bounces"]
+    C = args.macrocell
+    cam = scenes.orbit_camera((nx, ny, nz), W, H)
+    med = scenes.pt_medium(64.0)
+    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C,
+               flags=vdbc.RENDER_COUNT)
+    rays = W * H * spp
+    out = {"metric": "paper-scale VDB vs dense path-traced Mrays/s", "unit": "Mrays/s",
+           "config": {"workload": "fbm-cloud-1987x1351x2449-pt-1920x1080x64spp-16bounces",
+                      "dims": list(P["dims"]), "macrocell": C}, "rates": []}
+    for q in P["rates"]:
+        t = time.time()
+        buf, st = vdbc.encode(vol, q)
+        enc = time.time() - t
+        g = vdbc.Grid(buf)
+        r = vdbc.Renderer(g, cam, med, prm, vdbc.MODE_PT)
+        ms = _median_ms(torch, r.launch, 3)
+        rec = {"rate": q, "encode_s": round(enc, 2), "vdb_bytes": int(buf.size),
+               "achieved_rate": round(st["achieved_rate"], 5), "ms": round(ms, 2),
+               "mrays_per_s": round(rays / ms / 1e3, 2),
+               "samples_per_s": round(r.sample_count() / ms * 1e3, 1)}
+        log(f"[paper] q={q}: {rec}")
+        out["rates"].append(rec)
+        del r, g, buf
+        torch.cuda.empty_cache()
+    t = time.time()
+    dense = torch.from_numpy(vol).cuda()
+    log(f"[paper] dense upload {time.time() - t:.1f}s")
+    r = vdbc.Renderer(dense, cam, med, prm, vdbc.MODE_PT, background=0.0)
+    ms = _median_ms(torch, r.launch, 3)
+    out["dense"] = {"ms": round(ms, 2), "mrays_per_s": round(rays / ms / 1e3, 2),
+                    "samples_per_s": round(r.sample_count() / ms * 1e3, 1),
+                    "bytes": int(vol.nbytes)}
+    ten = [x for x in out["rates"] if abs(x["rate"] - 0.10) < 1e-9][0]
+    out["value"] = ten["mrays_per_s"]
+    out["vdb_over_dense_at_1:10"] = round(ten["mrays_per_s"] / out["dense"]["mrays_per_s"], 4)
+    log(f"[paper] dense {out['dense']}")
+    return out
+
+
+def denoiser(args, torch, vdbc, synth, scenes, log):
+    """Learned denoiser: training pairs rendered from seeded clouds at 1:10
+    (4-spp input with AOVs, high-spp target), training with the library's
+    BF16-MFMA step, evaluation on held-out clouds against a 1024-spp
+    reference."""
+    from paper_2504_04564_amd import denoiser as dz
+    rng = np.random.default_rng(1000)
+    n_vol, views, size = 16, 6, 256
+    spp_in, spp_tgt = 4, 512
+    med = scenes.pt_medium(64.0)
+    xs, ts = [], []
+    t = time.time()
+    for i in range(n_vol):
+        side = int(rng.integers(128, 257))
+        v = synth.cloud_volume((side, side, side), seed=1000 + i)
+        buf, _ = vdbc.encode(v, 0.10)
+        g = vdbc.Grid(buf)
+        for k in range(views):
+            cam = scenes.orbit_camera(g.dims, size, size, azimuth_deg=float(rng.uniform(0, 360)),
+                                      elevation_deg=float(rng.uniform(-30, 45)),
+                                      distance=float(rng.uniform(1.2, 2.0)))
+            x, ref = dz.render_pair(g, cam, med, spp_in, spp_tgt, seed=7919 * i + k)
+            xs.append(x)
+            ts.append(ref)
+    torch.cuda.synchronize()
+    gen_s = time.time() - t
+    X = torch.stack(xs)
+    T = torch.stack(ts)
+    log(f"[denoiser] {X.shape[0]} training crops of {size}^2 in {gen_s:.1f}s")
+    dn = vdbc.Denoiser(seed=5)
+    steps, batch = args.train_steps, 8
+    t = time.time()
+    losses = dz.train(dn, X, T, steps=steps, batch=batch, lr=1e-3, seed=1, log_every=200)
+    torch.cuda.synchronize()
+    train_s = time.time() - t
+    evals = []
+    for j in range(3):
+        side = 384
+        v = synth.cloud_volume((side, side, side), seed=5000 + j)
+        buf, _ = vdbc.encode(v, 0.10)
+        g = vdbc.Grid(buf)
+        cam = scenes.orbit_camera(g.dims, 512, 512, azimuth_deg=40.0 + 90 * j)
+        evals.append(dz.evaluate(dn, g, cam, med, seed=31 + j))
+        log(f"[denoiser] eval {j}: {evals[-1]}")
+    keys = ("relmse_plain_lo", "relmse_plain_hi", "relmse_denoised", "ms_plain_hi",
+            "ms_denoised_pipeline")
+    mean = {k: float(np.mean([e[k] for e in evals])) for k in keys}
+    return {"metric": "denoised 4-spp relMSE vs plain 64-spp relMSE (1024-spp reference)",
+            "value": mean["relmse_denoised"], "unit": "relMSE", "higher_is_better": False,
+            "config": {"workload": f"{n_vol}x{views} crops {size}^2 at 1:10, targets {spp_tgt} spp,"
+                                   f" eval 3 clouds 384^3 at 512^2",
+                       "train_steps": steps, "batch": batch, "lr": 1e-3},
+            "train_s": round(train_s, 2), "gen_s": round(gen_s, 2),
+            "ms_per_train_step": round(train_s / steps * 1e3, 3),
+            "loss_first": float(losses[0]), "loss_last": float(np.mean(losses[-20:])),
+            "mean": mean, "evals": evals}
+
+
+def batch(args, torch, vdbc, synth, scenes, log):
+    """64 volumes, sides log-uniform in [32, 768], rates from {1:4, 1:6,
+    1:10, 1:20}, 256x256 images with 1-8 spp: per-volume launches vs one
+    persistent launch vs graph replay, with the autotuned tuning."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2504_04564_amd import autotune
+    specs = synth.batch_sizes(64, seed=7)
+    t = time.time()
+
+    def make(i):
+        side, q, spp = specs[i]
+        v = synth.cloud_volume((side, side, side), seed=7000 + i)
+        buf, _ = vdbc.encode(v, q, threads=1)
+        return buf, v.nbytes
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        made = list(ex.map(make, range(len(specs))))
+    log(f"[batch] 64 volumes generated and encoded in {time.time() - t:.0f}s, "
+        f"dense total {sum(m[1] for m in made) / 1e9:.1f} GB")
+    med = scenes.pt_medium(64.0)
+    items = []
+    for i, ((buf, _), (side, q, spp)) in enumerate(zip(made, specs)):
+        g = vdbc.Grid(buf)
+        items.append(dict(grid=g, camera=scenes.orbit_camera(g.dims, 256, 256, azimuth_deg=7.0 * i),
+                          medium=med, spp=spp, max_bounces=8, seed=0xB00 + i, frame=0))
+    rays = sum(256 * 256 * it["spp"] for it in items)
+    best, allr = autotune.tune_batch(items, dict(macrocell=(8, 16), tile_w=(8, 16),
+                                                 blocks_per_cu=(2, 4, 8), persistent=(1,)), reps=3)
+    log(f"[batch] tuned: {best}")
+    t_best = dict(best)
+    t_best.pop("ms")
+    per = vdbc.Batch(items, dict(t_best, persistent=0))
+    ms_per = _median_ms(torch, per.launch, 5)
+    pers = vdbc.Batch(items, dict(t_best, persistent=1))
+    ms_pers = _median_ms(torch, pers.launch, 5)
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    pers.capture(s)
+
+    def replay():
+        with torch.cuda.stream(s):
+            pers.replay()
+        s.synchronize()
+
+    ms_graph = _median_ms(torch, replay, 5)
+    same = all(torch.equal(a.view(torch.int32), b.view(torch.int32))
+               for a, b in zip(per.images, pers.images))
+    return {"metric": "batched multi-volume path-traced Mrays/s", "unit": "Mrays/s",
+            "value": round(rays / ms_graph / 1e3, 2),
+            "config": {"workload": "64 fbm clouds 32^3-768^3, rates 1:4..1:20, 256x256, 1-8 spp",
+                       "tuning": t_best},
+            "ms_per_volume_launches": round(ms_per, 3), "ms_persistent": round(ms_pers, 3),
+            "ms_graph_replay": round(ms_graph, 3),
+            "mrays_per_volume_launches": round(rays / ms_per / 1e3, 2),
+            "images_bit_identical": bool(same), "tuning_candidates": allr}

@@ -191,3 +191,24 @@ def test_device_calls_reject_bad_arguments_before_launch(lib):
     tiny_step = vdbc.params_c(dict(step=1e-6), vdbc.MODE_EA)
     assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(tiny_step), 4096,
                            None, None, 0, None) == vdbc.E_INVALID
+
+
+def test_binding_structs_match_c_header(tmp_path):
+    # the ctypes mirrors of the ABI structs have the C header's size and offsets
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "vdbc.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(vdbc_batch_item), sizeof(vdbc_tuning), sizeof(vdbc_render_params),'
+                   'sizeof(vdbc_medium), sizeof(vdbc_camera), sizeof(vdbc_grid),'
+                   'sizeof(vdbc_encode_params), sizeof(vdbc_encode_stats),'
+                   'offsetof(vdbc_batch_item, image));return 0;}\n')
+    exe = tmp_path / "sz"
+    import subprocess
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = [C.sizeof(vdbc.BatchItemC), C.sizeof(vdbc.TuningC), C.sizeof(vdbc.RenderParamsC),
+            C.sizeof(vdbc.MediumC), C.sizeof(vdbc.CameraC), C.sizeof(vdbc.GridC),
+            C.sizeof(vdbc.EncodeParams), C.sizeof(vdbc.EncodeStats), vdbc.BatchItemC.image.offset]
+    assert got == want

@@ -184,7 +184,7 @@ typedef struct {
     uint32_t mode;          /* VDBC_MODE_EA or VDBC_MODE_PT */
     uint32_t spp;           /* PT samples per pixel (>= 1) */
     uint32_t max_bounces;   /* PT scattering events per path (>= 1) */
-    uint32_t macrocell;     /* majorant cell edge in voxels (4..64) */
+    uint32_t macrocell;     /* PT majorant cell edge in voxels: 4, 8, 16, 32 or 64 */
     uint32_t flags;         /* VDBC_RENDER_* */
     float step;             /* EA step in voxels (> 0) */
     float t_terminate;      /* EA: stop when transmittance < this (0 = off) */
@@ -237,7 +237,7 @@ typedef struct {
 } vdbc_batch_item;
 
 typedef struct {
-    uint32_t macrocell;      /* majorant cell edge in voxels, 4..64 (default 16) */
+    uint32_t macrocell;      /* majorant cell edge in voxels: 4, 8, 16, 32, 64 (default 16) */
     uint32_t tile_w;         /* pixels per wave row: 8, 16, 32, 64 (default 8) */
     uint32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4) */
     uint32_t persistent;     /* 1: one persistent launch over all (volume, tile)

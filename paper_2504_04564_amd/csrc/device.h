@@ -392,9 +392,10 @@ __device__ __forceinline__ void camera_ray(const CameraK& c, float x, float y, f
     for (int a = 0; a < 3; ++a) d[a] *= inv;
 }
 
-// Ray / box [-0.5, n-0.5]^3; t0 clamped to >= 0.
+// Ray / box [-0.5, n-0.5]^3 with the direction's reciprocals id = 1/d;
+// t0 clamped to >= 0.
 __device__ __forceinline__ bool box_clip(int nx, int ny, int nz, const float o[3],
-                                         const float d[3], float& t0, float& t1)
+                                         const float d[3], const float id[3], float& t0, float& t1)
 {
     const float hi[3] = {(float)nx - 0.5f, (float)ny - 0.5f, (float)nz - 0.5f};
     float lo_t = -INFINITY, hi_t = INFINITY;
@@ -404,8 +405,7 @@ __device__ __forceinline__ bool box_clip(int nx, int ny, int nz, const float o[3
             if (o[a] < -0.5f || o[a] > hi[a]) return false;
             continue;
         }
-        const float inv = 1.0f / d[a];
-        const float ta = (-0.5f - o[a]) * inv, tb = (hi[a] - o[a]) * inv;
+        const float ta = (-0.5f - o[a]) * id[a], tb = (hi[a] - o[a]) * id[a];
         lo_t = fmaxf(lo_t, fminf(ta, tb));
         hi_t = fminf(hi_t, fmaxf(ta, tb));
     }

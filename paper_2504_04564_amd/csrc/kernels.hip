@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
         float o[3], d[3], t0, t1;
         camera_ray(cam, (float)px + 0.5f, (float)py + 0.5f, o, d);
         float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, T = 1.0f;
-        if (box_clip(view.nx, view.ny, view.nz, o, d, t0, t1)) {
+        const float id[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
+        if (box_clip(view.nx, view.ny, view.nz, o, d, id, t0, t1)) {
             for (int k = 0;; ++k) {
                 const float t = fmaf((float)k + 0.5f, step, t0);
                 if (t >= t1) break;
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
 
 struct PtArgs {
     int spp, max_bounces, C, gx, gy, gz, tw;
+    float invC;
     int lf, cgx, cgy, cgz, cwords;   // coarse blocks of 2^lf macrocells per axis, bit words
     uint32_t seed_lo, seed_hi, frame;
 };
@@ -234,13 +236,13 @@ __device__ __forceinline__ void flight_begin(Flight& f, const PtArgs& g, int nx,
     }
     f.incell = false;
     f.budget = kMaxFlightSamples;
-    f.ok = box_clip(nx, ny, nz, o, d, t0, f.t1);
+    f.ok = box_clip(nx, ny, nz, o, d, f.id, t0, f.t1);
     f.t = t0;
     if (!f.ok) return;
-    const float C = (float)g.C;
-    f.cx = min(max((int)floorf((fmaf(t0, d[0], o[0]) + 0.5f) / C), 0), g.gx - 1);
-    f.cy = min(max((int)floorf((fmaf(t0, d[1], o[1]) + 0.5f) / C), 0), g.gy - 1);
-    f.cz = min(max((int)floorf((fmaf(t0, d[2], o[2]) + 0.5f) / C), 0), g.gz - 1);
+    // the macrocell edge is a power of two: multiplying by its reciprocal is exact
+    f.cx = min(max((int)floorf((fmaf(t0, d[0], o[0]) + 0.5f) * g.invC), 0), g.gx - 1);
+    f.cy = min(max((int)floorf((fmaf(t0, d[1], o[1]) + 0.5f) * g.invC), 0), g.gy - 1);
+    f.cz = min(max((int)floorf((fmaf(t0, d[2], o[2]) + 0.5f) * g.invC), 0), g.gz - 1);
 }
 
 __device__ __forceinline__ bool coarse_occupied(const uint32_t* bits, const PtArgs& g, int bx,
@@ -296,6 +298,7 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
     if (!f.ok) return 0;
     const float C = (float)g.C;
     const float CF = (float)(g.C << g.lf);
+    (void)C;
     for (;;) {
         if (f.incell) {
             f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
@@ -329,9 +332,9 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
             if (axis < 0) return 0;
             f.t = te;
             const int F = 1 << g.lf;
-            const float px = (fmaf(te, f.d[0], f.o[0]) + 0.5f) / C;
-            const float py = (fmaf(te, f.d[1], f.o[1]) + 0.5f) / C;
-            const float pz = (fmaf(te, f.d[2], f.o[2]) + 0.5f) / C;
+            const float px = (fmaf(te, f.d[0], f.o[0]) + 0.5f) * g.invC;
+            const float py = (fmaf(te, f.d[1], f.o[1]) + 0.5f) * g.invC;
+            const float pz = (fmaf(te, f.d[2], f.o[2]) + 0.5f) * g.invC;
             if (axis == 0) {
                 f.cx = f.d[0] > 0.0f ? (bx + 1) * F : bx * F - 1;
                 if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
@@ -383,39 +386,71 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
 // implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
 // stream << 16 | bounce, frame); stream 0 = jitter, free flights and the
 // scattering direction; stream 1 = the shadow ray of that bounce.
-// Delta-tracking path tracer (Section 4) for one pixel: that pixel's paths one
-// after another in a flat loop.  Every iteration moves the lane to its next
-// tentative collision and handles whatever event the lane reached (collision,
-// escape, end of a shadow ray, start of a new path), so the lanes of a wave
-// never wait for each other at bounce or sample boundaries.  The arithmetic
-// and the random draws of each path are those of a recursive implementation:
-// key (seed_lo ^ pixel, seed_hi), counter (block, sample, stream << 16 |
-// bounce, frame); stream 0 = jitter, free flights and the scattering
-// direction; stream 1 = the shadow ray of that bounce.  Results depend only
-// on the pixel, not on which thread or launch shape renders it.
-template <class Acc>
-__device__ __forceinline__ void pt_pixel(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
-                                         const MediumK& m, const PtArgs& g,
-                                         const float* __restrict__ maj, const uint32_t* cbits,
-                                         int px, int py, bool live, float4& rgba, float2& aovv,
-                                         uint32_t& nsamp, uint32_t& ncell)
+// LDS state of one 256-pixel tile: next unit of work and per-pixel sums in
+// 2^-32 fixed point (integer sums do not depend on the order of the adds).
+struct TileShared {
+    long long rgb[kBlock][3];
+    long long depth[kBlock];
+    unsigned int hits[kBlock], escapes[kBlock];
+    unsigned int next;
+};
+
+__device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v * 4294967296.0f); }
+
+// Delta-tracking path tracer (Section 4) over one tile of 256 pixels.  The
+// tile's 256 x spp paths (unit u = sample u / 256 of tile pixel u % 256) are
+// shared by the workgroup: every lane starts on one unit and takes the next
+// one from an LDS counter when its path ends, so lanes on empty pixels or on
+// short paths keep working.  Within a path the loop is flat: every iteration
+// moves the lane to its next tentative collision and handles whatever event
+// it reached (collision, escape, end of a shadow ray, start of a new path).
+// The arithmetic and the random draws of each path are those of a recursive
+// implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
+// stream << 16 | bounce, frame); stream 0 = jitter, free flights and the
+// scattering direction; stream 1 = the shadow ray of that bounce.  Results
+// depend only on the pixel, not on the lane, tile shape or launch.
+template <class Acc, bool AOV>
+__device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
+                                        const MediumK& m, const PtArgs& g,
+                                        const float* __restrict__ maj, const uint32_t* cbits,
+                                        int bx, int by, TileShared& ts, float* __restrict__ image,
+                                        float* __restrict__ aov, uint32_t& nsamp, uint32_t& ncell)
 {
-    const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
-    const uint32_t k0 = g.seed_lo ^ pix;
+    const int tid = threadIdx.x;
+    const int tw = g.tw, th = 64 / g.tw;
+    const int x0 = bx * 2 * tw, y0 = by * 2 * th;
+    ts.rgb[tid][0] = ts.rgb[tid][1] = ts.rgb[tid][2] = 0;
+    ts.depth[tid] = 0;
+    ts.hits[tid] = ts.escapes[tid] = 0;
+    if (tid == 0) ts.next = kBlock;
+    __syncthreads();
+    const uint32_t total = (uint32_t)kBlock * (uint32_t)g.spp;
     const float inv4pi = 0.0795774715459476679f;
-    float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f, opac = 0.0f, depth = 0.0f, trans = 0.0f;
+    uint32_t u = (uint32_t)tid;
+    int q = 0, px = 0, py = 0;
+    uint32_t k0 = 0, smp = 0;
     float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
-    float t0p = 0.0f;
-    int s = live ? 0 : g.spp;   // current sample of this lane's pixel
-    int b = 0;                  // bounce
+    float t0p = 0.0f, pdepth = 1.0f;
+    bool phit = false;
+    int b = 0;
     bool shadow = false, fresh = true;
     uint32_t path_d = 0;
     Rng rng;
     Flight f;
-    while (s < g.spp) {
+    while (u < total) {
         if (fresh) {
+            q = (int)(u & (kBlock - 1));
+            smp = u >> 8;
+            const int w = q >> 6, l = q & 63;
+            px = x0 + (w & 1) * tw + (l % tw);
+            py = y0 + (w >> 1) * th + (l / tw);
+            if (px >= cam.width || py >= cam.height) {   // no pixel here
+                u = atomicAdd(&ts.next, 1u);
+                continue;
+            }
             fresh = false;
-            rng.init(k0, g.seed_hi, (uint32_t)s, 0u, 0u, g.frame);
+            k0 = g.seed_lo ^ ((uint32_t)py * (uint32_t)cam.width + (uint32_t)px);
+            rng.init(k0, g.seed_hi, smp, 0u, 0u, g.frame);
             const float jx = rng.next(), jy = rng.next();
             float o[3], d[3];
             camera_ray(cam, (float)px + jx, (float)py + jy, o, d);
@@ -432,13 +467,8 @@ __device__ __forceinline__ void pt_pixel(Acc& acc, int nx, int ny, int nz, const
         bool path_done = false, next_bounce = false;
         if (!shadow) {
             if (b == 0) {
-                if (hit) {
-                    opac += 1.0f;
-                    depth += (f.t - t0p) / (f.t1 - t0p);
-                } else {
-                    trans += 1.0f;
-                    depth += 1.0f;
-                }
+                phit = hit;
+                pdepth = hit ? (f.t - t0p) / (f.t1 - t0p) : 1.0f;
             }
             if (hit) {
                 // real collision: weight by albedo and colour, then the
@@ -450,7 +480,7 @@ __device__ __forceinline__ void pt_pixel(Acc& acc, int nx, int ny, int nz, const
                 const float x[3] = {fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
                                     fmaf(f.t, f.d[2], f.o[2])};
                 path_d = rng.d;
-                rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 1u, g.frame);
+                rng.init(k0, g.seed_hi, smp, (uint32_t)b, 1u, g.frame);
                 float t0s;
                 flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
                 shadow = true;
@@ -473,35 +503,51 @@ __device__ __forceinline__ void pt_pixel(Acc& acc, int nx, int ny, int nz, const
         if (next_bounce) {
             // isotropic scattering from the collision point (the shadow ray's
             // origin), drawn from the path stream of this bounce
-            rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 0u, g.frame);
+            rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
             rng.seek(path_d);
             const float u1 = rng.next(), u2 = rng.next();
             const float z = 1.0f - 2.0f * u1;
             const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-            float sp, cp;
-            sincosf(6.28318530717958647692f * u2, &sp, &cp);
+            const float phi = 6.28318530717958647692f * u2;
             const float o[3] = {f.o[0], f.o[1], f.o[2]};
-            const float d[3] = {r * cp, r * sp, z};
+            const float d[3] = {r * __cosf(phi), r * __sinf(phi), z};
             ++b;
-            rng.init(k0, g.seed_hi, (uint32_t)s, (uint32_t)b, 0u, g.frame);
+            rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
             float t0n;
             flight_begin(f, g, nx, ny, nz, o, d, t0n);
         }
         if (path_done) {
-            r0 += L0;
-            r1 += L1;
-            r2 += L2;
-            ++s;
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][0]), (unsigned long long)to_fixed(L0));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][1]), (unsigned long long)to_fixed(L1));
+            atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][2]), (unsigned long long)to_fixed(L2));
+            if (AOV) atomicAdd(reinterpret_cast<unsigned long long*>(&ts.depth[q]),
+                               (unsigned long long)to_fixed(pdepth));
+            atomicAdd(phit ? &ts.hits[q] : &ts.escapes[q], 1u);
+            u = atomicAdd(&ts.next, 1u);
             fresh = true;
         }
     }
-    const float inv = 1.0f / (float)g.spp;
-    rgba = make_float4(r0 * inv, r1 * inv, r2 * inv, opac * inv);
-    aovv = make_float2(depth * inv, trans * inv);
+    __syncthreads();
+    {
+        const int w = tid >> 6, l = tid & 63;
+        const int qx = x0 + (w & 1) * tw + (l % tw), qy = y0 + (w >> 1) * th + (l / tw);
+        if (qx < cam.width && qy < cam.height) {
+            const uint32_t pix = (uint32_t)qy * (uint32_t)cam.width + (uint32_t)qx;
+            const double sc = 1.0 / (4294967296.0 * (double)g.spp);
+            const float inv = 1.0f / (float)g.spp;
+            reinterpret_cast<float4*>(image)[pix] =
+                make_float4((float)((double)ts.rgb[tid][0] * sc), (float)((double)ts.rgb[tid][1] * sc),
+                            (float)((double)ts.rgb[tid][2] * sc), (float)ts.hits[tid] * inv);
+            if (AOV)
+                reinterpret_cast<float2*>(aov)[pix] =
+                    make_float2((float)((double)ts.depth[tid] * sc), (float)ts.escapes[tid] * inv);
+        }
+    }
+    __syncthreads();
 }
 
 template <class Acc, class View, bool COUNT, bool AOV>
-__global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
+__global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
                                                     const float* __restrict__ maj,
                                                     const uint32_t* __restrict__ coarse,
                                                     float* __restrict__ image,
@@ -509,22 +555,14 @@ __global__ __launch_bounds__(kBlock) void pt_kernel(View view, CameraK cam, Medi
                                                     unsigned long long* counter)
 {
     extern __shared__ uint32_t cbits[];
+    __shared__ TileShared ts;
     for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = coarse[i];
     __syncthreads();
     Acc acc{view};
     acc.reset();
-    int px, py;
-    const bool live = tile_pixel(cam.width, cam.height, g.tw, blockIdx.x, blockIdx.y, px, py);
     uint32_t nsamp = 0, ncell = 0;
-    float4 rgba;
-    float2 aovv;
-    pt_pixel(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, px, py, live, rgba, aovv, nsamp,
-             ncell);
-    if (live) {
-        const uint32_t pix = (uint32_t)py * (uint32_t)cam.width + (uint32_t)px;
-        reinterpret_cast<float4*>(image)[pix] = rgba;
-        if (AOV) reinterpret_cast<float2*>(aov)[pix] = aovv;
-    }
+    pt_tile<Acc, AOV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, blockIdx.x, blockIdx.y, ts,
+                      image, aov, nsamp, ncell);
     if (COUNT) {
         block_count(nsamp, counter);
         block_count(ncell, counter + 1);
@@ -552,12 +590,13 @@ __global__ void zero_u32(uint32_t* p)
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void pt_batch_kernel(const BatchDesc* __restrict__ descs,
+__global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __restrict__ descs,
                                                           const uint32_t* __restrict__ items,
                                                           uint32_t n_items, uint32_t* counter)
 {
     extern __shared__ uint32_t cbits[];
     __shared__ uint32_t s_item;
+    __shared__ TileShared ts;
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
@@ -573,15 +612,10 @@ __global__ __launch_bounds__(kBlock) void pt_batch_kernel(const BatchDesc* __res
         __syncthreads();
         VdbAcc acc{D->view};
         acc.reset();
-        int px, py;
-        const bool live = tile_pixel(cam.width, cam.height, g.tw, (int)(tile % (uint32_t)D->tiles_x),
-                                     (int)(tile / (uint32_t)D->tiles_x), px, py);
-        float4 rgba;
-        float2 aovv;
         uint32_t ns = 0, nc = 0;
-        pt_pixel(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits, px, py, live,
-                 rgba, aovv, ns, nc);
-        if (live) reinterpret_cast<float4*>(D->image)[(uint32_t)py * (uint32_t)cam.width + (uint32_t)px] = rgba;
+        pt_tile<VdbAcc, false>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
+                               (int)(tile % (uint32_t)D->tiles_x), (int)(tile / (uint32_t)D->tiles_x), ts,
+                               D->image, nullptr, ns, nc);
     }
 }
 
@@ -723,6 +757,7 @@ static uint64_t majorant_bytes(uint32_t C, int nx, int ny, int nz)
 static void pt_geometry(uint32_t C, int nx, int ny, int nz, PtArgs* g)
 {
     g->C = (int)C;
+    g->invC = 1.0f / (float)C;
     g->gx = (nx + g->C - 1) / g->C;
     g->gy = (ny + g->C - 1) / g->C;
     g->gz = (nz + g->C - 1) / g->C;
@@ -918,8 +953,8 @@ extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_d
     if (!r || !bytes) return fail(VDBC_E_INVALID, "null argument");
     if (d.nx == 0 || d.ny == 0 || d.nz == 0) return fail(VDBC_E_INVALID, "zero dims");
     if (r->mode == VDBC_MODE_PT) {
-        if (r->macrocell < 4 || r->macrocell > 64)
-            return fail(VDBC_E_INVALID, "macrocell must be in [4, 64]");
+        if (r->macrocell < 4 || r->macrocell > 64 || (r->macrocell & (r->macrocell - 1)))
+            return fail(VDBC_E_INVALID, "macrocell must be 4, 8, 16, 32 or 64");
         *bytes = pt_workspace(r->macrocell, (int)d.nx, (int)d.ny, (int)d.nz);
     } else {
         *bytes = (r->flags & VDBC_RENDER_COUNT) ? 256 : 0;
@@ -1020,7 +1055,8 @@ static vdbc_status batch_tuning(const vdbc_tuning* t, vdbc_tuning* out)
 {
     vdbc_tuning d{16, 8, 4, 1};
     if (t) d = *t;
-    if (d.macrocell < 4 || d.macrocell > 64) return fail(VDBC_E_INVALID, "tuning.macrocell must be in [4, 64]");
+    if (d.macrocell < 4 || d.macrocell > 64 || (d.macrocell & (d.macrocell - 1)))
+        return fail(VDBC_E_INVALID, "tuning.macrocell must be 4, 8, 16, 32 or 64");
     if (d.tile_w == 0) d.tile_w = 8;
     if (d.tile_w != 8 && d.tile_w != 16 && d.tile_w != 32 && d.tile_w != 64)
         return fail(VDBC_E_INVALID, "tuning.tile_w must be 8, 16, 32 or 64");

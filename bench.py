@@ -37,6 +37,34 @@ def relmse(x, y):
     return float(np.mean((x - y) ** 2 / (y * y + 0.01)))
 
 
+PROFILE = os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")
+KERNEL_SOURCES = ["paper_2504_04564_amd/csrc/kernels.hip", "paper_2504_04564_amd/csrc/device.h",
+                  "paper_2504_04564_amd/csrc/format.h"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the PT kernel from the committed rocprofv3
+    counter summary, or None if the kernel sources changed since."""
+    import hashlib
+    if not os.path.exists(PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    for line in open(PROFILE):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, _, v = line.partition(":")
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != h.hexdigest()[:16]:
+        return None
+    try:
+        return int(float(vals["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def time_frames(torch, r, steps, warmup):
     """Times `steps` frames (majorant + path tracer) with HIP events on the
     stream the kernels are launched on (torch's current stream)."""
@@ -249,8 +277,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
+            "traffic": measured_traffic() if (args.rate == 0.10 and n == 512 and C == 16) else None,
             "per_launch": {"samples": int(samples), "bytes_per_sample": BYTES_PER_RENDER_SAMPLE,
+                           "algorithmic_bytes": int(samples * BYTES_PER_RENDER_SAMPLE),
                            "avg_ms": round(pt_ms, 4)},
         },
         "cpu_baseline": cpu,

@@ -25,6 +25,15 @@ constexpr float kHddaEps = 1.0f / 64.0f;
 // reaches it is treated as escaping.  Only a majorant that exceeds the
 // sampled extinction by many orders of magnitude can get near it.
 constexpr uint32_t kMaxFlightSamples = 1u << 20;
+// Macrocells a flight may enter in one iteration of the path loop before it
+// yields (the walk resumes at the next iteration).  Lanes of a wave that walk
+// long stretches of thin medium then wait at most this many DDA steps for the
+// lanes that sample, instead of the whole walk.
+constexpr int kWalkCells = 2;
+// Value of flight_advance() when the flight yielded mid-walk.
+constexpr int kFlightYield = 2;
+// Resident PT workgroups per compute unit (the kernel's launch bounds).
+constexpr int kPtBlocksPerCu = 4;
 
 // ---------------------------------------------------------------- helpers
 
@@ -51,9 +60,10 @@ __device__ __forceinline__ void block_count(uint32_t n, unsigned long long* coun
     if (threadIdx.x == 0 && s) atomicAdd(counter, (unsigned long long)s);
 }
 
+// Clears the workspace's counters: sample and cell counts, PT tile queue.
 __global__ void zero_u64(unsigned long long* p)
 {
-    if (threadIdx.x < 2 && blockIdx.x == 0) p[threadIdx.x] = 0ull;
+    if (threadIdx.x < 3 && blockIdx.x == 0) p[threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------- sampling
@@ -284,8 +294,10 @@ __device__ __forceinline__ int cell_exit(const Flight& f, float edge, int cx, in
 }
 
 // Advances the flight to its next tentative collision: returns 1 with the
-// density `sv` sampled there (the caller makes the accept test), or 0 when
-// the segment leaves the grid without one.  Empty cells draw no random
+// density `sv` sampled there (the caller makes the accept test), 0 when the
+// segment leaves the grid without one, or kFlightYield after entering
+// kWalkCells macrocells without a collision (call again to continue; the
+// walk and its random draws are the same as without the pause).  Empty cells draw no random
 // numbers and coarse-block faces are macrocell faces, so the tentative
 // collisions are those of a uniform walk over every macrocell; a flight that
 // overshoots a cell restarts at its exit (memorylessness).
@@ -298,7 +310,7 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
     if (!f.ok) return 0;
     const float C = (float)g.C;
     const float CF = (float)(g.C << g.lf);
-    (void)C;
+    int walk = kWalkCells;
     for (;;) {
         if (f.incell) {
             f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
@@ -323,6 +335,7 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
                 if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
             }
         }
+        if (--walk < 0) return kFlightYield;
         const int bx = f.cx >> g.lf, by = f.cy >> g.lf, bz = f.cz >> g.lf;
         ++ncell;
         if (!coarse_occupied(cbits, g, bx, by, bz)) {
@@ -377,15 +390,6 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
     }
 }
 
-// Delta-tracking path tracer (Section 4), one thread per pixel running that
-// pixel's paths one after another.  The loop is flat: every iteration moves
-// each lane to its next tentative collision and handles whatever event the
-// lane reached (collision, escape, end of a shadow ray, start of a new path),
-// so lanes never wait for each other at bounce or sample boundaries.  The
-// arithmetic and the random draws of each path are those of a recursive
-// implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
-// stream << 16 | bounce, frame); stream 0 = jitter, free flights and the
-// scattering direction; stream 1 = the shadow ray of that bounce.
 // LDS state of one 256-pixel tile: next unit of work and per-pixel sums in
 // 2^-32 fixed point (integer sums do not depend on the order of the adds).
 struct TileShared {
@@ -462,6 +466,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
         }
         float sv = 0.0f;
         const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
+        if (tentative == kFlightYield) continue;
         const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha(m, sv);
         if (tentative && !hit) continue;    // null collision: keep tracking
         bool path_done = false, next_bounce = false;
@@ -552,7 +557,8 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
                                                     const uint32_t* __restrict__ coarse,
                                                     float* __restrict__ image,
                                                     float* __restrict__ aov,
-                                                    unsigned long long* counter)
+                                                    unsigned long long* counter,
+                                                    uint32_t* queue)
 {
     extern __shared__ uint32_t cbits[];
     __shared__ TileShared ts;
@@ -561,8 +567,19 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
     Acc acc{view};
     acc.reset();
     uint32_t nsamp = 0, ncell = 0;
-    pt_tile<Acc, AOV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, blockIdx.x, blockIdx.y, ts,
-                      image, aov, nsamp, ncell);
+    // persistent workgroups take tiles in raster order from a queue, so a
+    // workgroup that drew cheap tiles goes on to the next one at once
+    __shared__ uint32_t s_tile;
+    const uint32_t tiles_x = (uint32_t)((cam.width + 2 * g.tw - 1) / (2 * g.tw));
+    const uint32_t tiles = tiles_x * (uint32_t)((cam.height + 128 / g.tw - 1) / (128 / g.tw));
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t t = s_tile;   // pt_tile's barriers order this read before the next write
+        if (t >= tiles) break;
+        pt_tile<Acc, AOV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
+                          (int)(t / tiles_x), ts, image, aov, nsamp, ncell);
+    }
     if (COUNT) {
         block_count(nsamp, counter);
         block_count(ncell, counter + 1);
@@ -802,6 +819,21 @@ static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, 
     return launch_check("majorant");
 }
 
+// Compute units of the current device (cached per device; 256 if unknown).
+static int device_cus()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 256;
+    if (dev < 64 && cache[dev].load(std::memory_order_relaxed) > 0)
+        return cache[dev].load(std::memory_order_relaxed);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (dev < 64) cache[dev].store(cus, std::memory_order_relaxed);
+    return cus;
+}
+
 template <class Acc, class View>
 static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_medium* med,
                                const vdbc_render_params* r, float* image, float* aov, void* ws,
@@ -827,7 +859,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     if (ws && reinterpret_cast<uintptr_t>(ws) % 256)
         return fail(VDBC_E_INVALID, "workspace must be 256-byte aligned");
     dim3 grid((cam.width + kTile - 1) / kTile, (cam.height + kTile - 1) / kTile);
-    if (count) {
+    if (count && r->mode == VDBC_MODE_EA) {
         hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
         if ((s = launch_check("zero counter"))) return s;
     }
@@ -861,6 +893,8 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
         if (!std::isfinite(med->albedo) || med->albedo < 0.0f)
             return fail(VDBC_E_INVALID, "albedo must be finite and >= 0");
     }
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);   // counters and tile queue
+    if ((s = launch_check("zero counters"))) return s;
     float* maj = reinterpret_cast<float*>(static_cast<uint8_t*>(ws) + 256);
     if (!(r->flags & VDBC_RENDER_KEEP_MAJORANT)) {
         s = launch_majorant<Acc>(v, m, r->macrocell, maj, st);
@@ -883,10 +917,15 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
         if ((s = launch_check("coarse occupancy"))) return s;
     }
     const size_t lds = 4u * (size_t)g.cwords;
-    grid = dim3((cam.width + 2 * g.tw - 1) / (2 * g.tw), (cam.height + 128 / g.tw - 1) / (128 / g.tw));
+    {
+        const uint64_t tiles = (uint64_t)((cam.width + 2 * g.tw - 1) / (2 * g.tw)) *
+                               (uint64_t)((cam.height + 128 / g.tw - 1) / (128 / g.tw));
+        grid = dim3((unsigned)std::min<uint64_t>(tiles, (uint64_t)device_cus() * kPtBlocksPerCu));
+    }
+    uint32_t* queue = reinterpret_cast<uint32_t*>(counter + 2);
 #define PT_LAUNCH(CNT, AO)                                                                     \
     hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO>), grid, dim3(kBlock), lds, st, v, cam, m, \
-                       g, maj, coarse, image, aov, counter)
+                       g, maj, coarse, image, aov, counter, queue)
     if (count) {
         if (aov) PT_LAUNCH(true, true);
         else PT_LAUNCH(true, false);
@@ -1146,11 +1185,16 @@ static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
                            b->d_descs, b->d_items, b->n_items, b->d_counter);
         return launch_check("batched render");
     }
+    // one launch per volume; the launches run in stream order, so they share
+    // the tile queue, cleared before each
     for (uint32_t i = 0; i < b->n; ++i) {
         const PtArgs& g = b->gs[i];
-        hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false>), dim3(b->tiles_x[i], b->tiles_y[i]),
-                           dim3(kBlock), 4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g,
-                           b->majs[i], b->coarse[i], b->images[i], nullptr, nullptr);
+        const uint32_t tiles = (uint32_t)(b->tiles_x[i] * b->tiles_y[i]);
+        hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, b->d_counter);
+        hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false>),
+                           dim3(std::min<uint32_t>(tiles, (uint32_t)b->grid_blocks)), dim3(kBlock),
+                           4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
+                           b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter);
         if ((s = launch_check("per-volume render"))) return s;
     }
     return VDBC_OK;
@@ -1221,9 +1265,7 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
         hipMemcpyAsync(b->d_items, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(VDBC_E_DEVICE, "batch descriptor upload: %s", hipGetErrorString(hipGetLastError()));
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    b->grid_blocks = std::max(1, cus) * (int)tt.blocks_per_cu;
+    b->grid_blocks = device_cus() * (int)tt.blocks_per_cu;
     *out = b.release();
     return VDBC_OK;
 }
@@ -1248,13 +1290,13 @@ extern "C" vdbc_status vdbc_batch_capture(vdbc_batch* b, void* stream)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (s) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return s;
     }
     if (e != hipSuccess || !g) return fail(VDBC_E_DEVICE, "end capture: %s", hipGetErrorString(e));
     hipGraphExec_t ex = nullptr;
     if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return fail(VDBC_E_DEVICE, "graph instantiate failed");
     }
     b->graph = g;
@@ -1274,7 +1316,8 @@ extern "C" vdbc_status vdbc_batch_graph_launch(vdbc_batch* b, void* stream)
 extern "C" void vdbc_batch_destroy(vdbc_batch* b)
 {
     if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    // teardown: nothing useful can be done with a failure here
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     delete b;
 }

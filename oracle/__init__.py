@@ -109,6 +109,8 @@ def lib():
         L.ref_transmittance.argtypes = [C.POINTER(Field), C.POINTER(Medium), u32, P, P,
                                         u64, u64]
         L.ref_transmittance.restype = C.c_double
+        L.ref_render_iso.argtypes = [C.POINTER(Field), C.POINTER(Camera), C.c_double, C.c_double,
+                                     u32, P, P]
         L.ref_isotropic.argtypes = [C.c_double, C.c_double, P]
         L.ref_isotropic.restype = None
         _lib = L
@@ -297,6 +299,17 @@ def render_ea(fld, camera: dict, medium: dict, params: dict) -> np.ndarray:
     _check(lib().ref_render_ea(C.byref(fld.f), C.byref(c), C.byref(m), C.byref(r), _ptr(img)),
            "ref_render_ea")
     return img
+
+
+def render_iso(fld, camera: dict, iso: float, step: float, refine: int = 12, aux=False):
+    """Iso-surface normals: RGBA [h][w][4]; with aux=True also [h][w][3] =
+    (hit ray parameter or -1, lattice margin, bisection margin)."""
+    c = make_camera(camera)
+    img = np.zeros((c.height, c.width, 4), np.float64)
+    ax = np.zeros((c.height, c.width, 3), np.float64) if aux else None
+    _check(lib().ref_render_iso(C.byref(fld.f), C.byref(c), float(iso), float(step), int(refine),
+                                _ptr(img), _ptr(ax) if aux else None), "ref_render_iso")
+    return (img, ax) if aux else img
 
 
 def render_pt(fld, camera: dict, medium: dict, params: dict, pixels=None, aov=False):

@@ -131,6 +131,18 @@ int ref_render_ea(const ref_field* f, const ref_camera* c, const ref_medium* m,
 int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                   const ref_render_params* r, const uint32_t* pixels,
                   uint64_t n_pixels, double* rgba, double* aov);
+/* Implicit iso-surface ray marcher (the interval-based marcher of Section
+ * 5.4, reading R22): one ray per pixel centre, field samples at
+ * t0 + (k + 1/2) step; the first interval between consecutive samples whose
+ * sides of the iso value differ (side = f >= iso) is refined by `refine`
+ * bisection steps; the hit is the midpoint of the final interval; the normal
+ * is -grad f / |grad f| with central differences of half a voxel.
+ * image[h][w][4] = (0.5 (n + 1), 1) on a hit, 0 otherwise.  aux[h][w][3]
+ * (may be NULL) = (ray parameter of the hit or -1, min |f - iso| over the
+ * lattice samples up to the hit (all of them on a miss), min |f - iso| over
+ * the bisection midpoints (+inf if none)). */
+int ref_render_iso(const ref_field* f, const ref_camera* c, double iso, double step,
+                   uint32_t refine, double* image, double* aux);
 /* Uniform direction on the sphere from two uniforms (isotropic phase). */
 void ref_isotropic(double u1, double u2, double d[3]);
 /* Mean of `trials` binary delta-tracking transmittance estimates along one

@@ -19,8 +19,11 @@
  *    fixed bounce cap, constant ambient radiance added on escape;
  *  - random numbers: Philox4x32-10 with key (seed_lo ^ pixel, seed_hi) and
  *    counter (block, sample, stream << 16 | bounce, frame); draw d of a
- *    (sample, bounce, stream) is word d & 3 of block d >> 2; stream 0 is the
- *    path (pixel jitter, free flight, direction), stream 1 the shadow ray.
+ *    (sample, bounce, stream) is word d & 3 of block d >> 2.  Stream 0 of
+ *    bounce b is path segment b: its first two draws choose the segment's
+ *    direction (the pixel jitter for b = 0, the isotropic scattering
+ *    direction after collision b - 1 otherwise), the rest are its free
+ *    flights.  Stream 1 of bounce b is the shadow ray cast from collision b.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -232,6 +235,69 @@ int ref_render_ea(const ref_field* f, const ref_camera* c, const ref_medium* m,
     return REF_OK;
 }
 
+/* Implicit iso-surface marcher (reading R22): plain lattice march, sign
+ * test between consecutive samples, bisection, central-difference normal. */
+int ref_render_iso(const ref_field* f, const ref_camera* c, double iso, double step,
+                   uint32_t refine, double* image, double* aux)
+{
+    if (!(step > 0.0) || refine > 64) return REF_E_INVALID;
+    for (uint32_t py = 0; py < c->height; ++py)
+        for (uint32_t px = 0; px < c->width; ++px) {
+            double o[3], d[3], t0, t1;
+            camera_ray(c, px + 0.5, py + 0.5, o, d);
+            double* out = image + 4 * ((uint64_t)py * c->width + px);
+            out[0] = out[1] = out[2] = out[3] = 0.0;
+            double m_lat = INFINITY, m_mid = INFINITY, thit = -1.0;
+            if (box_clip(f, o, d, &t0, &t1)) {
+                int have = 0, prev = 0;
+                double tprev = 0.0;
+                for (uint64_t k = 0;; ++k) {
+                    double t = t0 + ((double)k + 0.5) * step;
+                    if (t >= t1) break;
+                    double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                    double v = sample_d(f, x);
+                    if (fabs(v - iso) < m_lat) m_lat = fabs(v - iso);
+                    int inside = v >= iso;
+                    if (have && inside != prev) {
+                        double lo = tprev, hi = t;
+                        for (uint32_t it = 0; it < refine; ++it) {
+                            double mid = 0.5 * (lo + hi);
+                            double y[3] = {o[0] + mid * d[0], o[1] + mid * d[1], o[2] + mid * d[2]};
+                            double w = sample_d(f, y);
+                            if (fabs(w - iso) < m_mid) m_mid = fabs(w - iso);
+                            if ((w >= iso) == prev) lo = mid;
+                            else hi = mid;
+                        }
+                        double th = 0.5 * (lo + hi);
+                        thit = th;
+                        double p[3] = {o[0] + th * d[0], o[1] + th * d[1], o[2] + th * d[2]};
+                        double g[3];
+                        for (int a = 0; a < 3; ++a) {
+                            double pp[3] = {p[0], p[1], p[2]}, pm[3] = {p[0], p[1], p[2]};
+                            pp[a] += 0.5;
+                            pm[a] -= 0.5;
+                            g[a] = sample_d(f, pp) - sample_d(f, pm);
+                        }
+                        double len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+                        for (int a = 0; a < 3; ++a) out[a] = len > 0.0 ? 0.5 * (1.0 - g[a] / len) : 0.5;
+                        out[3] = 1.0;
+                        break;
+                    }
+                    have = 1;
+                    prev = inside;
+                    tprev = t;
+                }
+            }
+            if (aux) {
+                double* x = aux + 3 * ((uint64_t)py * c->width + px);
+                x[0] = thit;
+                x[1] = m_lat;
+                x[2] = m_mid;
+            }
+        }
+    return REF_OK;
+}
+
 /* Isotropic phase function sampling: uniform direction on the unit sphere
  * from two uniforms (z = 1 - 2u, phi = 2 pi u'). */
 void ref_isotropic(double u1, double u2, double d[3])
@@ -364,14 +430,17 @@ int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
         uint32_t px = pix % c->width, py = pix / c->width;
         double acc[3] = {0, 0, 0}, opac = 0.0, depth = 0.0, trans = 0.0;
         for (uint32_t s = 0; s < r->spp; ++s) {
-            rng_t path;
-            rng_init(&path, r->seed, pix, s, 0, 0, r->frame);
-            double jx = rng_next(&path), jy = rng_next(&path);
             double o[3], d[3];
-            camera_ray(c, (double)px + jx, (double)py + jy, o, d);
             double L[3] = {0, 0, 0}, beta[3] = {1, 1, 1};
             for (uint32_t b = 0; b < r->max_bounces; ++b) {
-                if (b > 0) rng_init(&path, r->seed, pix, s, b, 0, r->frame);
+                /* segment b: its direction, then its free flight */
+                rng_t path;
+                rng_init(&path, r->seed, pix, s, b, 0, r->frame);
+                double u1 = rng_next(&path), u2 = rng_next(&path);
+                if (b == 0)
+                    camera_ray(c, (double)px + u1, (double)py + u2, o, d);
+                else
+                    ref_isotropic(u1, u2, d);   /* o = previous collision */
                 double t0, t1, th = 0.0;
                 int hit = box_clip(f, o, d, &t0, &t1) &&
                           free_flight(&tk, o, d, t0, t1, &path, &th);
@@ -401,12 +470,9 @@ int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                     for (int ch = 0; ch < 3; ++ch)
                         L[ch] += beta[ch] * inv4pi * (double)m->light_E[ch];
                 if (b + 1 == r->max_bounces) break;
-                double u1 = rng_next(&path);
-                double u2 = rng_next(&path);
                 o[0] = x[0];
                 o[1] = x[1];
                 o[2] = x[2];
-                ref_isotropic(u1, u2, d);
             }
             for (int ch = 0; ch < 3; ++ch) acc[ch] += L[ch];
         }

@@ -189,3 +189,75 @@ def batch(args, torch, vdbc, synth, scenes, log):
             "ms_graph_replay": round(ms_graph, 3),
             "mrays_per_volume_launches": round(rays / ms_per / 1e3, 2),
             "images_bit_identical": bool(same), "tuning_candidates": allr}
+
+
+def quality(args, torch, vdbc, synth, scenes, log):
+    """Compression error against the dense original (Section 5.2): MSE and
+    PSNR of the 512^3 cloud at rates 10 %..100 % for the three similarity
+    metrics (tab:stats and fig:distance on the synthetic stand-in)."""
+    n = args.size
+    vol = synth.mid_volume(n=n)
+    dense = torch.from_numpy(vol).cuda()
+    names = {1: "closest", 2: "farthest", 3: "median"}
+    rows = []
+    for metric in (1, 2, 3):
+        for q in [round(0.1 * k, 1) for k in range(1, 11)]:
+            buf, st = vdbc.encode(vol, q, metric=metric)
+            g = vdbc.Grid(buf)
+            ms = _median_ms(torch, lambda: vdbc.compare_dense(g, dense), 3)
+            c = vdbc.compare_dense(g, dense)
+            rec = {"metric": names[metric], "rate": q, "mse": c["mse"], "psnr": c["psnr"],
+                   "max_abs": c["max_abs"], "differing_voxels": c["differing"],
+                   "vdb_bytes": int(buf.size), "achieved_rate": round(st["achieved_rate"], 5),
+                   "compare_ms": round(ms, 3)}
+            log(f"[quality] {rec}")
+            rows.append(rec)
+            del g
+    lossless = {names[m]: min([r["rate"] for r in rows if r["metric"] == names[m] and r["differing_voxels"] == 0],
+                              default=None) for m in (1, 2, 3)}
+    return {"metric": "MSE / PSNR of the compressed cloud vs the dense original", "unit": "dB",
+            "value": [r for r in rows if r["metric"] == "farthest" and r["rate"] == 0.1][0]["psnr"],
+            "config": {"workload": f"fbm-cloud-{n}^3-rates-0.1..1.0-metrics-f1f2f3",
+                       "psnr_peak": "max - min of the dense volume"},
+            "lowest_lossless_rate": lossless, "rows": rows}
+
+
+def worstcase(args, torch, vdbc, synth, scenes, log):
+    """Lossless encoding of truly dense noise, 32^3 up to --worst-max^3
+    (tab:worstcase): bytes of the VDB and of the dense array, path-traced
+    frame rate of both on the same GPU, and whether the images agree
+    bitwise (they must at 1:1)."""
+    rows = []
+    W = H = 1024
+    spp, bounces = 4, 8
+    med = scenes.pt_medium(64.0)
+    n = 32
+    while n <= args.worst_max:
+        t = time.time()
+        vol = synth.dense_noise(n, seed=n)
+        buf, st = vdbc.encode(vol, 1.0)
+        enc = time.time() - t
+        g = vdbc.Grid(buf)
+        dense = torch.from_numpy(vol).cuda()
+        del vol
+        cam = scenes.orbit_camera((n, n, n), W, H)
+        prm = dict(spp=spp, max_bounces=bounces, seed=0x5EED, macrocell=args.macrocell)
+        rv = vdbc.Renderer(g, cam, med, prm, vdbc.MODE_PT)
+        rd = vdbc.Renderer(dense, cam, med, prm, vdbc.MODE_PT, background=g.background)
+        ms_v = _median_ms(torch, rv.launch, 3)
+        ms_d = _median_ms(torch, rd.launch, 3)
+        same = bool(torch.equal(rv.image.view(torch.int32), rd.image.view(torch.int32)))
+        rec = {"n": n, "dense_bytes": n ** 3 * 4, "vdb_bytes": int(buf.size),
+               "overhead": round(buf.size / (n ** 3 * 4) - 1.0, 5), "encode_s": round(enc, 2),
+               "vdb_fps": round(1e3 / ms_v, 2), "dense_fps": round(1e3 / ms_d, 2),
+               "vdb_over_dense": round(ms_d / ms_v, 4), "images_bitwise_equal": same}
+        log(f"[worstcase] {rec}")
+        rows.append(rec)
+        del rv, rd, g, dense, buf
+        torch.cuda.empty_cache()
+        n *= 2
+    return {"metric": "worst case: lossless dense noise, VDB vs dense bytes and frame rate",
+            "unit": "fps", "value": rows[-1]["vdb_fps"],
+            "config": {"workload": f"dense-noise-32^3..{args.worst_max}^3-1to1-pt-{W}x{H}x{spp}spp-{bounces}bounces",
+                       "macrocell": args.macrocell},
+            "rows": rows}

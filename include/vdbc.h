@@ -146,6 +146,18 @@ vdbc_status vdbc_sample_dense(const float* dense, vdbc_dims d, float background,
 vdbc_status vdbc_lookup(const vdbc_grid* g, const int32_t* ijk, uint64_t n, float* out,
                         void* stream);
 
+/* Compression error of the grid against the dense volume it approximates
+ * (the MSE / PSNR evaluation of Section 5.2, tab:stats): dense = device
+ * float32 of the grid's dims, x-fastest.  out = device double[5] =
+ *   {sum over voxels of (vdb - dense)^2, max |vdb - dense|,
+ *    voxels whose float32 bits differ, min of dense, max of dense},
+ * so MSE = out[0] / voxels and a lossless grid has out[2] == 0.  ws: device
+ * scratch of vdbc_compare_workspace() bytes, 8-byte aligned.  Deterministic
+ * for a given size. */
+vdbc_status vdbc_compare_workspace(vdbc_dims d, uint64_t* bytes);
+vdbc_status vdbc_compare_dense(const vdbc_grid* g, const float* dense, double* out, void* ws,
+                               uint64_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Rendering (Section 4)                                                     */
 /* ------------------------------------------------------------------------ */
@@ -172,10 +184,10 @@ typedef struct {
     float ambient[3];       /* constant ambient radiance added on escape */
 } vdbc_medium;
 
-enum { VDBC_MODE_EA = 0u, VDBC_MODE_PT = 1u };
+enum { VDBC_MODE_EA = 0u, VDBC_MODE_PT = 1u, VDBC_MODE_ISO = 2u };
 enum {
-    VDBC_RENDER_HDDA = 1u,        /* EA: skip lattice samples inside empty tree nodes
-                                     (result-preserving; needs alpha_TF(B) == 0) */
+    VDBC_RENDER_HDDA = 1u,        /* EA, ISO: skip lattice samples inside empty tree
+                                     nodes (result-preserving; EA needs alpha_TF(B) == 0) */
     VDBC_RENDER_COUNT = 2u,       /* count trilinear samples into the workspace */
     VDBC_RENDER_KEEP_MAJORANT = 4u /* PT: reuse the majorant grid already in ws */
 };
@@ -192,7 +204,8 @@ typedef struct {
     uint32_t frame;         /* PT counter word 3 */
     uint32_t tile_w;        /* PT pixels per wave row: 8 (default; 0 = 8), 16, 32, 64;
                                the image does not depend on it */
-    uint32_t reserved[2];
+    float iso;              /* ISO: iso value */
+    uint32_t refine;        /* ISO: bisection steps on the crossing interval (<= 64) */
 } vdbc_render_params;
 
 /* Workspace layout (caller-owned device memory, 256-B aligned):
@@ -205,7 +218,15 @@ vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d, uint
 
 /* image: device float32 [height][width][4] (RGB radiance + opacity).  aov:
  * NULL or device float32 [height][width][2] = (first-scatter depth fraction,
- * primary transmittance), path tracer only.  The path tracer rebuilds the
+ * primary transmittance) for the path tracer, (hit ray parameter or -1, 0)
+ * for ISO.
+ * ISO (the interval-based implicit iso-surface marcher of Section 5.4): one
+ * ray per pixel centre, field samples at t0 + (k + 1/2) step; the first pair
+ * of consecutive samples on opposite sides of `iso` (side: f >= iso) is
+ * refined by `refine` bisection steps, the hit is the midpoint of the final
+ * interval and the pixel is (0.5 (n + 1), 1) with n = -grad f / |grad f|
+ * from central differences of half a voxel; (0, 0, 0, 0) on a miss.  The
+ * medium is not used (may be NULL).  The path tracer rebuilds the
  * majorant grid in ws first unless VDBC_RENDER_KEEP_MAJORANT. */
 vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
                         const vdbc_render_params* r, float* image, float* aov, void* ws,

@@ -94,6 +94,75 @@ __global__ __launch_bounds__(kBlock) void lookup_kernel(VdbView view, const int3
     out[i] = acc.voxel(x, y, z);
 }
 
+// ---------------------------------------------------------------- quality
+
+// Error statistics of the compressed grid against the dense volume it was
+// encoded from (the MSE / PSNR evaluation of Section 5.2).  Workgroups of
+// 512 threads take 8^3 voxel regions (one leaf each) in a grid-stride loop,
+// so every thread reads the same leaf as its workgroup and the dense rows in
+// 32-byte runs.  Per workgroup: {sum of squared differences, max |diff|,
+// differing voxels, min dense, max dense} into part[5 * block]; a second
+// kernel folds the partials in a fixed order (deterministic for a given
+// size).
+constexpr int kCmpThreads = 512;
+constexpr int kCmpBlocks = 4096;
+
+__global__ __launch_bounds__(kCmpThreads) void compare_kernel(VdbView view, const float* __restrict__ dense,
+                                                              double* __restrict__ part)
+{
+    VdbAcc acc{view};
+    acc.reset();
+    const int t = threadIdx.x;
+    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
+    const uint64_t rx = (uint64_t)(view.nx + 7) / 8, ry = (uint64_t)(view.ny + 7) / 8,
+                   rz = (uint64_t)(view.nz + 7) / 8;
+    double sse = 0.0, mx = 0.0, nd = 0.0, lo = INFINITY, hi = -INFINITY;
+    for (uint64_t r = blockIdx.x; r < rx * ry * rz; r += gridDim.x) {
+        const int x = (int)(r % rx) * 8 + lx, y = (int)((r / rx) % ry) * 8 + ly, z = (int)(r / (rx * ry)) * 8 + lz;
+        if (x >= view.nx || y >= view.ny || z >= view.nz) continue;
+        const float dv = dense[(uint64_t)x + (uint64_t)view.nx * ((uint64_t)y + (uint64_t)view.ny * (uint64_t)z)];
+        const float vv = acc.voxel(x, y, z);
+        const double e = (double)vv - (double)dv;
+        sse = fma(e, e, sse);
+        mx = fmax(mx, fabs(e));
+        nd += (__float_as_uint(vv) != __float_as_uint(dv)) ? 1.0 : 0.0;
+        lo = fmin(lo, (double)dv);
+        hi = fmax(hi, (double)dv);
+    }
+    __shared__ double red[5][kCmpThreads];
+    red[0][t] = sse;
+    red[1][t] = mx;
+    red[2][t] = nd;
+    red[3][t] = lo;
+    red[4][t] = hi;
+    __syncthreads();
+    for (int h = kCmpThreads / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] = fmax(red[1][t], red[1][t + h]);
+            red[2][t] += red[2][t + h];
+            red[3][t] = fmin(red[3][t], red[3][t + h]);
+            red[4][t] = fmax(red[4][t], red[4][t + h]);
+        }
+        __syncthreads();
+    }
+    if (t < 5) part[5 * blockIdx.x + t] = red[t][0];
+}
+
+__global__ __launch_bounds__(64) void compare_fold_kernel(const double* __restrict__ part, int blocks,
+                                                          double* __restrict__ out)
+{
+    // one lane per statistic, partials in block order
+    const int t = threadIdx.x;
+    if (t >= 5) return;
+    double a = (t == 3) ? INFINITY : (t == 4) ? -INFINITY : 0.0;
+    for (int b = 0; b < blocks; ++b) {
+        const double v = part[5 * b + t];
+        a = (t == 0 || t == 2) ? a + v : (t == 3) ? fmin(a, v) : fmax(a, v);
+    }
+    out[t] = a;
+}
+
 // ---------------------------------------------------------------- majorant
 
 template <class Acc, class View>
@@ -183,6 +252,107 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
         }
         float4* img = reinterpret_cast<float4*>(image);
         img[(uint64_t)py * cam.width + px] = make_float4(c0, c1, c2, 1.0f - T);
+    }
+    if (COUNT) block_count(nsamp, counter);
+}
+
+// ---------------------------------------------------------------- ISO
+
+// Implicit iso-surface marcher (the interval-based marcher of Section 5.4):
+// the EA lattice t0 + (k + 1/2) step, the first pair of consecutive samples
+// on opposite sides of the iso value (side: f >= iso), `refine` bisection
+// steps on that interval, normal -grad f / |grad f| by central differences
+// of half a voxel.  With HDDA, lattice samples whose trilinear footprint lies
+// inside an empty node read B at every corner, so they take B's side without
+// a field read; the crossing, the bisection and the image are unchanged.
+template <class Acc, class View, bool HDDA, bool COUNT>
+__global__ __launch_bounds__(kBlock) void iso_kernel(View view, CameraK cam, float iso, float step,
+                                                     int refine, float* __restrict__ image,
+                                                     float* __restrict__ aov,
+                                                     unsigned long long* counter)
+{
+    Acc acc{view};
+    acc.reset();
+    int px, py;
+    const bool live = tile_pixel(cam.width, cam.height, 8, blockIdx.x, blockIdx.y, px, py);
+    uint32_t nsamp = 0;
+    if (live) {
+        float o[3], d[3], t0, t1;
+        camera_ray(cam, (float)px + 0.5f, (float)py + 0.5f, o, d);
+        float4 out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float thit = -1.0f;
+        const float id[3] = {1.0f / d[0], 1.0f / d[1], 1.0f / d[2]};
+        if (box_clip(view.nx, view.ny, view.nz, o, d, id, t0, t1)) {
+            const bool bg_side = acc.background() >= iso;
+            bool have = false, prev = false;
+            float tprev = 0.0f;
+            for (int k = 0;; ++k) {
+                const float t = fmaf((float)k + 0.5f, step, t0);
+                if (t >= t1) break;
+                const float x = fmaf(t, d[0], o[0]), y = fmaf(t, d[1], o[1]), z = fmaf(t, d[2], o[2]);
+                bool side;
+                int last = k;   // last lattice sample of this step
+                bool skip = false;
+                if (HDDA) {
+                    const int i = (int)floorf(fmaxf(x, -2.0f)), j = (int)floorf(fmaxf(y, -2.0f)),
+                              kk = (int)floorf(fmaxf(z, -2.0f));
+                    const int L = acc.empty_level(i, j, kk);
+                    if (L) {
+                        const int mask = (1 << L) - 1;
+                        if ((i & mask) != mask && (j & mask) != mask && (kk & mask) != mask) {
+                            const int lo[3] = {i & ~mask, j & ~mask, kk & ~mask};
+                            float te = INFINITY;
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                if (d[a] > 0.0f)
+                                    te = fminf(te, ((float)(lo[a] + mask) - kHddaEps - o[a]) / d[a]);
+                                else if (d[a] < 0.0f)
+                                    te = fminf(te, ((float)lo[a] + kHddaEps - o[a]) / d[a]);
+                            }
+                            const int kn = (int)floorf(fminf((te - t0) / step - 0.5f, 2.0e9f));
+                            last = (kn > k + 1 ? kn : k + 1) - 1;
+                            skip = true;
+                        }
+                    }
+                }
+                if (skip) {
+                    side = bg_side;
+                } else {
+                    side = trilinear(acc, x, y, z) >= iso;
+                    if (COUNT) ++nsamp;
+                }
+                if (have && side != prev) {
+                    float lo = tprev, hi = t;
+                    for (int it = 0; it < refine; ++it) {
+                        const float mid = 0.5f * (lo + hi);
+                        const float w = trilinear(acc, fmaf(mid, d[0], o[0]), fmaf(mid, d[1], o[1]),
+                                                  fmaf(mid, d[2], o[2]));
+                        if (COUNT) ++nsamp;
+                        if ((w >= iso) == prev) lo = mid;
+                        else hi = mid;
+                    }
+                    thit = 0.5f * (lo + hi);
+                    const float p[3] = {fmaf(thit, d[0], o[0]), fmaf(thit, d[1], o[1]),
+                                        fmaf(thit, d[2], o[2])};
+                    const float gx = trilinear(acc, p[0] + 0.5f, p[1], p[2]) - trilinear(acc, p[0] - 0.5f, p[1], p[2]);
+                    const float gy = trilinear(acc, p[0], p[1] + 0.5f, p[2]) - trilinear(acc, p[0], p[1] - 0.5f, p[2]);
+                    const float gz = trilinear(acc, p[0], p[1], p[2] + 0.5f) - trilinear(acc, p[0], p[1], p[2] - 0.5f);
+                    if (COUNT) nsamp += 6;
+                    const float len = sqrtf(gx * gx + gy * gy + gz * gz);
+                    out = len > 0.0f ? make_float4(0.5f * (1.0f - gx / len), 0.5f * (1.0f - gy / len),
+                                                   0.5f * (1.0f - gz / len), 1.0f)
+                                     : make_float4(0.5f, 0.5f, 0.5f, 1.0f);
+                    break;
+                }
+                have = true;
+                prev = side;
+                tprev = last == k ? t : fmaf((float)last + 0.5f, step, t0);
+                k = last;
+            }
+        }
+        const uint64_t pix = (uint64_t)py * cam.width + px;
+        reinterpret_cast<float4*>(image)[pix] = out;
+        if (aov) reinterpret_cast<float2*>(aov)[pix] = make_float2(thit, 0.0f);
     }
     if (COUNT) block_count(nsamp, counter);
 }
@@ -294,18 +464,21 @@ __device__ __forceinline__ int cell_exit(const Flight& f, float edge, int cx, in
 }
 
 // Advances the flight to its next tentative collision: returns 1 with the
-// density `sv` sampled there (the caller makes the accept test), 0 when the
-// segment leaves the grid without one, or kFlightYield after entering
-// kWalkCells macrocells without a collision (call again to continue; the
-// walk and its random draws are the same as without the pause).  Empty cells draw no random
+// density `sv` sampled there (the caller makes the accept test with one more
+// draw), 0 when the segment leaves the grid without one, or kFlightYield
+// after entering kWalkCells macrocells, or when a free-flight draw would
+// leave fewer than one of the `held` random numbers for the accept test
+// (call again to continue; the walk and its draws are the same as without
+// the pause).  Empty cells draw no random
 // numbers and coarse-block faces are macrocell faces, so the tentative
 // collisions are those of a uniform walk over every macrocell; a flight that
 // overshoots a cell restarts at its exit (memorylessness).
 template <class Acc>
 __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK& m,
                                               const float* __restrict__ maj,
-                                              const uint32_t* cbits, const PtArgs& g, Rng& rng,
-                                              float& sv, uint32_t& nsamp, uint32_t& ncell)
+                                              const uint32_t* cbits, const PtArgs& g,
+                                              PathRng& rng, uint32_t held, float& sv,
+                                              uint32_t& nsamp, uint32_t& ncell)
 {
     if (!f.ok) return 0;
     const float C = (float)g.C;
@@ -313,6 +486,8 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
     int walk = kWalkCells;
     for (;;) {
         if (f.incell) {
+            if (held < 2u) return kFlightYield;
+            --held;
             f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
             if (f.t < f.te) {
                 if (--f.budget == 0) return 0;
@@ -405,14 +580,28 @@ __device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v 
 // tile's 256 x spp paths (unit u = sample u / 256 of tile pixel u % 256) are
 // shared by the workgroup: every lane starts on one unit and takes the next
 // one from an LDS counter when its path ends, so lanes on empty pixels or on
-// short paths keep working.  Within a path the loop is flat: every iteration
-// moves the lane to its next tentative collision and handles whatever event
-// it reached (collision, escape, end of a shadow ray, start of a new path).
-// The arithmetic and the random draws of each path are those of a recursive
-// implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
-// stream << 16 | bounce, frame); stream 0 = jitter, free flights and the
-// scattering direction; stream 1 = the shadow ray of that bounce.  Results
-// depend only on the pixel, not on the lane, tile shape or launch.
+// short paths keep working.  Within a path the loop is flat and each kind of
+// work has one place in it: refill the random stream (the only Philox call),
+// start a ray segment (the only ray set-up: camera ray, scattered ray or
+// shadow ray), advance the flight to its next tentative collision, handle the
+// event it reached.  Lanes of a wave in different states then share one pass
+// over each part instead of one pass per call site.
+// Random numbers: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
+// stream << 16 | bounce, frame).  Stream 0 of bounce b is path segment b: two
+// draws for its direction (pixel jitter for b = 0, isotropic scattering
+// otherwise), then its free flights and accept tests; stream 1 of bounce b is
+// the shadow ray from collision b.  Results depend only on the pixel, not on
+// the lane, tile shape or launch.
+// Pixel of work unit u in the tile at (x0, y0): wave w of the tile covers a
+// tw x th block, the four waves a 2 x 2 arrangement of blocks.
+__device__ __forceinline__ void unit_pixel(uint32_t u, int x0, int y0, int tw, int th, int& px, int& py)
+{
+    const int q = (int)(u & (kBlock - 1));
+    const int w = q >> 6, l = q & 63;
+    px = x0 + (w & 1) * tw + (l % tw);
+    py = y0 + (w >> 1) * th + (l / tw);
+}
+
 template <class Acc, bool AOV>
 __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
                                         const MediumK& m, const PtArgs& g,
@@ -431,64 +620,84 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
     const uint32_t total = (uint32_t)kBlock * (uint32_t)g.spp;
     const float inv4pi = 0.0795774715459476679f;
     uint32_t u = (uint32_t)tid;
-    int q = 0, px = 0, py = 0;
-    uint32_t k0 = 0, smp = 0;
     float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
     float t0p = 0.0f, pdepth = 1.0f;
     bool phit = false;
     int b = 0;
-    bool shadow = false, fresh = true;
-    uint32_t path_d = 0;
-    Rng rng;
+    bool shadow = false, fresh = true, begin = false;
+    PathRng rng;
     Flight f;
-    while (u < total) {
+    f.o[0] = f.o[1] = f.o[2] = 0.0f;
+    for (;;) {
         if (fresh) {
-            q = (int)(u & (kBlock - 1));
-            smp = u >> 8;
-            const int w = q >> 6, l = q & 63;
-            px = x0 + (w & 1) * tw + (l % tw);
-            py = y0 + (w >> 1) * th + (l / tw);
-            if (px >= cam.width || py >= cam.height) {   // no pixel here
+            // next unit of the tile that has a pixel
+            int px = 0, py = 0;
+            for (;;) {
+                if (u >= total) break;
+                unit_pixel(u, x0, y0, tw, th, px, py);
+                if (px < cam.width && py < cam.height) break;
                 u = atomicAdd(&ts.next, 1u);
-                continue;
             }
+            if (u >= total) break;
             fresh = false;
-            k0 = g.seed_lo ^ ((uint32_t)py * (uint32_t)cam.width + (uint32_t)px);
-            rng.init(k0, g.seed_hi, smp, 0u, 0u, g.frame);
-            const float jx = rng.next(), jy = rng.next();
-            float o[3], d[3];
-            camera_ray(cam, (float)px + jx, (float)py + jy, o, d);
+            rng.start(g.seed_lo ^ ((uint32_t)py * (uint32_t)cam.width + (uint32_t)px));
             b = 0;
             shadow = false;
+            begin = true;
             L0 = L1 = L2 = 0.0f;
             b0 = b1 = b2 = 1.0f;
-            flight_begin(f, g, nx, ny, nz, o, d, t0p);
+        }
+        rng.refill(g.seed_hi, u >> 8, ((shadow ? 1u : 0u) << 16) | (uint32_t)b, g.frame);
+        if (begin) {
+            // start a segment from f.o (the last collision) or the camera
+            begin = false;
+            float o[3] = {f.o[0], f.o[1], f.o[2]}, d[3] = {m.light[0], m.light[1], m.light[2]};
+            if (!shadow) {
+                const float u1 = rng.next(), u2 = rng.next();
+                if (b == 0) {
+                    int px, py;
+                    unit_pixel(u, x0, y0, tw, th, px, py);
+                    camera_ray(cam, (float)px + u1, (float)py + u2, o, d);
+                } else {
+                    const float z = 1.0f - 2.0f * u1;
+                    const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+                    const float phi = 6.28318530717958647692f * u2;
+                    d[0] = r * __cosf(phi);
+                    d[1] = r * __sinf(phi);
+                    d[2] = z;
+                }
+            }
+            float t0;
+            flight_begin(f, g, nx, ny, nz, o, d, t0);
+            if (!shadow && b == 0) t0p = t0;
         }
         float sv = 0.0f;
-        const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
+        const int tentative =
+            flight_advance(f, acc, m, maj, cbits, g, rng, rng.held(), sv, nsamp, ncell);
         if (tentative == kFlightYield) continue;
         const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha(m, sv);
         if (tentative && !hit) continue;    // null collision: keep tracking
-        bool path_done = false, next_bounce = false;
+        bool path_done = false;
         if (!shadow) {
             if (b == 0) {
                 phit = hit;
                 pdepth = hit ? (f.t - t0p) / (f.t1 - t0p) : 1.0f;
             }
             if (hit) {
-                // real collision: weight by albedo and colour, then the
-                // shadow ray towards the light from the collision point
+                // real collision: weight by albedo and colour; the shadow ray
+                // towards the light starts here next
                 const float4 c = tf_eval(m, sv);
                 b0 *= m.albedo * c.x;
                 b1 *= m.albedo * c.y;
                 b2 *= m.albedo * c.z;
                 const float x[3] = {fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
                                     fmaf(f.t, f.d[2], f.o[2])};
-                path_d = rng.d;
-                rng.init(k0, g.seed_hi, smp, (uint32_t)b, 1u, g.frame);
-                float t0s;
-                flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
+                f.o[0] = x[0];
+                f.o[1] = x[1];
+                f.o[2] = x[2];
+                rng.start(rng.key0);
                 shadow = true;
+                begin = true;
             } else {
                 L0 = fmaf(b0, m.ambient[0], L0);
                 L1 = fmaf(b1, m.ambient[1], L1);
@@ -502,26 +711,18 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                 L2 = fmaf(b2 * inv4pi, m.light_E[2], L2);
             }
             shadow = false;
-            if (b + 1 == g.max_bounces) path_done = true;
-            else next_bounce = true;
-        }
-        if (next_bounce) {
-            // isotropic scattering from the collision point (the shadow ray's
-            // origin), drawn from the path stream of this bounce
-            rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
-            rng.seek(path_d);
-            const float u1 = rng.next(), u2 = rng.next();
-            const float z = 1.0f - 2.0f * u1;
-            const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-            const float phi = 6.28318530717958647692f * u2;
-            const float o[3] = {f.o[0], f.o[1], f.o[2]};
-            const float d[3] = {r * __cosf(phi), r * __sinf(phi), z};
-            ++b;
-            rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
-            float t0n;
-            flight_begin(f, g, nx, ny, nz, o, d, t0n);
+            if (b + 1 == g.max_bounces) {
+                path_done = true;
+            } else {
+                // scatter: the next segment starts at the collision (the
+                // shadow ray's origin, still in f.o)
+                ++b;
+                rng.start(rng.key0);
+                begin = true;
+            }
         }
         if (path_done) {
+            const uint32_t q = u & (kBlock - 1);
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][0]), (unsigned long long)to_fixed(L0));
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][1]), (unsigned long long)to_fixed(L1));
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][2]), (unsigned long long)to_fixed(L2));
@@ -844,9 +1045,11 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     MediumK m;
     vdbc_status s = make_camera(c, &cam);
     if (s) return s;
-    s = make_medium(med, v.nx, v.ny, v.nz, &m);
-    if (s) return s;
-    if (r->mode > 1) return fail(VDBC_E_INVALID, "mode must be EA (0) or PT (1)");
+    if (r->mode > 2) return fail(VDBC_E_INVALID, "mode must be EA (0), PT (1) or ISO (2)");
+    if (r->mode != VDBC_MODE_ISO) {
+        s = make_medium(med, v.nx, v.ny, v.nz, &m);
+        if (s) return s;
+    }
     const bool count = (r->flags & VDBC_RENDER_COUNT) != 0;
     hipStream_t st = static_cast<hipStream_t>(stream);
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(ws);
@@ -859,6 +1062,32 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     if (ws && reinterpret_cast<uintptr_t>(ws) % 256)
         return fail(VDBC_E_INVALID, "workspace must be 256-byte aligned");
     dim3 grid((cam.width + kTile - 1) / kTile, (cam.height + kTile - 1) / kTile);
+    if (r->mode == VDBC_MODE_ISO) {
+        if (!(r->step > 0.0f) || !std::isfinite(r->step))
+            return fail(VDBC_E_INVALID, "ISO step must be finite and > 0");
+        const double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
+        if (diag / r->step > 16777216.0)
+            return fail(VDBC_E_INVALID, "ISO step too small for this volume (> 2^24 samples per ray)");
+        if (!std::isfinite(r->iso)) return fail(VDBC_E_INVALID, "iso value must be finite");
+        if (r->refine > 64) return fail(VDBC_E_INVALID, "refine must be <= 64");
+        if (count) {
+            hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
+            if ((s = launch_check("zero counter"))) return s;
+        }
+        const bool hdda = (r->flags & VDBC_RENDER_HDDA) != 0;
+#define ISO_LAUNCH(H, CNT)                                                                      \
+    hipLaunchKernelGGL((iso_kernel<Acc, View, H, CNT>), grid, dim3(kBlock), 0, st, v, cam, r->iso, \
+                       r->step, (int)r->refine, image, aov, counter)
+        if (hdda) {
+            if (count) ISO_LAUNCH(true, true);
+            else ISO_LAUNCH(true, false);
+        } else {
+            if (count) ISO_LAUNCH(false, true);
+            else ISO_LAUNCH(false, false);
+        }
+#undef ISO_LAUNCH
+        return launch_check("iso render");
+    }
     if (count && r->mode == VDBC_MODE_EA) {
         hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
         if ((s = launch_check("zero counter"))) return s;
@@ -984,6 +1213,42 @@ extern "C" vdbc_status vdbc_lookup(const vdbc_grid* g, const int32_t* ijk, uint6
     hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                        static_cast<hipStream_t>(stream), v, ijk, n, out);
     return launch_check("vdbc_lookup");
+}
+
+static uint32_t compare_blocks(const VdbView& v)
+{
+    const uint64_t regions = (uint64_t)((v.nx + 7) / 8) * (uint64_t)((v.ny + 7) / 8) * (uint64_t)((v.nz + 7) / 8);
+    return (uint32_t)std::min<uint64_t>(regions, kCmpBlocks);
+}
+
+extern "C" vdbc_status vdbc_compare_workspace(vdbc_dims d, uint64_t* bytes)
+{
+    clear_error();
+    if (!bytes) return fail(VDBC_E_INVALID, "null argument");
+    if (d.nx == 0 || d.ny == 0 || d.nz == 0) return fail(VDBC_E_INVALID, "zero dims");
+    const uint64_t regions = (uint64_t)((d.nx + 7) / 8) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
+    *bytes = 5ull * 8ull * std::min<uint64_t>(regions, kCmpBlocks);
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_compare_dense(const vdbc_grid* g, const float* dense, double* out, void* ws,
+                                          uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    VdbView v;
+    vdbc_status s = make_view(g, &v);
+    if (s) return s;
+    if (!dense || !out) return fail(VDBC_E_INVALID, "null dense volume or output");
+    const uint32_t blocks = compare_blocks(v);
+    if (!ws || ws_bytes < 40ull * blocks)
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace needs %llu bytes", 40ull * blocks);
+    if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(VDBC_E_INVALID, "workspace must be 8-byte aligned");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* part = static_cast<double*>(ws);
+    hipLaunchKernelGGL(compare_kernel, dim3(blocks), dim3(kCmpThreads), 0, st, v, dense, part);
+    if ((s = launch_check("compare"))) return s;
+    hipLaunchKernelGGL(compare_fold_kernel, dim3(1), dim3(64), 0, st, part, (int)blocks, out);
+    return launch_check("compare fold");
 }
 
 extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d,

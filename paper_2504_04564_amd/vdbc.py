@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libvdbc.so")
 
 OK, E_INVALID, E_NOMEM, E_BUFFER_TOO_SMALL, E_FORMAT, E_DEVICE, E_UNSUPPORTED = range(7)
 BG_EXPLICIT, NO_CORNERS, NO_PRUNE = 1, 2, 4
-MODE_EA, MODE_PT = 0, 1
+MODE_EA, MODE_PT, MODE_ISO = 0, 1, 2
 RENDER_HDDA, RENDER_COUNT, RENDER_KEEP_MAJORANT = 1, 2, 4
 
 
@@ -66,7 +66,7 @@ class RenderParamsC(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("spp", C.c_uint32), ("max_bounces", C.c_uint32),
                 ("macrocell", C.c_uint32), ("flags", C.c_uint32), ("step", C.c_float),
                 ("t_terminate", C.c_float), ("seed", C.c_uint64), ("frame", C.c_uint32),
-                ("tile_w", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("tile_w", C.c_uint32), ("iso", C.c_float), ("refine", C.c_uint32)]
 
 
 SYMBOLS = [
@@ -108,6 +108,8 @@ def load():
     L.vdbc_sample.argtypes = [C.POINTER(GridC), P, u64, u32, P, P]
     L.vdbc_sample_dense.argtypes = [P, Dims, f32, P, u64, u32, P, P]
     L.vdbc_lookup.argtypes = [C.POINTER(GridC), P, u64, P, P]
+    L.vdbc_compare_workspace.argtypes = [Dims, C.POINTER(u64)]
+    L.vdbc_compare_dense.argtypes = [C.POINTER(GridC), P, P, P, u64, P]
     L.vdbc_render_workspace.argtypes = [C.POINTER(RenderParamsC), Dims, C.POINTER(u64)]
     L.vdbc_render.argtypes = [C.POINTER(GridC), C.POINTER(CameraC), C.POINTER(MediumC),
                               C.POINTER(RenderParamsC), P, P, P, u64, P]
@@ -233,6 +235,27 @@ def lookup(grid: Grid, ijk, out=None):
     return out
 
 
+def compare_dense(grid: Grid, dense) -> dict:
+    """vdbc_compare_dense: error statistics of `grid` against the dense
+    float32 device volume [nz][ny][nx] (MSE, max error, differing voxels,
+    value range and PSNR over that range)."""
+    torch = _torch()
+    d = dense.contiguous()
+    dims = _dims_of(tuple(d.shape))
+    need = C.c_uint64(0)
+    _check(load().vdbc_compare_workspace(dims, C.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device=d.device)
+    out = torch.empty(5, dtype=torch.float64, device=d.device)
+    _check(load().vdbc_compare_dense(C.byref(grid.c), _dptr(d), _dptr(out), _dptr(ws), need.value,
+                                     _stream()))
+    sse, mx, nd, lo, hi = out.cpu().tolist()
+    n = d.numel()
+    mse = sse / n
+    rng = hi - lo
+    psnr = float("inf") if mse == 0 else (10.0 * np.log10(rng * rng / mse) if rng > 0 else float("-inf"))
+    return dict(sse=sse, mse=mse, max_abs=mx, differing=int(nd), min=lo, max=hi, psnr=psnr)
+
+
 def camera_c(cam: dict) -> CameraC:
     c = CameraC()
     c.kind = cam["kind"]
@@ -269,6 +292,8 @@ def params_c(p: dict, mode: int) -> RenderParamsC:
     r.seed = p.get("seed", 0)
     r.frame = p.get("frame", 0)
     r.tile_w = p.get("tile_w", 8)
+    r.iso = p.get("iso", 0.5)
+    r.refine = p.get("refine", 12)
     return r
 
 
@@ -286,7 +311,8 @@ class Renderer:
         else:
             nx, ny, nz = field.dims
             self.dims = Dims(nx, ny, nz)
-        self.cam, self.med = camera_c(camera), medium_c(medium)
+        # the iso-surface mode reads no medium
+        self.cam, self.med = camera_c(camera), (medium_c(medium) if medium else MediumC())
         self.prm = params_c(params, mode)
         ws = C.c_uint64(0)
         _check(load().vdbc_render_workspace(C.byref(self.prm), self.dims, C.byref(ws)))

@@ -183,11 +183,13 @@ def paper_volume(seed: int = 3, dims=(1987, 1351, 2449), active: float = 0.25,
     return out
 
 
-def dense_noise(n: int, seed: int = 11) -> np.ndarray:
+def dense_noise(n, seed: int = 11) -> np.ndarray:
     """Truly dense white noise in [0, 1): no brick is background-like (the
-    adversarial case of the paper's worst-case table)."""
+    adversarial case of the paper's worst-case table).  ``n`` is the cube
+    edge or a shape (nz, ny, nx)."""
     rng = np.random.default_rng(seed)
-    return rng.random((n, n, n), dtype=np.float32)
+    shape = (n, n, n) if isinstance(n, (int, np.integer)) else tuple(int(x) for x in n)
+    return rng.random(shape, dtype=np.float32)
 
 
 def batch_sizes(count: int = 64, seed: int = 7, lo: int = 32, hi: int = 768):

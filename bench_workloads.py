@@ -261,3 +261,31 @@ def worstcase(args, torch, vdbc, synth, scenes, log):
             "config": {"workload": f"dense-noise-32^3..{args.worst_max}^3-1to1-pt-{W}x{H}x{spp}spp-{bounces}bounces",
                        "macrocell": args.macrocell},
             "rows": rows}
+
+
+def iso(args, torch, vdbc, synth, scenes, log):
+    """Iso-surface marcher at iso 0.5 (Section 5.4) on the 512^3 cloud at
+    1:10 and on the dense array: frame time and samples/s, with and without
+    empty-node skipping (VDB only), 1024x1024, step 0.5, 12 bisection steps."""
+    n = args.size
+    vol = synth.mid_volume(n=n)
+    buf, st = vdbc.encode(vol, args.rate)
+    g = vdbc.Grid(buf)
+    dense = torch.from_numpy(vol).cuda()
+    W = H = 1024
+    cam = scenes.orbit_camera((n, n, n), W, H)
+    base = dict(step=0.5, iso=0.5, refine=12)
+    rows = {}
+    for name, field, flags, bg in (("vdb", g, 0, None), ("vdb_hdda", g, vdbc.RENDER_HDDA, None),
+                                   ("dense", dense, 0, 0.0)):
+        r = vdbc.Renderer(field, cam, None, dict(base, flags=flags | vdbc.RENDER_COUNT),
+                          vdbc.MODE_ISO, background=bg)
+        ms = _median_ms(torch, r.launch, 5)
+        rows[name] = {"ms": round(ms, 3), "fps": round(1e3 / ms, 2),
+                      "samples_per_s": round(r.sample_count() / ms * 1e3, 1),
+                      "hits": int((r.image[..., 3] == 1.0).sum().item())}
+        log(f"[iso] {name}: {rows[name]}")
+    return {"metric": "iso-surface frames/s, VDB (1:10) vs dense", "unit": "fps",
+            "value": rows["vdb_hdda"]["fps"],
+            "config": {"workload": f"fbm-cloud-{n}^3-1to10-iso0.5-{W}x{H}-step0.5-refine12"},
+            "vdb_over_dense": round(rows["dense"]["ms"] / rows["vdb_hdda"]["ms"], 4), "rows": rows}

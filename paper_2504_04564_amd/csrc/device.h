@@ -34,54 +34,34 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
 
 // One random stream of a path: key (seed_lo ^ pixel, seed_hi), counter
 // (block, sample, stream << 16 | bounce, frame); draw d is word d & 3 of
-// block d >> 2; u = (x >> 8) * 2^-24.  The stream is read ahead by up to
-// two blocks (even blocks in a, odd blocks in b): the path loop calls
-// refill() once per iteration, the only place Philox runs, and after it at
-// least four draws are held.
-struct PathRng {
-    uint32_t key0;
-    uint32_t d;      // next draw
-    uint32_t nblk;   // blocks generated so far; blocks [d >> 2, nblk) are held
-    uint32_t a0, a1, a2, a3, b0, b1, b2, b3;
+// block d >> 2; u = (x >> 8) * 2^-24.
+struct Rng {
+    uint32_t k0, k1, sample, tag, frame;
+    uint32_t d;
+    uint32_t w0, w1, w2, w3;
 
-    // A new stream; its sample and stream/bounce words are passed to refill().
-    __device__ __forceinline__ void start(uint32_t k0)
+    __device__ void init(uint32_t key0, uint32_t key1, uint32_t s, uint32_t bounce,
+                         uint32_t stream, uint32_t f)
     {
-        key0 = k0;
+        k0 = key0;
+        k1 = key1;
+        sample = s;
+        tag = (stream << 16) | bounce;
+        frame = f;
         d = 0;
-        nblk = 0;
     }
-    // Draws held (>= 4 after refill()).
-    __device__ __forceinline__ uint32_t held() const { return 4u * nblk - d; }
-    // Generates the next block of stream (sample, tag = stream << 16 | bounce)
-    // if fewer than two are held.
-    __device__ __forceinline__ void refill(uint32_t key1, uint32_t sample, uint32_t tag, uint32_t frame)
-    {
-        if (nblk - (d >> 2) < 2u) {
-            uint32_t w0 = nblk, w1 = sample, w2 = tag, w3 = frame;
-            philox4x32_10(w0, w1, w2, w3, key0, key1);
-            if (nblk & 1u) {
-                b0 = w0;
-                b1 = w1;
-                b2 = w2;
-                b3 = w3;
-            } else {
-                a0 = w0;
-                a1 = w1;
-                a2 = w2;
-                a3 = w3;
-            }
-            ++nblk;
-        }
-    }
-    // The next draw; the caller keeps within held().
     __device__ __forceinline__ float next()
     {
         const uint32_t q = d & 3u;
-        const bool odd = (d >> 2) & 1u;
-        const uint32_t x0 = odd ? b0 : a0, x1 = odd ? b1 : a1, x2 = odd ? b2 : a2, x3 = odd ? b3 : a3;
-        const uint32_t x = q == 0 ? x0 : q == 1 ? x1 : q == 2 ? x2 : x3;
+        if (q == 0) {
+            w0 = d >> 2;
+            w1 = sample;
+            w2 = tag;
+            w3 = frame;
+            philox4x32_10(w0, w1, w2, w3, k0, k1);
+        }
         ++d;
+        const uint32_t x = q == 0 ? w0 : q == 1 ? w1 : q == 2 ? w2 : w3;
         return (float)(x >> 8) * (1.0f / 16777216.0f);
     }
 };

@@ -464,21 +464,18 @@ __device__ __forceinline__ int cell_exit(const Flight& f, float edge, int cx, in
 }
 
 // Advances the flight to its next tentative collision: returns 1 with the
-// density `sv` sampled there (the caller makes the accept test with one more
-// draw), 0 when the segment leaves the grid without one, or kFlightYield
-// after entering kWalkCells macrocells, or when a free-flight draw would
-// leave fewer than one of the `held` random numbers for the accept test
-// (call again to continue; the walk and its draws are the same as without
-// the pause).  Empty cells draw no random
+// density `sv` sampled there (the caller makes the accept test), 0 when the
+// segment leaves the grid without one, or kFlightYield after entering
+// kWalkCells macrocells without a collision (call again to continue; the
+// walk and its random draws are the same as without the pause).  Empty cells draw no random
 // numbers and coarse-block faces are macrocell faces, so the tentative
 // collisions are those of a uniform walk over every macrocell; a flight that
 // overshoots a cell restarts at its exit (memorylessness).
 template <class Acc>
 __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK& m,
                                               const float* __restrict__ maj,
-                                              const uint32_t* cbits, const PtArgs& g,
-                                              PathRng& rng, uint32_t held, float& sv,
-                                              uint32_t& nsamp, uint32_t& ncell)
+                                              const uint32_t* cbits, const PtArgs& g, Rng& rng,
+                                              float& sv, uint32_t& nsamp, uint32_t& ncell)
 {
     if (!f.ok) return 0;
     const float C = (float)g.C;
@@ -486,8 +483,6 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
     int walk = kWalkCells;
     for (;;) {
         if (f.incell) {
-            if (held < 2u) return kFlightYield;
-            --held;
             f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
             if (f.t < f.te) {
                 if (--f.budget == 0) return 0;
@@ -580,28 +575,16 @@ __device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v 
 // tile's 256 x spp paths (unit u = sample u / 256 of tile pixel u % 256) are
 // shared by the workgroup: every lane starts on one unit and takes the next
 // one from an LDS counter when its path ends, so lanes on empty pixels or on
-// short paths keep working.  Within a path the loop is flat and each kind of
-// work has one place in it: refill the random stream (the only Philox call),
-// start a ray segment (the only ray set-up: camera ray, scattered ray or
-// shadow ray), advance the flight to its next tentative collision, handle the
-// event it reached.  Lanes of a wave in different states then share one pass
-// over each part instead of one pass per call site.
-// Random numbers: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
-// stream << 16 | bounce, frame).  Stream 0 of bounce b is path segment b: two
-// draws for its direction (pixel jitter for b = 0, isotropic scattering
+// short paths keep working.  Within a path the loop is flat: every iteration
+// moves the lane to its next tentative collision and handles whatever event
+// it reached (collision, escape, end of a shadow ray, start of a new path).
+// The arithmetic and the random draws of each path are those of a recursive
+// implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
+// stream << 16 | bounce, frame).  Stream 0 of bounce b is path segment b:
+// two draws for its direction (pixel jitter for b = 0, isotropic scattering
 // otherwise), then its free flights and accept tests; stream 1 of bounce b is
 // the shadow ray from collision b.  Results depend only on the pixel, not on
 // the lane, tile shape or launch.
-// Pixel of work unit u in the tile at (x0, y0): wave w of the tile covers a
-// tw x th block, the four waves a 2 x 2 arrangement of blocks.
-__device__ __forceinline__ void unit_pixel(uint32_t u, int x0, int y0, int tw, int th, int& px, int& py)
-{
-    const int q = (int)(u & (kBlock - 1));
-    const int w = q >> 6, l = q & 63;
-    px = x0 + (w & 1) * tw + (l % tw);
-    py = y0 + (w >> 1) * th + (l / tw);
-}
-
 template <class Acc, bool AOV>
 __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
                                         const MediumK& m, const PtArgs& g,
@@ -620,84 +603,62 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
     const uint32_t total = (uint32_t)kBlock * (uint32_t)g.spp;
     const float inv4pi = 0.0795774715459476679f;
     uint32_t u = (uint32_t)tid;
+    int q = 0, px = 0, py = 0;
+    uint32_t k0 = 0, smp = 0;
     float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
     float t0p = 0.0f, pdepth = 1.0f;
     bool phit = false;
     int b = 0;
-    bool shadow = false, fresh = true, begin = false;
-    PathRng rng;
+    bool shadow = false, fresh = true;
+    Rng rng;
     Flight f;
-    f.o[0] = f.o[1] = f.o[2] = 0.0f;
-    for (;;) {
+    while (u < total) {
         if (fresh) {
-            // next unit of the tile that has a pixel
-            int px = 0, py = 0;
-            for (;;) {
-                if (u >= total) break;
-                unit_pixel(u, x0, y0, tw, th, px, py);
-                if (px < cam.width && py < cam.height) break;
+            q = (int)(u & (kBlock - 1));
+            smp = u >> 8;
+            const int w = q >> 6, l = q & 63;
+            px = x0 + (w & 1) * tw + (l % tw);
+            py = y0 + (w >> 1) * th + (l / tw);
+            if (px >= cam.width || py >= cam.height) {   // no pixel here
                 u = atomicAdd(&ts.next, 1u);
+                continue;
             }
-            if (u >= total) break;
             fresh = false;
-            rng.start(g.seed_lo ^ ((uint32_t)py * (uint32_t)cam.width + (uint32_t)px));
+            k0 = g.seed_lo ^ ((uint32_t)py * (uint32_t)cam.width + (uint32_t)px);
+            rng.init(k0, g.seed_hi, smp, 0u, 0u, g.frame);
+            const float jx = rng.next(), jy = rng.next();
+            float o[3], d[3];
+            camera_ray(cam, (float)px + jx, (float)py + jy, o, d);
             b = 0;
             shadow = false;
-            begin = true;
             L0 = L1 = L2 = 0.0f;
             b0 = b1 = b2 = 1.0f;
-        }
-        rng.refill(g.seed_hi, u >> 8, ((shadow ? 1u : 0u) << 16) | (uint32_t)b, g.frame);
-        if (begin) {
-            // start a segment from f.o (the last collision) or the camera
-            begin = false;
-            float o[3] = {f.o[0], f.o[1], f.o[2]}, d[3] = {m.light[0], m.light[1], m.light[2]};
-            if (!shadow) {
-                const float u1 = rng.next(), u2 = rng.next();
-                if (b == 0) {
-                    int px, py;
-                    unit_pixel(u, x0, y0, tw, th, px, py);
-                    camera_ray(cam, (float)px + u1, (float)py + u2, o, d);
-                } else {
-                    const float z = 1.0f - 2.0f * u1;
-                    const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-                    const float phi = 6.28318530717958647692f * u2;
-                    d[0] = r * __cosf(phi);
-                    d[1] = r * __sinf(phi);
-                    d[2] = z;
-                }
-            }
-            float t0;
-            flight_begin(f, g, nx, ny, nz, o, d, t0);
-            if (!shadow && b == 0) t0p = t0;
+            flight_begin(f, g, nx, ny, nz, o, d, t0p);
         }
         float sv = 0.0f;
-        const int tentative =
-            flight_advance(f, acc, m, maj, cbits, g, rng, rng.held(), sv, nsamp, ncell);
+        const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
         if (tentative == kFlightYield) continue;
         const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha(m, sv);
         if (tentative && !hit) continue;    // null collision: keep tracking
-        bool path_done = false;
+        bool path_done = false, next_bounce = false;
         if (!shadow) {
             if (b == 0) {
                 phit = hit;
                 pdepth = hit ? (f.t - t0p) / (f.t1 - t0p) : 1.0f;
             }
             if (hit) {
-                // real collision: weight by albedo and colour; the shadow ray
-                // towards the light starts here next
+                // real collision: weight by albedo and colour, then the
+                // shadow ray towards the light from the collision point
                 const float4 c = tf_eval(m, sv);
                 b0 *= m.albedo * c.x;
                 b1 *= m.albedo * c.y;
                 b2 *= m.albedo * c.z;
                 const float x[3] = {fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
                                     fmaf(f.t, f.d[2], f.o[2])};
-                f.o[0] = x[0];
-                f.o[1] = x[1];
-                f.o[2] = x[2];
-                rng.start(rng.key0);
+                rng.init(k0, g.seed_hi, smp, (uint32_t)b, 1u, g.frame);
+                float t0s;
+                flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
                 shadow = true;
-                begin = true;
             } else {
                 L0 = fmaf(b0, m.ambient[0], L0);
                 L1 = fmaf(b1, m.ambient[1], L1);
@@ -711,18 +672,24 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                 L2 = fmaf(b2 * inv4pi, m.light_E[2], L2);
             }
             shadow = false;
-            if (b + 1 == g.max_bounces) {
-                path_done = true;
-            } else {
-                // scatter: the next segment starts at the collision (the
-                // shadow ray's origin, still in f.o)
-                ++b;
-                rng.start(rng.key0);
-                begin = true;
-            }
+            if (b + 1 == g.max_bounces) path_done = true;
+            else next_bounce = true;
+        }
+        if (next_bounce) {
+            // segment b + 1: isotropic scattering from the collision point
+            // (the shadow ray's origin) with the first two draws of its stream
+            ++b;
+            rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
+            const float u1 = rng.next(), u2 = rng.next();
+            const float z = 1.0f - 2.0f * u1;
+            const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+            const float phi = 6.28318530717958647692f * u2;
+            const float o[3] = {f.o[0], f.o[1], f.o[2]};
+            const float d[3] = {r * __cosf(phi), r * __sinf(phi), z};
+            float t0n;
+            flight_begin(f, g, nx, ny, nz, o, d, t0n);
         }
         if (path_done) {
-            const uint32_t q = u & (kBlock - 1);
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][0]), (unsigned long long)to_fixed(L0));
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][1]), (unsigned long long)to_fixed(L1));
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][2]), (unsigned long long)to_fixed(L2));

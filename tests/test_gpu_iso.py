@@ -45,7 +45,7 @@ def _check(img, aov, want, aux, step, refine):
     assert np.all(img[~hit_g] == 0.0) and np.all(aov[..., 0][~hit_g] == -1.0)
 
 
-@pytest.mark.parametrize("shape,q,iso", [((48, 40, 56), 0.25, 0.5), ((33, 47, 29), 0.10, 0.3),
+@pytest.mark.parametrize("shape,q,iso", [((48, 40, 56), 0.25, 0.5), ((33, 47, 29), 0.5, 0.3),
                                          ((64, 64, 64), 1.0, 0.5)])
 def test_iso_vdb_vs_oracle(shape, q, iso):
     v = synth.cloud_volume(shape, seed=7 + shape[0])

@@ -122,11 +122,11 @@ def main():
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--train-steps", type=int, default=1500, help="denoiser workload: Adam steps")
     ap.add_argument("--workload", default="mid",
-                    choices=("mid", "paper", "denoiser", "batch", "quality", "worstcase", "iso"),
+                    choices=("mid", "paper", "denoiser", "batch", "quality", "worstcase", "iso", "ea"),
                     help="mid: the headline 512^3 frame; paper: 1987x1351x2449 rate sweep; "
                          "denoiser: train and evaluate the learned denoiser; batch: 64 volumes; "
                          "quality: MSE/PSNR vs rate and metric; worstcase: lossless dense noise; "
-                         "iso: iso-surface marcher")
+                         "iso: iso-surface marcher; ea: emission-absorption marcher")
     ap.add_argument("--worst-max", type=int, default=1024,
                     help="worstcase workload: largest noise cube edge (2048 = the paper's 34 GB)")
     args = ap.parse_args()

@@ -222,6 +222,13 @@ struct VdbAcc {
     // log2 edge of the largest empty aligned node region (no child, no tile)
     // holding voxel (i,j,k): 12 (no upper node), 7 (empty lower slot),
     // 3 (empty leaf slot), 0 (a leaf or tile is there, or i,j,k < 0).
+    // True when voxel (i,j,k) lies in the cached leaf and that leaf stores
+    // voxels: the sample is then not inside an empty node (no query needed).
+    __device__ __forceinline__ bool in_stored_leaf(int i, int j, int k) const
+    {
+        return (i >> 3) == clx && (j >> 3) == cly && (k >> 3) == clz && cleaf.m != 0u;
+    }
+
     __device__ int empty_level(int i, int j, int k)
     {
         if ((i | j | k) < 0) return 0;
@@ -281,6 +288,7 @@ struct DenseAcc {
         c[6] = (ix0 & iy1 & iz1) ? d[x0 + y1 + z1] : B;
         c[7] = (ix1 & iy1 & iz1) ? d[x1 + y1 + z1] : B;
     }
+    __device__ bool in_stored_leaf(int, int, int) const { return true; }
     __device__ int empty_level(int, int, int) { return 0; }
 };
 

@@ -97,13 +97,14 @@ __global__ __launch_bounds__(kBlock) void lookup_kernel(VdbView view, const int3
 // ---------------------------------------------------------------- quality
 
 // Error statistics of the compressed grid against the dense volume it was
-// encoded from (the MSE / PSNR evaluation of Section 5.2).  Workgroups of
-// 512 threads take 8^3 voxel regions (one leaf each) in a grid-stride loop,
-// so every thread reads the same leaf as its workgroup and the dense rows in
-// 32-byte runs.  Per workgroup: {sum of squared differences, max |diff|,
-// differing voxels, min dense, max dense} into part[5 * block]; a second
-// kernel folds the partials in a fixed order (deterministic for a given
-// size).
+// encoded from (the MSE / PSNR evaluation of Section 5.2).  A workgroup of
+// 512 threads takes a 64 x 8 x 8 voxel region (eight leaves along x) in a
+// grid-stride loop: thread (x, y) walks the region's 8 slices, so each wave
+// reads 256 contiguous bytes of a dense row per slice and every thread stays
+// in one leaf (one descent, then its leaf cache).  Per workgroup: {sum of
+// squared differences, max |diff|, differing voxels, min dense, max dense}
+// into part[5 * block]; a second kernel folds the partials in a fixed order
+// (deterministic for a given size).
 constexpr int kCmpThreads = 512;
 constexpr int kCmpBlocks = 4096;
 
@@ -113,21 +114,25 @@ __global__ __launch_bounds__(kCmpThreads) void compare_kernel(VdbView view, cons
     VdbAcc acc{view};
     acc.reset();
     const int t = threadIdx.x;
-    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const uint64_t rx = (uint64_t)(view.nx + 7) / 8, ry = (uint64_t)(view.ny + 7) / 8,
+    const int lx = t & 63, ly = t >> 6;
+    const uint64_t rx = (uint64_t)(view.nx + 63) / 64, ry = (uint64_t)(view.ny + 7) / 8,
                    rz = (uint64_t)(view.nz + 7) / 8;
     double sse = 0.0, mx = 0.0, nd = 0.0, lo = INFINITY, hi = -INFINITY;
     for (uint64_t r = blockIdx.x; r < rx * ry * rz; r += gridDim.x) {
-        const int x = (int)(r % rx) * 8 + lx, y = (int)((r / rx) % ry) * 8 + ly, z = (int)(r / (rx * ry)) * 8 + lz;
-        if (x >= view.nx || y >= view.ny || z >= view.nz) continue;
-        const float dv = dense[(uint64_t)x + (uint64_t)view.nx * ((uint64_t)y + (uint64_t)view.ny * (uint64_t)z)];
-        const float vv = acc.voxel(x, y, z);
-        const double e = (double)vv - (double)dv;
-        sse = fma(e, e, sse);
-        mx = fmax(mx, fabs(e));
-        nd += (__float_as_uint(vv) != __float_as_uint(dv)) ? 1.0 : 0.0;
-        lo = fmin(lo, (double)dv);
-        hi = fmax(hi, (double)dv);
+        const int x = (int)(r % rx) * 64 + lx, y = (int)((r / rx) % ry) * 8 + ly;
+        const int z0 = (int)(r / (rx * ry)) * 8;
+        if (x >= view.nx || y >= view.ny) continue;
+        for (int z = z0; z < z0 + 8 && z < view.nz; ++z) {
+            const float dv =
+                dense[(uint64_t)x + (uint64_t)view.nx * ((uint64_t)y + (uint64_t)view.ny * (uint64_t)z)];
+            const float vv = acc.voxel(x, y, z);
+            const double e = (double)vv - (double)dv;
+            sse = fma(e, e, sse);
+            mx = fmax(mx, fabs(e));
+            nd += (__float_as_uint(vv) != __float_as_uint(dv)) ? 1.0 : 0.0;
+            lo = fmin(lo, (double)dv);
+            hi = fmax(hi, (double)dv);
+        }
     }
     __shared__ double red[5][kCmpThreads];
     red[0][t] = sse;
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void ea_kernel(View view, CameraK cam, Medi
                 if (HDDA) {
                     const int i = (int)floorf(fmaxf(x, -2.0f)), j = (int)floorf(fmaxf(y, -2.0f)),
                               kk = (int)floorf(fmaxf(z, -2.0f));
-                    const int L = acc.empty_level(i, j, kk);
+                    const int L = acc.in_stored_leaf(i, j, kk) ? 0 : acc.empty_level(i, j, kk);
                     if (L) {
                         const int mask = (1 << L) - 1;
                         if ((i & mask) != mask && (j & mask) != mask && (kk & mask) != mask) {
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void iso_kernel(View view, CameraK cam, flo
                 if (HDDA) {
                     const int i = (int)floorf(fmaxf(x, -2.0f)), j = (int)floorf(fmaxf(y, -2.0f)),
                               kk = (int)floorf(fmaxf(z, -2.0f));
-                    const int L = acc.empty_level(i, j, kk);
+                    const int L = acc.in_stored_leaf(i, j, kk) ? 0 : acc.empty_level(i, j, kk);
                     if (L) {
                         const int mask = (1 << L) - 1;
                         if ((i & mask) != mask && (j & mask) != mask && (kk & mask) != mask) {
@@ -322,22 +327,42 @@ __global__ __launch_bounds__(kBlock) void iso_kernel(View view, CameraK cam, flo
                     if (COUNT) ++nsamp;
                 }
                 if (have && side != prev) {
-                    float lo = tprev, hi = t;
-                    for (int it = 0; it < refine; ++it) {
-                        const float mid = 0.5f * (lo + hi);
-                        const float w = trilinear(acc, fmaf(mid, d[0], o[0]), fmaf(mid, d[1], o[1]),
-                                                  fmaf(mid, d[2], o[2]));
+                    // `refine` bisection steps, then the six central-difference
+                    // samples of the normal, through one field evaluation
+                    float lo = tprev, hi = t, mid = 0.0f;
+                    float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+                    for (int it = 0; it < refine + 6; ++it) {
+                        float q0, q1, q2;
+                        const int e = it - refine;   // >= 0: gradient sample e
+                        if (e < 0) {
+                            mid = 0.5f * (lo + hi);
+                            q0 = fmaf(mid, d[0], o[0]);
+                            q1 = fmaf(mid, d[1], o[1]);
+                            q2 = fmaf(mid, d[2], o[2]);
+                        } else {
+                            if (e == 0) {
+                                thit = 0.5f * (lo + hi);
+                                p0 = fmaf(thit, d[0], o[0]);
+                                p1 = fmaf(thit, d[1], o[1]);
+                                p2 = fmaf(thit, d[2], o[2]);
+                            }
+                            const float sh = (e & 1) ? -0.5f : 0.5f;
+                            q0 = p0 + ((e >> 1) == 0 ? sh : 0.0f);
+                            q1 = p1 + ((e >> 1) == 1 ? sh : 0.0f);
+                            q2 = p2 + ((e >> 1) == 2 ? sh : 0.0f);
+                        }
+                        const float w = trilinear(acc, q0, q1, q2);
                         if (COUNT) ++nsamp;
-                        if ((w >= iso) == prev) lo = mid;
-                        else hi = mid;
+                        if (e < 0) {
+                            if ((w >= iso) == prev) lo = mid;
+                            else hi = mid;
+                        } else {
+                            const float sw = (e & 1) ? -w : w;
+                            if ((e >> 1) == 0) gx += sw;
+                            else if ((e >> 1) == 1) gy += sw;
+                            else gz += sw;
+                        }
                     }
-                    thit = 0.5f * (lo + hi);
-                    const float p[3] = {fmaf(thit, d[0], o[0]), fmaf(thit, d[1], o[1]),
-                                        fmaf(thit, d[2], o[2])};
-                    const float gx = trilinear(acc, p[0] + 0.5f, p[1], p[2]) - trilinear(acc, p[0] - 0.5f, p[1], p[2]);
-                    const float gy = trilinear(acc, p[0], p[1] + 0.5f, p[2]) - trilinear(acc, p[0], p[1] - 0.5f, p[2]);
-                    const float gz = trilinear(acc, p[0], p[1], p[2] + 0.5f) - trilinear(acc, p[0], p[1], p[2] - 0.5f);
-                    if (COUNT) nsamp += 6;
                     const float len = sqrtf(gx * gx + gy * gy + gz * gz);
                     out = len > 0.0f ? make_float4(0.5f * (1.0f - gx / len), 0.5f * (1.0f - gy / len),
                                                    0.5f * (1.0f - gz / len), 1.0f)
@@ -1182,9 +1207,14 @@ extern "C" vdbc_status vdbc_lookup(const vdbc_grid* g, const int32_t* ijk, uint6
     return launch_check("vdbc_lookup");
 }
 
+static uint64_t compare_regions(uint64_t nx, uint64_t ny, uint64_t nz)
+{
+    return ((nx + 63) / 64) * ((ny + 7) / 8) * ((nz + 7) / 8);
+}
+
 static uint32_t compare_blocks(const VdbView& v)
 {
-    const uint64_t regions = (uint64_t)((v.nx + 7) / 8) * (uint64_t)((v.ny + 7) / 8) * (uint64_t)((v.nz + 7) / 8);
+    const uint64_t regions = compare_regions((uint64_t)v.nx, (uint64_t)v.ny, (uint64_t)v.nz);
     return (uint32_t)std::min<uint64_t>(regions, kCmpBlocks);
 }
 
@@ -1193,7 +1223,7 @@ extern "C" vdbc_status vdbc_compare_workspace(vdbc_dims d, uint64_t* bytes)
     clear_error();
     if (!bytes) return fail(VDBC_E_INVALID, "null argument");
     if (d.nx == 0 || d.ny == 0 || d.nz == 0) return fail(VDBC_E_INVALID, "zero dims");
-    const uint64_t regions = (uint64_t)((d.nx + 7) / 8) * ((d.ny + 7) / 8) * ((d.nz + 7) / 8);
+    const uint64_t regions = compare_regions(d.nx, d.ny, d.nz);
     *bytes = 5ull * 8ull * std::min<uint64_t>(regions, kCmpBlocks);
     return VDBC_OK;
 }

@@ -66,7 +66,8 @@ class Medium(C.Structure):
 class Params(C.Structure):
     _fields_ = [("spp", C.c_uint32), ("max_bounces", C.c_uint32),
                 ("macrocell", C.c_uint32), ("step", C.c_float),
-                ("t_terminate", C.c_float), ("seed", C.c_uint64), ("frame", C.c_uint32)]
+                ("t_terminate", C.c_float), ("seed", C.c_uint64), ("frame", C.c_uint32),
+                ("rr", C.c_uint32)]
 
 
 _lib = None
@@ -281,6 +282,7 @@ def make_params(p: dict) -> Params:
     r.t_terminate = p.get("t_terminate", 0.0)
     r.seed = p.get("seed", 0)
     r.frame = p.get("frame", 0)
+    r.rr = 1 if p.get("rr", False) else 0
     return r
 
 

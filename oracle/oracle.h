@@ -117,6 +117,7 @@ typedef struct {
     float t_terminate;        /* EA early termination threshold, 0 = off */
     uint64_t seed;
     uint32_t frame;
+    uint32_t rr;              /* path tracer: Russian roulette (reading R24) */
 } ref_render_params;
 
 /* Majorant grid (Section 4, macrocells): per cell the extinction max over the

@@ -24,6 +24,10 @@
  *    direction (the pixel jitter for b = 0, the isotropic scattering
  *    direction after collision b - 1 otherwise), the rest are its free
  *    flights.  Stream 1 of bounce b is the shadow ray cast from collision b.
+ *  - Russian roulette (optional, reading R24): a segment b >= 1 then opens
+ *    with one more draw u; from b = 2 on the path survives with probability
+ *    q = min(1, max(beta)) (u < q) and its throughput is divided by q; the
+ *    direction takes the next two draws.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -436,6 +440,17 @@ int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                 /* segment b: its direction, then its free flight */
                 rng_t path;
                 rng_init(&path, r->seed, pix, s, b, 0, r->frame);
+                if (r->rr && b > 0) {
+                    double u = rng_next(&path);
+                    double q = 1.0;
+                    if (b >= 2) {
+                        q = beta[0] > beta[1] ? beta[0] : beta[1];
+                        q = beta[2] > q ? beta[2] : q;
+                        q = q < 1.0 ? q : 1.0;
+                    }
+                    if (!(u < q)) break;
+                    for (int ch = 0; ch < 3; ++ch) beta[ch] /= q;
+                }
                 double u1 = rng_next(&path), u2 = rng_next(&path);
                 if (b == 0)
                     camera_ray(c, (double)px + u1, (double)py + u2, o, d);

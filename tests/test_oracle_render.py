@@ -344,3 +344,41 @@ def test_pt_deterministic_per_pixel():
     full = oracle.render_pt(f, cam, med, prm)
     sub = oracle.render_pt(f, cam, med, prm, pixels=np.array([119, 5, 60], np.uint32))
     assert np.array_equal(sub, full[[119, 5, 60]])
+
+
+def test_pt_russian_roulette_is_unbiased():
+    # a thick white medium lit only by ambient: deep paths carry most of the
+    # radiance, so roulette from bounce 2 on (survival max(beta), survivors
+    # divided by it) must keep the mean of the plain estimator; dropping the
+    # division or the survival test moves it by far more than the noise
+    n, sigma_scale, albedo, amb, bounces = 16, 96.0, 0.8, 1.0, 48
+    f = _homog(n)
+    med = dict(sigma_scale=sigma_scale, albedo=albedo, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(amb, amb, amb))
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    spp = 256
+    runs = [oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=bounces, seed=s, rr=True))[:, 0]
+            for s in (11, 12)]
+    Lo = 0.5 * (runs[0] + runs[1])
+    se_o = math.sqrt(np.var(runs[0] - runs[1]) / 4 / len(Lo))
+    Ln = _numpy_homog_pt(n, sigma_scale / n, albedo, 0.0, (0.0, 1.0, 0.0), amb, bounces, 600_000, 12)
+    se = math.sqrt(se_o ** 2 + Ln.var() / len(Ln))
+    assert abs(Lo.mean() - Ln.mean()) < 4 * se, (Lo.mean(), Ln.mean(), se)
+    # the roulette changes the draws: the image differs from the plain one
+    plain = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=bounces, seed=11))[:, 0]
+    assert not np.array_equal(plain, runs[0])
+    # deep paths matter here: cutting them at 2 bounces loses far more than the noise
+    S = _numpy_homog_pt(n, sigma_scale / n, albedo, 0.0, (0.0, 1.0, 0.0), amb, 2, 300_000, 13)
+    assert Ln.mean() - S.mean() > 20 * se
+
+
+def test_pt_russian_roulette_white_furnace_never_kills():
+    # albedo 1 and a white medium keep beta = 1, so the survival probability
+    # is 1 and every path still returns exactly the ambient radiance
+    n = 16
+    f = _homog(n)
+    med = dict(sigma_scale=40.0, albedo=1.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(0.25, 0.5, 1.0))
+    cam = scenes.orbit_camera((n, n, n), 8, 8)
+    rgba = oracle.render_pt(f, cam, med, dict(spp=8, max_bounces=10_000, seed=4, rr=True))
+    np.testing.assert_allclose(rgba[:, :3], np.tile([0.25, 0.5, 1.0], (64, 1)), rtol=1e-12)

@@ -82,13 +82,19 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
     reference."""
     from paper_2504_04564_amd import denoiser as dz
     rng = np.random.default_rng(1000)
-    n_vol, views, size = 16, 6, 256
-    spp_in, spp_tgt = 4, 512
+    if args.denoiser_full:
+        # the full recipe: 2,000 crops of 512^2 from 256^3..512^3 clouds, 1024-spp targets
+        n_vol, views, size, spp_tgt, lo, hi = 200, 10, 512, 1024, 256, 512
+    else:
+        n_vol, views, size, spp_tgt, lo, hi = 16, 6, 256, 512, 128, 256
+    spp_in = 4
     med = scenes.pt_medium(64.0)
     xs, ts = [], []
     t = time.time()
     for i in range(n_vol):
-        side = int(rng.integers(128, 257))
+        if args.denoiser_full and i % 10 == 0:
+            log(f"[denoiser] volume {i}/{n_vol}, {len(xs)} crops, {time.time() - t:.0f}s")
+        side = int(rng.integers(lo, hi + 1))
         v = synth.cloud_volume((side, side, side), seed=1000 + i)
         buf, _ = vdbc.encode(v, 0.10)
         g = vdbc.Grid(buf)
@@ -124,8 +130,8 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
     mean = {k: float(np.mean([e[k] for e in evals])) for k in keys}
     return {"metric": "denoised 4-spp relMSE vs plain 64-spp relMSE (1024-spp reference)",
             "value": mean["relmse_denoised"], "unit": "relMSE", "higher_is_better": False,
-            "config": {"workload": f"{n_vol}x{views} crops {size}^2 at 1:10, targets {spp_tgt} spp,"
-                                   f" eval 3 clouds 384^3 at 512^2",
+            "config": {"workload": f"{n_vol}x{views} crops {size}^2 of {lo}^3..{hi}^3 clouds at 1:10,"
+                                   f" targets {spp_tgt} spp, eval 3 clouds 384^3 at 512^2",
                        "train_steps": steps, "batch": batch, "lr": 1e-3},
             "train_s": round(train_s, 2), "gen_s": round(gen_s, 2),
             "ms_per_train_step": round(train_s / steps * 1e3, 3),

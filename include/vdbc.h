@@ -189,7 +189,12 @@ enum {
     VDBC_RENDER_HDDA = 1u,        /* EA, ISO: skip lattice samples inside empty tree
                                      nodes (result-preserving; EA needs alpha_TF(B) == 0) */
     VDBC_RENDER_COUNT = 2u,       /* count trilinear samples into the workspace */
-    VDBC_RENDER_KEEP_MAJORANT = 4u /* PT: reuse the majorant grid already in ws */
+    VDBC_RENDER_KEEP_MAJORANT = 4u, /* PT: reuse the majorant grid already in ws */
+    VDBC_RENDER_RR = 8u            /* PT: Russian roulette (Section 4): from bounce 2 on a
+                                      path survives with q = min(1, max throughput) and
+                                      survivors carry throughput / q; the survival draw
+                                      precedes the two direction draws of each segment's
+                                      stream (bounce >= 1) */
 };
 
 typedef struct {

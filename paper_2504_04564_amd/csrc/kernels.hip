@@ -389,6 +389,7 @@ struct PtArgs {
     float invC;
     int lf, cgx, cgy, cgz, cwords;   // coarse blocks of 2^lf macrocells per axis, bit words
     uint32_t seed_lo, seed_hi, frame;
+    int rr;                          // Russian roulette from bounce 2 on
 };
 
 // Occupancy of the coarse blocks: bit set iff some macrocell of the block has
@@ -702,9 +703,25 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
         }
         if (next_bounce) {
             // segment b + 1: isotropic scattering from the collision point
-            // (the shadow ray's origin) with the first two draws of its stream
+            // (the shadow ray's origin) with the first two draws of its
+            // stream; with Russian roulette one survival draw comes first
+            // (from bounce 2 on: survive with q = min(1, max throughput),
+            // survivors carry throughput / q)
             ++b;
             rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
+            if (g.rr) {
+                const float ur = rng.next();
+                const float qs = b >= 2 ? fminf(fmaxf(fmaxf(b0, b1), b2), 1.0f) : 1.0f;
+                if (ur < qs) {
+                    b0 /= qs;
+                    b1 /= qs;
+                    b2 /= qs;
+                } else {
+                    path_done = true;
+                }
+            }
+        }
+        if (next_bounce && !path_done) {
             const float u1 = rng.next(), u2 = rng.next();
             const float z = 1.0f - 2.0f * u1;
             const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
@@ -1129,6 +1146,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     g.seed_lo = (uint32_t)r->seed;
     g.seed_hi = (uint32_t)(r->seed >> 32);
     g.frame = r->frame;
+    g.rr = (r->flags & VDBC_RENDER_RR) ? 1 : 0;
     uint32_t* coarse = reinterpret_cast<uint32_t*>(
         static_cast<uint8_t*>(ws) + 256 + align256(majorant_bytes(r->macrocell, v.nx, v.ny, v.nz)));
     {
@@ -1401,6 +1419,7 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         g.seed_lo = (uint32_t)it.seed;
         g.seed_hi = (uint32_t)(it.seed >> 32);
         g.frame = it.frame;
+        g.rr = 0;
         const int tx = (cam.width + 2 * g.tw - 1) / (2 * g.tw), ty = (cam.height + 128 / g.tw - 1) / (128 / g.tw);
         if ((uint64_t)tx * ty > 0xFFFFFu) return fail(VDBC_E_INVALID, "batch item %u: image too large", i);
         b->views.push_back(v);

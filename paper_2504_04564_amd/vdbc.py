@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libvdbc.so")
 OK, E_INVALID, E_NOMEM, E_BUFFER_TOO_SMALL, E_FORMAT, E_DEVICE, E_UNSUPPORTED = range(7)
 BG_EXPLICIT, NO_CORNERS, NO_PRUNE = 1, 2, 4
 MODE_EA, MODE_PT, MODE_ISO = 0, 1, 2
-RENDER_HDDA, RENDER_COUNT, RENDER_KEEP_MAJORANT = 1, 2, 4
+RENDER_HDDA, RENDER_COUNT, RENDER_KEEP_MAJORANT, RENDER_RR = 1, 2, 4, 8
 
 
 class VdbcError(RuntimeError):

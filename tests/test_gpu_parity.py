@@ -377,3 +377,34 @@ def test_pt_image_independent_of_wave_tile_shape():
         imgs.append(vdbc.render(g, cam, med, p, vdbc.MODE_PT).cpu().numpy())
     for im in imgs[1:]:
         assert np.array_equal(im.view(np.uint32), imgs[0].view(np.uint32))
+
+
+def test_pt_russian_roulette_vs_oracle():
+    # albedo 0.9 and 16 bounces: roulette from bounce 2 changes the draws and
+    # ends paths early; the GPU must follow the oracle path by path
+    v = synth.mid_volume(n=96)
+    buf, _ = vdbc.encode(v, 0.25)
+    cam, med, prm = _pt_scene(96, 48, 40, 4)
+    prm = dict(prm, max_bounces=16, flags=vdbc.RENDER_RR, rr=True)
+    want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm)
+    got = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
+    assert relmse(got, want) <= 1e-4
+    plain = vdbc.render(vdbc.Grid(buf), cam, med, dict(prm, flags=0), vdbc.MODE_PT)
+    assert not np.array_equal(plain.cpu().numpy().reshape(-1, 4), got)
+    want_d = oracle.render_pt(oracle.DenseField(v, 0.0), cam, med, prm)
+    got_d = vdbc.render(_dense_t(v), cam, med, prm, vdbc.MODE_PT, background=0.0)
+    assert relmse(got_d.cpu().numpy().reshape(-1, 4), want_d) <= 1e-4
+
+
+def test_pt_russian_roulette_white_furnace():
+    n = 32
+    v = np.full((n, n, n), 1.0, np.float32)
+    buf, _ = vdbc.encode(v, 1.0)
+    cam = scenes.orbit_camera((n, n, n), 24, 24)
+    med = dict(sigma_scale=40.0, albedo=1.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
+               light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(0.25, 0.5, 1.0))
+    img = vdbc.render(vdbc.Grid(buf), cam, med,
+                      dict(spp=4, max_bounces=100000, seed=3, flags=vdbc.RENDER_RR),
+                      vdbc.MODE_PT).cpu().numpy()
+    np.testing.assert_allclose(img[..., :3], np.broadcast_to([0.25, 0.5, 1.0], img[..., :3].shape),
+                               rtol=1e-6)

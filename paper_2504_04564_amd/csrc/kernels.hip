@@ -154,39 +154,72 @@ __global__ __launch_bounds__(kCmpThreads) void compare_kernel(VdbView view, cons
     if (t < 5) part[5 * blockIdx.x + t] = red[t][0];
 }
 
-__global__ __launch_bounds__(64) void compare_fold_kernel(const double* __restrict__ part, int blocks,
-                                                          double* __restrict__ out)
+// Folds the per-workgroup partials: workgroup s reduces statistic s, each
+// thread a fixed stride of partials, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void compare_fold_kernel(const double* __restrict__ part, int blocks,
+                                                           double* __restrict__ out)
 {
-    // one lane per statistic, partials in block order
-    const int t = threadIdx.x;
-    if (t >= 5) return;
-    double a = (t == 3) ? INFINITY : (t == 4) ? -INFINITY : 0.0;
-    for (int b = 0; b < blocks; ++b) {
-        const double v = part[5 * b + t];
-        a = (t == 0 || t == 2) ? a + v : (t == 3) ? fmin(a, v) : fmax(a, v);
+    const int s = blockIdx.x, t = threadIdx.x;
+    const bool sum = (s == 0 || s == 2), mn = (s == 3);
+    double a = sum ? 0.0 : mn ? INFINITY : (s == 1 ? 0.0 : -INFINITY);
+    for (int b = t; b < blocks; b += 256) {
+        const double v = part[5 * b + s];
+        a = sum ? a + v : mn ? fmin(a, v) : fmax(a, v);
     }
-    out[t] = a;
+    __shared__ double red[256];
+    red[t] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            const double v = red[t + h];
+            red[t] = sum ? red[t] + v : mn ? fmin(red[t], v) : fmax(red[t], v);
+        }
+        __syncthreads();
+    }
+    if (t == 0) out[s] = red[0];
 }
 
 // ---------------------------------------------------------------- majorant
 
+// One workgroup per macrocell: the 256 threads split the (C+2)^3 dilated
+// footprint into z-columns (thread -> (i, j), walking k, so consecutive
+// lookups stay in one leaf), then reduce min and max across the workgroup.
 template <class Acc, class View>
 __global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, int C, int gx,
                                                           int gy, int gz, float* __restrict__ out)
 {
     Acc acc{view};
     acc.reset();
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= gx * gy * gz) return;
-    const int cx = cell % gx, cy = (cell / gx) % gy, cz = cell / (gx * gy);
+    const uint32_t cell = blockIdx.x;
+    const int cx = (int)(cell % (uint32_t)gx), cy = (int)((cell / (uint32_t)gx) % (uint32_t)gy),
+              cz = (int)(cell / ((uint32_t)gx * (uint32_t)gy));
+    const int E = C + 2, x0 = C * cx - 1, y0 = C * cy - 1, z0 = C * cz - 1;
     float vmin = INFINITY, vmax = -INFINITY;
-    for (int k = C * cz - 1; k <= C * cz + C; ++k)
-        for (int j = C * cy - 1; j <= C * cy + C; ++j)
-            for (int i = C * cx - 1; i <= C * cx + C; ++i) {
-                const float v = acc.voxel(i, j, k);
-                vmin = fminf(vmin, v);
-                vmax = fmaxf(vmax, v);
-            }
+    for (int col = threadIdx.x; col < E * E; col += kBlock) {
+        const int i = col % E, j = col / E;
+        for (int k = 0; k < E; ++k) {
+            const float v = acc.voxel(x0 + i, y0 + j, z0 + k);
+            vmin = fminf(vmin, v);
+            vmax = fmaxf(vmax, v);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        vmin = fminf(vmin, __shfl_xor(vmin, o));
+        vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    }
+    __shared__ float red[2][kBlock / 64];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = vmin;
+        red[1][w] = vmax;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int q = 1; q < kBlock / 64; ++q) {
+        vmin = fminf(vmin, red[0][q]);
+        vmax = fmaxf(vmax, red[1][q]);
+    }
     // max of the piecewise-linear alpha over [vmin, vmax]: the two ends and
     // every control point strictly inside
     float a = fmaxf(tf_alpha(m, vmin), tf_alpha(m, vmax));
@@ -1024,8 +1057,9 @@ static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, 
 {
     const int gx = (v.nx + C - 1) / C, gy = (v.ny + C - 1) / C, gz = (v.nz + C - 1) / C;
     const uint64_t cells = (uint64_t)gx * gy * gz;
-    hipLaunchKernelGGL((majorant_kernel<Acc, View>), dim3((unsigned)((cells + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, st, v, m, (int)C, gx, gy, gz, out);
+    if (cells > 0x7FFFFFFFull) return fail(VDBC_E_INVALID, "too many macrocells (%llu)", (unsigned long long)cells);
+    hipLaunchKernelGGL((majorant_kernel<Acc, View>), dim3((unsigned)cells), dim3(kBlock), 0, st, v, m,
+                       (int)C, gx, gy, gz, out);
     return launch_check("majorant");
 }
 
@@ -1262,7 +1296,7 @@ extern "C" vdbc_status vdbc_compare_dense(const vdbc_grid* g, const float* dense
     double* part = static_cast<double*>(ws);
     hipLaunchKernelGGL(compare_kernel, dim3(blocks), dim3(kCmpThreads), 0, st, v, dense, part);
     if ((s = launch_check("compare"))) return s;
-    hipLaunchKernelGGL(compare_fold_kernel, dim3(1), dim3(64), 0, st, part, (int)blocks, out);
+    hipLaunchKernelGGL(compare_fold_kernel, dim3(5), dim3(256), 0, st, part, (int)blocks, out);
     return launch_check("compare fold");
 }
 

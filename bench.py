@@ -42,12 +42,13 @@ KERNEL_SOURCES = ["paper_2504_04564_amd/csrc/kernels.hip", "paper_2504_04564_amd
                   "paper_2504_04564_amd/csrc/format.h"]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the PT kernel from the committed rocprofv3
-    counter summary, or None if the kernel sources changed since."""
+def profile_values():
+    """Figures of the committed rocprofv3 counter summary of the PT kernel
+    (HBM bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the
+    kernel sources changed since the counters were taken."""
     import hashlib
     if not os.path.exists(PROFILE):
-        return None
+        return {}
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -58,11 +59,13 @@ def measured_traffic():
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != h.hexdigest()[:16]:
-        return None
+        return {}
     try:
-        return int(float(vals["traffic_bytes_per_launch"]))
+        return {"traffic": int(float(vals["traffic_bytes_per_launch"])),
+                "valu_lane_utilisation": float(vals["valu_lane_utilisation"]),
+                "l2_hit_rate": float(vals["l2_hit_rate"])}
     except (KeyError, ValueError):
-        return None
+        return {}
 
 
 def time_frames(torch, r, steps, warmup):
@@ -256,6 +259,7 @@ def main():
         log(f"[bench] oracle {cpu['value']:.4f} Mrays/s; relMSE GPU vs oracle {rel:.3e}")
 
     pt_s = pt_ms * 1e-3
+    prof = profile_values() if (args.rate == 0.10 and n == 512 and C == 16) else {}
     achieved = samples * BYTES_PER_RENDER_SAMPLE / pt_s / 1e9
     line = {
         "metric": METRIC,
@@ -279,13 +283,18 @@ def main():
             "achieved_rate": round(st["achieved_rate"], 5),
         },
         "roofline": {
+            # the committed counters describe this exact workload only
             "kernel": "pt_kernel<VdbAcc>",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": measured_traffic() if (args.rate == 0.10 and n == 512 and C == 16) else None,
+            "traffic": prof.get("traffic"),
+            "limiter": ({"kind": "VALU issue of divergent lanes (counters of the same kernel build)",
+                         "valu_lane_utilisation": prof["valu_lane_utilisation"],
+                         "l2_hit_rate": prof["l2_hit_rate"],
+                         "source": os.path.relpath(PROFILE, ROOT)} if prof else None),
             "per_launch": {"samples": int(samples), "bytes_per_sample": BYTES_PER_RENDER_SAMPLE,
                            "algorithmic_bytes": int(samples * BYTES_PER_RENDER_SAMPLE),
                            "avg_ms": round(pt_ms, 4)},

@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--cpu-pixels", type=int, default=65536,
                     help="pixels of the frame the CPU oracle renders for its baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads for the all-core oracle figure (1 = single-core only)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the dense renderer and the random-sample microbenchmark")
     ap.add_argument("--macrocell", type=int, default=16, help="majorant cell edge in voxels")
@@ -257,6 +259,27 @@ def main():
                          f"({t_all:.1f}s incl. a {t_maj:.1f}s majorant build); frame time "
                          f"extrapolated as majorant + paths x {W * H}/{len(pix)}"}
         log(f"[bench] oracle {cpu['value']:.4f} Mrays/s; relMSE GPU vs oracle {rel:.3e}")
+        if args.cpu_threads > 1:
+            # the same oracle on every host core: disjoint pixel sets rendered
+            # by concurrent calls (ctypes releases the GIL during each call)
+            from concurrent.futures import ThreadPoolExecutor
+            nt = args.cpu_threads
+            pix_all = np.sort(rng.choice(W * H, args.cpu_pixels * nt, replace=False)).astype(np.uint32)
+            parts = np.array_split(pix_all, nt)
+            prm_o = dict(spp=spp, max_bounces=bounces, seed=M["seed"], macrocell=C)
+            t = time.time()
+            with ThreadPoolExecutor(max_workers=nt) as ex:
+                list(ex.map(lambda pp: oracle.render_pt(fld, cam, med, prm_o, pixels=pp), parts))
+            t_par = time.time() - t
+            # each call also builds its own majorant (t_maj of work per thread)
+            paths_s = max(t_par - t_maj, 1e-9)
+            frame_par = t_maj + paths_s * (W * H / len(pix_all))
+            cpu["all_cores"] = {
+                "value": round(rays / frame_par / 1e6, 6), "unit": "Mrays/s", "cores": nt,
+                "sample": f"{len(pix_all)} random pixels x {spp} spp in {nt} concurrent oracle calls "
+                          f"({t_par:.1f}s); frame time extrapolated as majorant + paths x "
+                          f"{W * H}/{len(pix_all)}"}
+            log(f"[bench] oracle on {nt} threads: {cpu['all_cores']['value']:.3f} Mrays/s")
 
     pt_s = pt_ms * 1e-3
     prof = profile_values() if (args.rate == 0.10 and n == 512 and C == 16) else {}

@@ -38,7 +38,10 @@ def relmse(x, y):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")
-KERNEL_SOURCES = ["paper_2504_04564_amd/csrc/kernels.hip", "paper_2504_04564_amd/csrc/device.h",
+# sources of the PT kernel and its launch: the committed counters are valid
+# while these files are unchanged
+KERNEL_SOURCES = ["paper_2504_04564_amd/csrc/pt.h", "paper_2504_04564_amd/csrc/render.hip",
+                  "paper_2504_04564_amd/csrc/kcommon.h", "paper_2504_04564_amd/csrc/device.h",
                   "paper_2504_04564_amd/csrc/format.h"]
 
 

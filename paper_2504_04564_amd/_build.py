@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libvdbc.so")
 OBJ = os.path.join(HERE, "_obj")
 
 HOST_SOURCES = ["api.cpp", "encode.cpp"]
-HIP_SOURCES = ["kernels.hip", "denoise.hip"]
+HIP_SOURCES = ["sample.hip", "render.hip", "denoise.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -1,182 +1,16 @@
-// HIP kernels for gfx950 and their C-ABI launchers: sampling (Section 3.2.2),
-// majorant macrocells, emission-absorption marching and the delta-tracking
-// path tracer (Section 4), each for the compressed VDB and for the dense
-// float32 baseline through the same templated code.
-#include <hip/hip_runtime.h>
-
-#include <algorithm>
-#include <cmath>
-#include <cstring>
-#include <memory>
-#include <new>
-#include <vector>
-
-#include "common.h"
-#include "device.h"
-#include "format.h"
-#include "host_header.h"
+// HIP kernels for gfx950 and their C-ABI launchers: majorant macrocells,
+// emission-absorption and iso-surface marching, and the delta-tracking path
+// tracer (Section 4), each for the compressed VDB and for the dense float32
+// baseline through the same templated code, plus batched rendering.
+#include "kcommon.h"
+#include "pt.h"
 
 namespace vdbc {
-
-constexpr int kTile = 16;          // 16x16 pixels per 256-thread workgroup
-constexpr int kBlock = 256;
-constexpr float kHddaEps = 1.0f / 64.0f;
-// Upper bound on density evaluations in one free-flight search; a flight that
-// reaches it is treated as escaping.  Only a majorant that exceeds the
-// sampled extinction by many orders of magnitude can get near it.
-constexpr uint32_t kMaxFlightSamples = 1u << 20;
-// Macrocells a flight may enter in one iteration of the path loop before it
-// yields (the walk resumes at the next iteration).  Lanes of a wave that walk
-// long stretches of thin medium then wait at most this many DDA steps for the
-// lanes that sample, instead of the whole walk.
-constexpr int kWalkCells = 2;
-// Value of flight_advance() when the flight yielded mid-walk.
-constexpr int kFlightYield = 2;
-// Resident PT workgroups per compute unit (the kernel's launch bounds).
-constexpr int kPtBlocksPerCu = 4;
-
-// ---------------------------------------------------------------- helpers
-
-// 256 threads = 4 waves in a 2x2 arrangement, each wave a tw x (64/tw) pixel
-// tile (tw = 8, 16, 32 or 64); workgroup (bx, by) covers a (2 tw) x (128/tw)
-// block.  Returns false outside the image.
-__device__ __forceinline__ bool tile_pixel(int width, int height, int tw, int bx, int by, int& px,
-                                           int& py)
-{
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6, th = 64 / tw;
-    px = bx * 2 * tw + (w & 1) * tw + (lane % tw);
-    py = by * 2 * th + (w >> 1) * th + (lane / tw);
-    return px < width && py < height;
-}
-
-// Adds a per-thread count to a global 64-bit counter, one atomic per block.
-__device__ __forceinline__ void block_count(uint32_t n, unsigned long long* counter)
-{
-    __shared__ unsigned int s;
-    if (threadIdx.x == 0) s = 0;
-    __syncthreads();
-    if (n) atomicAdd(&s, n);
-    __syncthreads();
-    if (threadIdx.x == 0 && s) atomicAdd(counter, (unsigned long long)s);
-}
 
 // Clears the workspace's counters: sample and cell counts, PT tile queue.
 __global__ void zero_u64(unsigned long long* p)
 {
     if (threadIdx.x < 3 && blockIdx.x == 0) p[threadIdx.x] = 0ull;
-}
-
-// ---------------------------------------------------------------- sampling
-
-template <class Acc, class View>
-__global__ __launch_bounds__(kBlock) void sample_kernel(View view, const float* __restrict__ pos,
-                                                        uint64_t n, int filter,
-                                                        float* __restrict__ out)
-{
-    Acc acc{view};
-    acc.reset();
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
-    out[i] = filter ? trilinear(acc, x, y, z) : nearest(acc, x, y, z);
-}
-
-__global__ __launch_bounds__(kBlock) void lookup_kernel(VdbView view, const int32_t* __restrict__ ijk,
-                                                        uint64_t n, float* __restrict__ out)
-{
-    VdbAcc acc{view};
-    acc.reset();
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int x = ijk[3 * i], y = ijk[3 * i + 1], z = ijk[3 * i + 2];
-    // voxels beyond the volume read B (edge leaves store B there, regions
-    // past the last leaf or outside the root table resolve to B)
-    out[i] = acc.voxel(x, y, z);
-}
-
-// ---------------------------------------------------------------- quality
-
-// Error statistics of the compressed grid against the dense volume it was
-// encoded from (the MSE / PSNR evaluation of Section 5.2).  A workgroup of
-// 512 threads takes a 64 x 8 x 8 voxel region (eight leaves along x) in a
-// grid-stride loop: thread (x, y) walks the region's 8 slices, so each wave
-// reads 256 contiguous bytes of a dense row per slice and every thread stays
-// in one leaf (one descent, then its leaf cache).  Per workgroup: {sum of
-// squared differences, max |diff|, differing voxels, min dense, max dense}
-// into part[5 * block]; a second kernel folds the partials in a fixed order
-// (deterministic for a given size).
-constexpr int kCmpThreads = 512;
-constexpr int kCmpBlocks = 4096;
-
-__global__ __launch_bounds__(kCmpThreads) void compare_kernel(VdbView view, const float* __restrict__ dense,
-                                                              double* __restrict__ part)
-{
-    VdbAcc acc{view};
-    acc.reset();
-    const int t = threadIdx.x;
-    const int lx = t & 63, ly = t >> 6;
-    const uint64_t rx = (uint64_t)(view.nx + 63) / 64, ry = (uint64_t)(view.ny + 7) / 8,
-                   rz = (uint64_t)(view.nz + 7) / 8;
-    double sse = 0.0, mx = 0.0, nd = 0.0, lo = INFINITY, hi = -INFINITY;
-    for (uint64_t r = blockIdx.x; r < rx * ry * rz; r += gridDim.x) {
-        const int x = (int)(r % rx) * 64 + lx, y = (int)((r / rx) % ry) * 8 + ly;
-        const int z0 = (int)(r / (rx * ry)) * 8;
-        if (x >= view.nx || y >= view.ny) continue;
-        for (int z = z0; z < z0 + 8 && z < view.nz; ++z) {
-            const float dv =
-                dense[(uint64_t)x + (uint64_t)view.nx * ((uint64_t)y + (uint64_t)view.ny * (uint64_t)z)];
-            const float vv = acc.voxel(x, y, z);
-            const double e = (double)vv - (double)dv;
-            sse = fma(e, e, sse);
-            mx = fmax(mx, fabs(e));
-            nd += (__float_as_uint(vv) != __float_as_uint(dv)) ? 1.0 : 0.0;
-            lo = fmin(lo, (double)dv);
-            hi = fmax(hi, (double)dv);
-        }
-    }
-    __shared__ double red[5][kCmpThreads];
-    red[0][t] = sse;
-    red[1][t] = mx;
-    red[2][t] = nd;
-    red[3][t] = lo;
-    red[4][t] = hi;
-    __syncthreads();
-    for (int h = kCmpThreads / 2; h > 0; h >>= 1) {
-        if (t < h) {
-            red[0][t] += red[0][t + h];
-            red[1][t] = fmax(red[1][t], red[1][t + h]);
-            red[2][t] += red[2][t + h];
-            red[3][t] = fmin(red[3][t], red[3][t + h]);
-            red[4][t] = fmax(red[4][t], red[4][t + h]);
-        }
-        __syncthreads();
-    }
-    if (t < 5) part[5 * blockIdx.x + t] = red[t][0];
-}
-
-// Folds the per-workgroup partials: workgroup s reduces statistic s, each
-// thread a fixed stride of partials, then a fixed-order tree in LDS.
-__global__ __launch_bounds__(256) void compare_fold_kernel(const double* __restrict__ part, int blocks,
-                                                           double* __restrict__ out)
-{
-    const int s = blockIdx.x, t = threadIdx.x;
-    const bool sum = (s == 0 || s == 2), mn = (s == 3);
-    double a = sum ? 0.0 : mn ? INFINITY : (s == 1 ? 0.0 : -INFINITY);
-    for (int b = t; b < blocks; b += 256) {
-        const double v = part[5 * b + s];
-        a = sum ? a + v : mn ? fmin(a, v) : fmax(a, v);
-    }
-    __shared__ double red[256];
-    red[t] = a;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) {
-            const double v = red[t + h];
-            red[t] = sum ? red[t] + v : mn ? fmin(red[t], v) : fmax(red[t], v);
-        }
-        __syncthreads();
-    }
-    if (t == 0) out[s] = red[0];
 }
 
 // ---------------------------------------------------------------- majorant
@@ -415,530 +249,7 @@ __global__ __launch_bounds__(kBlock) void iso_kernel(View view, CameraK cam, flo
     if (COUNT) block_count(nsamp, counter);
 }
 
-// ---------------------------------------------------------------- PT
-
-struct PtArgs {
-    int spp, max_bounces, C, gx, gy, gz, tw;
-    float invC;
-    int lf, cgx, cgy, cgz, cwords;   // coarse blocks of 2^lf macrocells per axis, bit words
-    uint32_t seed_lo, seed_hi, frame;
-    int rr;                          // Russian roulette from bounce 2 on
-};
-
-// Occupancy of the coarse blocks: bit set iff some macrocell of the block has
-// a non-zero majorant.  One thread per block; a wave ballot assembles two
-// 32-bit words per wave.
-__global__ __launch_bounds__(kBlock) void coarse_bits_kernel(const float* __restrict__ maj,
-                                                             PtArgs g, uint32_t* __restrict__ bits)
-{
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ncoarse = g.cgx * g.cgy * g.cgz;
-    const int F = 1 << g.lf;
-    bool occ = false;
-    if (cell < ncoarse) {
-        const int bx = cell % g.cgx, by = (cell / g.cgx) % g.cgy, bz = cell / (g.cgx * g.cgy);
-        for (int z = bz * F; z < min(bz * F + F, g.gz) && !occ; ++z)
-            for (int y = by * F; y < min(by * F + F, g.gy) && !occ; ++y)
-                for (int x = bx * F; x < min(bx * F + F, g.gx); ++x)
-                    if (maj[x + g.gx * (y + g.gy * z)] > 0.0f) {
-                        occ = true;
-                        break;
-                    }
-    }
-    const uint64_t ballot = __ballot(occ);
-    const int lane = threadIdx.x & 63;
-    const int w = (blockIdx.x * blockDim.x + threadIdx.x - lane) >> 5;   // first word of the wave
-    if (lane == 0 && w < g.cwords) bits[w] = (uint32_t)ballot;
-    if (lane == 0 && w + 1 < g.cwords) bits[w + 1] = (uint32_t)(ballot >> 32);
-}
-
-// One ray segment being tracked through the majorant grid (Section 4): a 3D
-// DDA over macrocells, hierarchical over coarse blocks of macrocells whose
-// occupancy bits live in LDS, and delta tracking inside non-empty cells.
-struct Flight {
-    float o[3], d[3], id[3];
-    float t, t1, te, mu, imu;
-    int cx, cy, cz, axis;
-    bool incell, ok;
-    uint32_t budget;
-};
-
-// Starts a segment: clip to the box and find the first macrocell.
-__device__ __forceinline__ void flight_begin(Flight& f, const PtArgs& g, int nx, int ny, int nz,
-                                             const float o[3], const float d[3], float& t0)
-{
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        f.o[a] = o[a];
-        f.d[a] = d[a];
-        f.id[a] = 1.0f / d[a];
-    }
-    f.incell = false;
-    f.budget = kMaxFlightSamples;
-    f.ok = box_clip(nx, ny, nz, o, d, f.id, t0, f.t1);
-    f.t = t0;
-    if (!f.ok) return;
-    // the macrocell edge is a power of two: multiplying by its reciprocal is exact
-    f.cx = min(max((int)floorf((fmaf(t0, d[0], o[0]) + 0.5f) * g.invC), 0), g.gx - 1);
-    f.cy = min(max((int)floorf((fmaf(t0, d[1], o[1]) + 0.5f) * g.invC), 0), g.gy - 1);
-    f.cz = min(max((int)floorf((fmaf(t0, d[2], o[2]) + 0.5f) * g.invC), 0), g.gz - 1);
-}
-
-__device__ __forceinline__ bool coarse_occupied(const uint32_t* bits, const PtArgs& g, int bx,
-                                                int by, int bz)
-{
-    const uint32_t i = (uint32_t)(bx + g.cgx * (by + g.cgy * bz));
-    return (bits[i >> 5] >> (i & 31u)) & 1u;
-}
-
-// Exit distance through the faces of an axis-aligned cell of edge `edge`
-// (index c along each axis); returns the crossing axis or -1 if t1 is closer.
-__device__ __forceinline__ int cell_exit(const Flight& f, float edge, int cx, int cy, int cz,
-                                         float& te)
-{
-    te = f.t1;
-    int axis = -1;
-    if (f.d[0] != 0.0f) {
-        const float ta = (edge * (float)(cx + (f.d[0] > 0.0f)) - 0.5f - f.o[0]) * f.id[0];
-        if (ta < te) {
-            te = ta;
-            axis = 0;
-        }
-    }
-    if (f.d[1] != 0.0f) {
-        const float ta = (edge * (float)(cy + (f.d[1] > 0.0f)) - 0.5f - f.o[1]) * f.id[1];
-        if (ta < te) {
-            te = ta;
-            axis = 1;
-        }
-    }
-    if (f.d[2] != 0.0f) {
-        const float ta = (edge * (float)(cz + (f.d[2] > 0.0f)) - 0.5f - f.o[2]) * f.id[2];
-        if (ta < te) {
-            te = ta;
-            axis = 2;
-        }
-    }
-    return axis;
-}
-
-// Advances the flight to its next tentative collision: returns 1 with the
-// density `sv` sampled there (the caller makes the accept test), 0 when the
-// segment leaves the grid without one, or kFlightYield after entering
-// kWalkCells macrocells without a collision (call again to continue; the
-// walk and its random draws are the same as without the pause).  Empty cells draw no random
-// numbers and coarse-block faces are macrocell faces, so the tentative
-// collisions are those of a uniform walk over every macrocell; a flight that
-// overshoots a cell restarts at its exit (memorylessness).
-template <class Acc>
-__device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK& m,
-                                              const float* __restrict__ maj,
-                                              const uint32_t* cbits, const PtArgs& g, Rng& rng,
-                                              float& sv, uint32_t& nsamp, uint32_t& ncell)
-{
-    if (!f.ok) return 0;
-    const float C = (float)g.C;
-    const float CF = (float)(g.C << g.lf);
-    int walk = kWalkCells;
-    for (;;) {
-        if (f.incell) {
-            f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
-            if (f.t < f.te) {
-                if (--f.budget == 0) return 0;
-                sv = trilinear(acc, fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
-                               fmaf(f.t, f.d[2], f.o[2]));
-                ++nsamp;
-                return 1;
-            }
-            f.incell = false;
-            if (f.axis < 0) return 0;
-            f.t = f.te;
-            if (f.axis == 0) {
-                f.cx += f.d[0] > 0.0f ? 1 : -1;
-                if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
-            } else if (f.axis == 1) {
-                f.cy += f.d[1] > 0.0f ? 1 : -1;
-                if ((unsigned)f.cy >= (unsigned)g.gy) return 0;
-            } else {
-                f.cz += f.d[2] > 0.0f ? 1 : -1;
-                if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
-            }
-        }
-        if (--walk < 0) return kFlightYield;
-        const int bx = f.cx >> g.lf, by = f.cy >> g.lf, bz = f.cz >> g.lf;
-        ++ncell;
-        if (!coarse_occupied(cbits, g, bx, by, bz)) {
-            // cross the empty block in one step
-            float te;
-            const int axis = cell_exit(f, CF, bx, by, bz, te);
-            if (axis < 0) return 0;
-            f.t = te;
-            const int F = 1 << g.lf;
-            const float px = (fmaf(te, f.d[0], f.o[0]) + 0.5f) * g.invC;
-            const float py = (fmaf(te, f.d[1], f.o[1]) + 0.5f) * g.invC;
-            const float pz = (fmaf(te, f.d[2], f.o[2]) + 0.5f) * g.invC;
-            if (axis == 0) {
-                f.cx = f.d[0] > 0.0f ? (bx + 1) * F : bx * F - 1;
-                if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
-            } else {
-                f.cx = min(max((int)floorf(px), bx * F), min(bx * F + F, g.gx) - 1);
-            }
-            if (axis == 1) {
-                f.cy = f.d[1] > 0.0f ? (by + 1) * F : by * F - 1;
-                if ((unsigned)f.cy >= (unsigned)g.gy) return 0;
-            } else {
-                f.cy = min(max((int)floorf(py), by * F), min(by * F + F, g.gy) - 1);
-            }
-            if (axis == 2) {
-                f.cz = f.d[2] > 0.0f ? (bz + 1) * F : bz * F - 1;
-                if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
-            } else {
-                f.cz = min(max((int)floorf(pz), bz * F), min(bz * F + F, g.gz) - 1);
-            }
-            continue;
-        }
-        f.axis = cell_exit(f, C, f.cx, f.cy, f.cz, f.te);
-        f.mu = maj[f.cx + g.gx * (f.cy + g.gy * f.cz)];
-        if (f.mu > 0.0f && f.t < f.te) {
-            f.incell = true;
-            f.imu = 1.0f / f.mu;
-            continue;
-        }
-        if (f.axis < 0) return 0;
-        f.t = f.te;
-        if (f.axis == 0) {
-            f.cx += f.d[0] > 0.0f ? 1 : -1;
-            if ((unsigned)f.cx >= (unsigned)g.gx) return 0;
-        } else if (f.axis == 1) {
-            f.cy += f.d[1] > 0.0f ? 1 : -1;
-            if ((unsigned)f.cy >= (unsigned)g.gy) return 0;
-        } else {
-            f.cz += f.d[2] > 0.0f ? 1 : -1;
-            if ((unsigned)f.cz >= (unsigned)g.gz) return 0;
-        }
-    }
-}
-
-// LDS state of one 256-pixel tile: next unit of work and per-pixel sums in
-// 2^-32 fixed point (integer sums do not depend on the order of the adds).
-struct TileShared {
-    long long rgb[kBlock][3];
-    long long depth[kBlock];
-    unsigned int hits[kBlock], escapes[kBlock];
-    unsigned int next;
-};
-
-__device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v * 4294967296.0f); }
-
-// Delta-tracking path tracer (Section 4) over one tile of 256 pixels.  The
-// tile's 256 x spp paths (unit u = sample u / 256 of tile pixel u % 256) are
-// shared by the workgroup: every lane starts on one unit and takes the next
-// one from an LDS counter when its path ends, so lanes on empty pixels or on
-// short paths keep working.  Within a path the loop is flat: every iteration
-// moves the lane to its next tentative collision and handles whatever event
-// it reached (collision, escape, end of a shadow ray, start of a new path).
-// The arithmetic and the random draws of each path are those of a recursive
-// implementation: key (seed_lo ^ pixel, seed_hi), counter (block, sample,
-// stream << 16 | bounce, frame).  Stream 0 of bounce b is path segment b:
-// two draws for its direction (pixel jitter for b = 0, isotropic scattering
-// otherwise), then its free flights and accept tests; stream 1 of bounce b is
-// the shadow ray from collision b.  Results depend only on the pixel, not on
-// the lane, tile shape or launch.
-template <class Acc, bool AOV>
-__device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
-                                        const MediumK& m, const PtArgs& g,
-                                        const float* __restrict__ maj, const uint32_t* cbits,
-                                        int bx, int by, TileShared& ts, float* __restrict__ image,
-                                        float* __restrict__ aov, uint32_t& nsamp, uint32_t& ncell)
-{
-    const int tid = threadIdx.x;
-    const int tw = g.tw, th = 64 / g.tw;
-    const int x0 = bx * 2 * tw, y0 = by * 2 * th;
-    ts.rgb[tid][0] = ts.rgb[tid][1] = ts.rgb[tid][2] = 0;
-    ts.depth[tid] = 0;
-    ts.hits[tid] = ts.escapes[tid] = 0;
-    if (tid == 0) ts.next = kBlock;
-    __syncthreads();
-    const uint32_t total = (uint32_t)kBlock * (uint32_t)g.spp;
-    const float inv4pi = 0.0795774715459476679f;
-    uint32_t u = (uint32_t)tid;
-    int q = 0, px = 0, py = 0;
-    uint32_t k0 = 0, smp = 0;
-    float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
-    float t0p = 0.0f, pdepth = 1.0f;
-    bool phit = false;
-    int b = 0;
-    bool shadow = false, fresh = true;
-    Rng rng;
-    Flight f;
-    while (u < total) {
-        if (fresh) {
-            q = (int)(u & (kBlock - 1));
-            smp = u >> 8;
-            const int w = q >> 6, l = q & 63;
-            px = x0 + (w & 1) * tw + (l % tw);
-            py = y0 + (w >> 1) * th + (l / tw);
-            if (px >= cam.width || py >= cam.height) {   // no pixel here
-                u = atomicAdd(&ts.next, 1u);
-                continue;
-            }
-            fresh = false;
-            k0 = g.seed_lo ^ ((uint32_t)py * (uint32_t)cam.width + (uint32_t)px);
-            rng.init(k0, g.seed_hi, smp, 0u, 0u, g.frame);
-            const float jx = rng.next(), jy = rng.next();
-            float o[3], d[3];
-            camera_ray(cam, (float)px + jx, (float)py + jy, o, d);
-            b = 0;
-            shadow = false;
-            L0 = L1 = L2 = 0.0f;
-            b0 = b1 = b2 = 1.0f;
-            flight_begin(f, g, nx, ny, nz, o, d, t0p);
-        }
-        float sv = 0.0f;
-        const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
-        if (tentative == kFlightYield) continue;
-        const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha(m, sv);
-        if (tentative && !hit) continue;    // null collision: keep tracking
-        bool path_done = false, next_bounce = false;
-        if (!shadow) {
-            if (b == 0) {
-                phit = hit;
-                pdepth = hit ? (f.t - t0p) / (f.t1 - t0p) : 1.0f;
-            }
-            if (hit) {
-                // real collision: weight by albedo and colour, then the
-                // shadow ray towards the light from the collision point
-                const float4 c = tf_eval(m, sv);
-                b0 *= m.albedo * c.x;
-                b1 *= m.albedo * c.y;
-                b2 *= m.albedo * c.z;
-                const float x[3] = {fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
-                                    fmaf(f.t, f.d[2], f.o[2])};
-                rng.init(k0, g.seed_hi, smp, (uint32_t)b, 1u, g.frame);
-                float t0s;
-                flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
-                shadow = true;
-            } else {
-                L0 = fmaf(b0, m.ambient[0], L0);
-                L1 = fmaf(b1, m.ambient[1], L1);
-                L2 = fmaf(b2, m.ambient[2], L2);
-                path_done = true;
-            }
-        } else {
-            if (!hit) {
-                L0 = fmaf(b0 * inv4pi, m.light_E[0], L0);
-                L1 = fmaf(b1 * inv4pi, m.light_E[1], L1);
-                L2 = fmaf(b2 * inv4pi, m.light_E[2], L2);
-            }
-            shadow = false;
-            if (b + 1 == g.max_bounces) path_done = true;
-            else next_bounce = true;
-        }
-        if (next_bounce) {
-            // segment b + 1: isotropic scattering from the collision point
-            // (the shadow ray's origin) with the first two draws of its
-            // stream; with Russian roulette one survival draw comes first
-            // (from bounce 2 on: survive with q = min(1, max throughput),
-            // survivors carry throughput / q)
-            ++b;
-            rng.init(k0, g.seed_hi, smp, (uint32_t)b, 0u, g.frame);
-            if (g.rr) {
-                const float ur = rng.next();
-                const float qs = b >= 2 ? fminf(fmaxf(fmaxf(b0, b1), b2), 1.0f) : 1.0f;
-                if (ur < qs) {
-                    b0 /= qs;
-                    b1 /= qs;
-                    b2 /= qs;
-                } else {
-                    path_done = true;
-                }
-            }
-        }
-        if (next_bounce && !path_done) {
-            const float u1 = rng.next(), u2 = rng.next();
-            const float z = 1.0f - 2.0f * u1;
-            const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-            const float phi = 6.28318530717958647692f * u2;
-            const float o[3] = {f.o[0], f.o[1], f.o[2]};
-            const float d[3] = {r * __cosf(phi), r * __sinf(phi), z};
-            float t0n;
-            flight_begin(f, g, nx, ny, nz, o, d, t0n);
-        }
-        if (path_done) {
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][0]), (unsigned long long)to_fixed(L0));
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][1]), (unsigned long long)to_fixed(L1));
-            atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][2]), (unsigned long long)to_fixed(L2));
-            if (AOV) atomicAdd(reinterpret_cast<unsigned long long*>(&ts.depth[q]),
-                               (unsigned long long)to_fixed(pdepth));
-            atomicAdd(phit ? &ts.hits[q] : &ts.escapes[q], 1u);
-            u = atomicAdd(&ts.next, 1u);
-            fresh = true;
-        }
-    }
-    __syncthreads();
-    {
-        const int w = tid >> 6, l = tid & 63;
-        const int qx = x0 + (w & 1) * tw + (l % tw), qy = y0 + (w >> 1) * th + (l / tw);
-        if (qx < cam.width && qy < cam.height) {
-            const uint32_t pix = (uint32_t)qy * (uint32_t)cam.width + (uint32_t)qx;
-            const double sc = 1.0 / (4294967296.0 * (double)g.spp);
-            const float inv = 1.0f / (float)g.spp;
-            reinterpret_cast<float4*>(image)[pix] =
-                make_float4((float)((double)ts.rgb[tid][0] * sc), (float)((double)ts.rgb[tid][1] * sc),
-                            (float)((double)ts.rgb[tid][2] * sc), (float)ts.hits[tid] * inv);
-            if (AOV)
-                reinterpret_cast<float2*>(aov)[pix] =
-                    make_float2((float)((double)ts.depth[tid] * sc), (float)ts.escapes[tid] * inv);
-        }
-    }
-    __syncthreads();
-}
-
-template <class Acc, class View, bool COUNT, bool AOV>
-__global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
-                                                    const float* __restrict__ maj,
-                                                    const uint32_t* __restrict__ coarse,
-                                                    float* __restrict__ image,
-                                                    float* __restrict__ aov,
-                                                    unsigned long long* counter,
-                                                    uint32_t* queue)
-{
-    extern __shared__ uint32_t cbits[];
-    __shared__ TileShared ts;
-    for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = coarse[i];
-    __syncthreads();
-    Acc acc{view};
-    acc.reset();
-    uint32_t nsamp = 0, ncell = 0;
-    // persistent workgroups take tiles in raster order from a queue, so a
-    // workgroup that drew cheap tiles goes on to the next one at once
-    __shared__ uint32_t s_tile;
-    const uint32_t tiles_x = (uint32_t)((cam.width + 2 * g.tw - 1) / (2 * g.tw));
-    const uint32_t tiles = tiles_x * (uint32_t)((cam.height + 128 / g.tw - 1) / (128 / g.tw));
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1u);
-        __syncthreads();
-        const uint32_t t = s_tile;   // pt_tile's barriers order this read before the next write
-        if (t >= tiles) break;
-        pt_tile<Acc, AOV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
-                          (int)(t / tiles_x), ts, image, aov, nsamp, ncell);
-    }
-    if (COUNT) {
-        block_count(nsamp, counter);
-        block_count(ncell, counter + 1);
-    }
-}
-
-// ---------------------------------------------------------------- batched PT
-// Many volumes in one persistent launch: workgroups pull (volume, tile) items
-// from an atomic counter over a list ordered by estimated cost (largest
-// first) and render each tile with the per-pixel code of pt_kernel, so every
-// image is bit-identical to its own launch.
-struct BatchDesc {
-    VdbView view;
-    CameraK cam;
-    MediumK med;
-    PtArgs g;
-    const float* maj;
-    const uint32_t* coarse;
-    float* image;
-    int tiles_x;
-};
-
-__global__ void zero_u32(uint32_t* p)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
-}
-
-__global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __restrict__ descs,
-                                                          const uint32_t* __restrict__ items,
-                                                          uint32_t n_items, uint32_t* counter)
-{
-    extern __shared__ uint32_t cbits[];
-    __shared__ uint32_t s_item;
-    __shared__ TileShared ts;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t it = __builtin_amdgcn_readfirstlane(s_item);
-        if (it >= n_items) break;
-        const uint32_t code = __builtin_amdgcn_readfirstlane(items[it]);
-        const BatchDesc* D = descs + (code >> 20);
-        const uint32_t tile = code & 0xFFFFFu;
-        const PtArgs g = D->g;
-        const CameraK cam = D->cam;
-        for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = D->coarse[i];
-        __syncthreads();
-        VdbAcc acc{D->view};
-        acc.reset();
-        uint32_t ns = 0, nc = 0;
-        pt_tile<VdbAcc, false>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
-                               (int)(tile % (uint32_t)D->tiles_x), (int)(tile / (uint32_t)D->tiles_x), ts,
-                               D->image, nullptr, ns, nc);
-    }
-}
-
-__global__ void philox_kernel(const uint32_t* __restrict__ ctr, const uint32_t* __restrict__ key,
-                              uint64_t n, uint32_t* __restrict__ out)
-{
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c0 = ctr[4 * i], c1 = ctr[4 * i + 1], c2 = ctr[4 * i + 2], c3 = ctr[4 * i + 3];
-    philox4x32_10(c0, c1, c2, c3, key[2 * i], key[2 * i + 1]);
-    out[4 * i] = c0;
-    out[4 * i + 1] = c1;
-    out[4 * i + 2] = c2;
-    out[4 * i + 3] = c3;
-}
-
 // ---------------------------------------------------------------- host side
-
-static vdbc_status launch_check(const char* what)
-{
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(VDBC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
-    return VDBC_OK;
-}
-
-static vdbc_status make_view(const vdbc_grid* g, VdbView* v)
-{
-    if (!g || !g->device) return fail(VDBC_E_INVALID, "null grid");
-    Header h;
-    vdbc_status s = parse_header(g->header, g->bytes, &h);
-    if (s) return s;
-    const uint8_t* b = static_cast<const uint8_t*>(g->device);
-    v->root = reinterpret_cast<const uint32_t*>(b + h.off_root);
-    v->upper = reinterpret_cast<const Word*>(b + h.off_upper);
-    v->lower = reinterpret_cast<const Word*>(b + h.off_lower);
-    v->upper_tiles = reinterpret_cast<const float*>(b + h.off_upper_tiles);
-    v->lower_tiles = reinterpret_cast<const float*>(b + h.off_lower_tiles);
-    v->leaf_values = reinterpret_cast<const float*>(b + h.off_leaf_values);
-    v->bg = reinterpret_cast<const float*>(b + hdr::background);
-    v->nx = (int)h.nx;
-    v->ny = (int)h.ny;
-    v->nz = (int)h.nz;
-    v->rnx = (int)h.root_nx;
-    v->rny = (int)h.root_ny;
-    v->rnz = (int)h.root_nz;
-    v->background = h.background;
-    return VDBC_OK;
-}
-
-static vdbc_status make_dense(const float* dense, vdbc_dims d, float background, DenseView* v)
-{
-    if (!dense) return fail(VDBC_E_INVALID, "null dense array");
-    if (d.nx == 0 || d.ny == 0 || d.nz == 0 || d.nx > 0x7FFFFFFFu || d.ny > 0x7FFFFFFFu ||
-        d.nz > 0x7FFFFFFFu)
-        return fail(VDBC_E_INVALID, "dims must be in [1, 2^31)");
-    if (!std::isfinite(background)) return fail(VDBC_E_INVALID, "background must be finite");
-    v->data = dense;
-    v->nx = (int)d.nx;
-    v->ny = (int)d.ny;
-    v->nz = (int)d.nz;
-    v->background = background;
-    return VDBC_OK;
-}
 
 static vdbc_status make_medium(const vdbc_medium* m, int nx, int ny, int nz, MediumK* k)
 {
@@ -1043,13 +354,6 @@ static uint64_t pt_workspace(uint32_t C, int nx, int ny, int nz)
     return 256 + align256(majorant_bytes(C, nx, ny, nz)) + align256(4ull * g.cwords);
 }
 
-static vdbc_status check_samples(const float* pos, uint64_t n, uint32_t filter, float* out)
-{
-    if (filter > 1) return fail(VDBC_E_INVALID, "filter must be 0 or 1");
-    if (n && (!pos || !out)) return fail(VDBC_E_INVALID, "null positions or output");
-    if (n > (uint64_t)0x7FFFFFFFull * kBlock) return fail(VDBC_E_INVALID, "too many samples");
-    return VDBC_OK;
-}
 
 template <class Acc, class View>
 static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, float* out,
@@ -1214,92 +518,6 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
 
 using namespace vdbc;
 
-extern "C" vdbc_status vdbc_sample(const vdbc_grid* g, const float* pos, uint64_t n,
-                                   uint32_t filter, float* out, void* stream)
-{
-    clear_error();
-    VdbView v;
-    vdbc_status s = make_view(g, &v);
-    if (s) return s;
-    if ((s = check_samples(pos, n, filter, out))) return s;
-    if (n == 0) return VDBC_OK;
-    hipLaunchKernelGGL((sample_kernel<VdbAcc, VdbView>), dim3((unsigned)((n + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, static_cast<hipStream_t>(stream), v, pos, n, (int)filter, out);
-    return launch_check("vdbc_sample");
-}
-
-extern "C" vdbc_status vdbc_sample_dense(const float* dense, vdbc_dims d, float background,
-                                         const float* pos, uint64_t n, uint32_t filter, float* out,
-                                         void* stream)
-{
-    clear_error();
-    DenseView v;
-    vdbc_status s = make_dense(dense, d, background, &v);
-    if (s) return s;
-    if ((s = check_samples(pos, n, filter, out))) return s;
-    if (n == 0) return VDBC_OK;
-    hipLaunchKernelGGL((sample_kernel<DenseAcc, DenseView>),
-                       dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       static_cast<hipStream_t>(stream), v, pos, n, (int)filter, out);
-    return launch_check("vdbc_sample_dense");
-}
-
-extern "C" vdbc_status vdbc_lookup(const vdbc_grid* g, const int32_t* ijk, uint64_t n, float* out,
-                                   void* stream)
-{
-    clear_error();
-    VdbView v;
-    vdbc_status s = make_view(g, &v);
-    if (s) return s;
-    if (n && (!ijk || !out)) return fail(VDBC_E_INVALID, "null coordinates or output");
-    if (n > (uint64_t)0x7FFFFFFFull * kBlock) return fail(VDBC_E_INVALID, "too many lookups");
-    if (n == 0) return VDBC_OK;
-    hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       static_cast<hipStream_t>(stream), v, ijk, n, out);
-    return launch_check("vdbc_lookup");
-}
-
-static uint64_t compare_regions(uint64_t nx, uint64_t ny, uint64_t nz)
-{
-    return ((nx + 63) / 64) * ((ny + 7) / 8) * ((nz + 7) / 8);
-}
-
-static uint32_t compare_blocks(const VdbView& v)
-{
-    const uint64_t regions = compare_regions((uint64_t)v.nx, (uint64_t)v.ny, (uint64_t)v.nz);
-    return (uint32_t)std::min<uint64_t>(regions, kCmpBlocks);
-}
-
-extern "C" vdbc_status vdbc_compare_workspace(vdbc_dims d, uint64_t* bytes)
-{
-    clear_error();
-    if (!bytes) return fail(VDBC_E_INVALID, "null argument");
-    if (d.nx == 0 || d.ny == 0 || d.nz == 0) return fail(VDBC_E_INVALID, "zero dims");
-    const uint64_t regions = compare_regions(d.nx, d.ny, d.nz);
-    *bytes = 5ull * 8ull * std::min<uint64_t>(regions, kCmpBlocks);
-    return VDBC_OK;
-}
-
-extern "C" vdbc_status vdbc_compare_dense(const vdbc_grid* g, const float* dense, double* out, void* ws,
-                                          uint64_t ws_bytes, void* stream)
-{
-    clear_error();
-    VdbView v;
-    vdbc_status s = make_view(g, &v);
-    if (s) return s;
-    if (!dense || !out) return fail(VDBC_E_INVALID, "null dense volume or output");
-    const uint32_t blocks = compare_blocks(v);
-    if (!ws || ws_bytes < 40ull * blocks)
-        return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace needs %llu bytes", 40ull * blocks);
-    if (reinterpret_cast<uintptr_t>(ws) % 8) return fail(VDBC_E_INVALID, "workspace must be 8-byte aligned");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    double* part = static_cast<double*>(ws);
-    hipLaunchKernelGGL(compare_kernel, dim3(blocks), dim3(kCmpThreads), 0, st, v, dense, part);
-    if ((s = launch_check("compare"))) return s;
-    hipLaunchKernelGGL(compare_fold_kernel, dim3(5), dim3(256), 0, st, part, (int)blocks, out);
-    return launch_check("compare fold");
-}
-
 extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d,
                                              uint64_t* bytes)
 {
@@ -1365,18 +583,6 @@ extern "C" vdbc_status vdbc_majorant_dense(const float* dense, vdbc_dims d, floa
     MediumK m;
     if ((s = make_medium(med, v.nx, v.ny, v.nz, &m))) return s;
     return launch_majorant<DenseAcc>(v, m, C, out, static_cast<hipStream_t>(stream));
-}
-
-extern "C" vdbc_status vdbc_philox(const uint32_t* ctr, const uint32_t* key, uint64_t n,
-                                   uint32_t* out, void* stream)
-{
-    clear_error();
-    if (n && (!ctr || !key || !out)) return fail(VDBC_E_INVALID, "null argument");
-    if (n > (uint64_t)0x7FFFFFFFull * kBlock) return fail(VDBC_E_INVALID, "too many counters");
-    if (n == 0) return VDBC_OK;
-    hipLaunchKernelGGL(philox_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       static_cast<hipStream_t>(stream), ctr, key, n, out);
-    return launch_check("vdbc_philox");
 }
 
 // ---------------------------------------------------------------- batched PT (host)

@@ -212,3 +212,33 @@ def test_binding_structs_match_c_header(tmp_path):
             C.sizeof(vdbc.MediumC), C.sizeof(vdbc.CameraC), C.sizeof(vdbc.GridC),
             C.sizeof(vdbc.EncodeParams), C.sizeof(vdbc.EncodeStats), vdbc.BatchItemC.image.offset]
     assert got == want
+
+
+def test_iso_and_compare_reject_bad_arguments_before_launch(lib):
+    # iso-surface mode and the compression-error call validate everything on
+    # the host, so these run without a GPU
+    g = vdbc.GridC()
+    buf, _ = vdbc.encode(_rand((16, 16, 16), 2), 0.5)
+    assert lib.vdbc_grid_init(C.byref(g), 512, buf.size, buf.ctypes.data) == vdbc.OK
+    cam = vdbc.camera_c(dict(kind=0, width=4, height=4, dir=(0, 0, 1)))
+    for bad in (dict(step=0.0), dict(step=float("nan")), dict(step=1e-6), dict(refine=65),
+                dict(iso=float("inf"))):
+        prm = vdbc.params_c(bad, vdbc.MODE_ISO)
+        assert lib.vdbc_render(C.byref(g), C.byref(cam), None, C.byref(prm), 4096, None, None, 0,
+                               None) == vdbc.E_INVALID, bad
+    prm = vdbc.params_c(dict(), 3)
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), None, C.byref(prm), 4096, None, None, 0,
+                           None) == vdbc.E_INVALID
+    # the iso mode needs no workspace unless counting
+    ws = C.c_uint64(1)
+    assert lib.vdbc_render_workspace(C.byref(vdbc.params_c(dict(), vdbc.MODE_ISO)),
+                                     vdbc.Dims(16, 16, 16), C.byref(ws)) == 0 and ws.value == 0
+    # compare: workspace = 5 doubles per workgroup, 64x8x8 voxels per workgroup
+    for dims, blocks in (((16, 16, 16), 4), ((64, 8, 8), 1), ((65, 9, 9), 8),
+                         ((2048, 2048, 2048), 4096)):
+        assert lib.vdbc_compare_workspace(vdbc.Dims(*dims), C.byref(ws)) == 0
+        assert ws.value == 40 * blocks, dims
+    assert lib.vdbc_compare_workspace(vdbc.Dims(0, 4, 4), C.byref(ws)) == vdbc.E_INVALID
+    assert lib.vdbc_compare_dense(C.byref(g), None, 4096, 8192, 160, None) == vdbc.E_INVALID
+    assert lib.vdbc_compare_dense(C.byref(g), 4096, 8192, 8192, 8, None) == vdbc.E_BUFFER_TOO_SMALL
+    assert lib.vdbc_compare_dense(C.byref(g), 4096, 8192, 8193, 160, None) == vdbc.E_INVALID

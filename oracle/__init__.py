@@ -60,7 +60,8 @@ class Medium(C.Structure):
     _fields_ = [("sigma_scale", C.c_float), ("albedo", C.c_float), ("tf_n", C.c_uint32),
                 ("tf", (C.c_float * 4) * 64), ("tf_lo", C.c_float), ("tf_hi", C.c_float),
                 ("light_dir", C.c_float * 3), ("light_E", C.c_float * 3),
-                ("ambient", C.c_float * 3)]
+                ("ambient", C.c_float * 3), ("env", C.c_void_p), ("env_w", C.c_uint32),
+                ("env_h", C.c_uint32)]
 
 
 class Params(C.Structure):
@@ -270,6 +271,15 @@ def make_medium(med: dict) -> Medium:
     m.light_dir[:] = [float(x) for x in med.get("light_dir", (0.0, 0.0, 1.0))]
     m.light_E[:] = [float(x) for x in med.get("light_E", (0.0, 0.0, 0.0))]
     m.ambient[:] = [float(x) for x in med.get("ambient", (0.0, 0.0, 0.0))]
+    env = med.get("env")
+    if env is not None:
+        # host float32 [h][w][3]; the array is kept alive on the struct
+        e = np.ascontiguousarray(env, dtype=np.float32)
+        if e.ndim != 3 or e.shape[2] != 3:
+            raise ValueError("env must be [h][w][3]")
+        m._env = e
+        m.env = e.ctypes.data
+        m.env_h, m.env_w = e.shape[0], e.shape[1]
     return m
 
 

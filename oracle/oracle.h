@@ -109,6 +109,9 @@ typedef struct {
     float light_dir[3];       /* unit vector pointing towards the light */
     float light_E[3];
     float ambient[3];
+    const float* env;         /* NULL or [env_h][env_w][3] lat-long radiance seen by
+                                 escaping path-tracer rays instead of ambient (R25) */
+    uint32_t env_w, env_h;
 } ref_medium;
 
 typedef struct {

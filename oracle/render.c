@@ -24,6 +24,9 @@
  *    direction (the pixel jitter for b = 0, the isotropic scattering
  *    direction after collision b - 1 otherwise), the rest are its free
  *    flights.  Stream 1 of bounce b is the shadow ray cast from collision b.
+ *  - image-based light (optional, reading R25): an escaping path sees the
+ *    radiance of a lat-long map, nearest texel at u = (atan2(d_z, d_x) + pi) /
+ *    (2 pi), v = acos(d_y) / pi, instead of the constant ambient;
  *  - Russian roulette (optional, reading R24): a segment b >= 1 then opens
  *    with one more draw u; from b = 2 on the path survives with probability
  *    q = min(1, max(beta)) (u < q) and its throughput is divided by q; the
@@ -418,6 +421,26 @@ double ref_transmittance(const ref_field* f, const ref_medium* m, uint32_t C,
     return sum / (double)trials;
 }
 
+/* Radiance seen by a ray leaving the volume along unit direction d: the
+ * constant ambient, or the nearest texel of the lat-long map (R25). */
+static void escape_radiance(const ref_medium* m, const double d[3], double out[3])
+{
+    if (!m->env) {
+        for (int ch = 0; ch < 3; ++ch) out[ch] = (double)m->ambient[ch];
+        return;
+    }
+    double u = (atan2(d[2], d[0]) + PI_D) / (2.0 * PI_D);
+    double y = d[1] < -1.0 ? -1.0 : d[1] > 1.0 ? 1.0 : d[1];
+    double v = acos(y) / PI_D;
+    int64_t tx = (int64_t)floor(u * (double)m->env_w), ty = (int64_t)floor(v * (double)m->env_h);
+    if (tx > (int64_t)m->env_w - 1) tx = (int64_t)m->env_w - 1;
+    if (ty > (int64_t)m->env_h - 1) ty = (int64_t)m->env_h - 1;
+    if (tx < 0) tx = 0;
+    if (ty < 0) ty = 0;
+    const float* p = m->env + 3 * ((uint64_t)ty * m->env_w + (uint64_t)tx);
+    for (int ch = 0; ch < 3; ++ch) out[ch] = (double)p[ch];
+}
+
 int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                   const ref_render_params* r, const uint32_t* pixels, uint64_t n_pixels,
                   double* rgba, double* aov)
@@ -469,7 +492,9 @@ int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                     }
                 }
                 if (!hit) {
-                    for (int ch = 0; ch < 3; ++ch) L[ch] += beta[ch] * (double)m->ambient[ch];
+                    double env[3];
+                    escape_radiance(m, d, env);
+                    for (int ch = 0; ch < 3; ++ch) L[ch] += beta[ch] * env[ch];
                     break;
                 }
                 double x[3] = {o[0] + th * d[0], o[1] + th * d[1], o[2] + th * d[2]};

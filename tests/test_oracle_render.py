@@ -382,3 +382,55 @@ def test_pt_russian_roulette_white_furnace_never_kills():
     cam = scenes.orbit_camera((n, n, n), 8, 8)
     rgba = oracle.render_pt(f, cam, med, dict(spp=8, max_bounces=10_000, seed=4, rr=True))
     np.testing.assert_allclose(rgba[:, :3], np.tile([0.25, 0.5, 1.0], (64, 1)), rtol=1e-12)
+
+
+def _env_unique(w=8, h=4):
+    # texel (y, x) carries (x, y, 100 + x + w y): every texel is distinguishable
+    e = np.zeros((h, w, 3), np.float32)
+    for y in range(h):
+        for x in range(w):
+            e[y, x] = (x, y, 100 + x + w * y)
+    return e
+
+
+@pytest.mark.parametrize("direction,texel", [((1, 0, 0), (4, 2)), ((-1, 0, 0), (7, 2)),
+                                             ((0, 1, 0), (4, 0)), ((0, -1, 0), (4, 3)),
+                                             ((0, 0, 1), (6, 2)), ((0, 0, -1), (2, 2))])
+def test_pt_env_map_axis_directions(direction, texel):
+    # empty volume: every camera ray escapes along the camera direction, so
+    # the pixel is the texel the lat-long mapping assigns to that axis:
+    # u = (atan2(z, x) + pi) / 2pi, v = acos(y) / pi, nearest texel, clamped
+    n = 8
+    f = oracle.DenseField(np.zeros((n, n, n), np.float32), 0.0)
+    env = _env_unique()
+    med = dict(scenes.pt_medium(16.0), env=env)
+    d = np.asarray(direction, np.float64)
+    a = np.roll(d, 1)                       # two axes orthogonal to d
+    b = np.cross(d, a)
+    cam = dict(kind=0, width=4, height=4, lower_left=tuple(-20.0 * d - a - b),
+               du=tuple(0.5 * a), dv=tuple(0.5 * b), dir=tuple(d))
+    rgba = oracle.render_pt(f, cam, med, dict(spp=3, max_bounces=2, seed=1))
+    want = env[texel[1], texel[0]].astype(np.float64)
+    assert np.array_equal(rgba[:, :3], np.tile(want, (16, 1)))
+
+
+def test_pt_constant_env_map_equals_ambient():
+    # a constant map is the ambient term: same draws, same sums, bit for bit
+    n = 16
+    v = _vol((n, n, n), 21, zero=0.3)
+    buf, _ = oracle.encode(v, 0.5)
+    f = oracle.VdbField(buf)
+    med = scenes.pt_medium(48.0)
+    env = np.broadcast_to(np.asarray(med["ambient"], np.float32), (6, 12, 3)).copy()
+    cam = scenes.orbit_camera((n, n, n), 10, 9)
+    prm = dict(spp=4, max_bounces=6, seed=17)
+    a = oracle.render_pt(f, cam, med, prm)
+    b = oracle.render_pt(f, cam, dict(med, env=env), prm)
+    assert np.array_equal(a, b)
+    # a brighter map adds exactly (escaped throughput) x 1 per channel: no
+    # pixel loses light and pixels whose camera rays all escape gain 1
+    c = oracle.render_pt(f, cam, dict(med, env=env + 1.0), prm)
+    assert np.all(c[:, :3] >= a[:, :3]) and np.any(c[:, :3] > a[:, :3])
+    clear = a[:, 3] == 0.0
+    assert clear.any()
+    np.testing.assert_allclose(c[clear, :3] - a[clear, :3], 1.0, rtol=1e-6)

@@ -182,6 +182,11 @@ typedef struct {
     float light_dir[3];     /* unit vector towards the directional light */
     float light_E[3];       /* its irradiance */
     float ambient[3];       /* constant ambient radiance added on escape */
+    const float* env;       /* NULL, or device float32 [env_h][env_w][3]: lat-long radiance
+                               an escaping path-tracer ray sees instead of `ambient`
+                               (image-based light, Section 4): nearest texel at
+                               u = (atan2(d_z, d_x) + pi) / (2 pi), v = acos(d_y) / pi */
+    uint32_t env_w, env_h;  /* texels (>= 1 each when env is set) */
 } vdbc_medium;
 
 enum { VDBC_MODE_EA = 0u, VDBC_MODE_PT = 1u, VDBC_MODE_ISO = 2u };

@@ -336,7 +336,31 @@ struct MediumK {
     float tf_lo, tf_inv;  // (tf_n - 1) / (tf_hi - tf_lo)
     float4 tf[64];
     float light[3], light_E[3], ambient[3];
+    const float* env;  // lat-long escape radiance [env_h][env_w][3], or null
+    int env_w, env_h;
 };
+
+// Radiance seen by a ray leaving the volume along unit direction d: the
+// constant ambient, or the nearest texel of the lat-long map at
+// u = (atan2(d_z, d_x) + pi) / 2 pi, v = acos(d_y) / pi.
+__device__ __forceinline__ void escape_radiance(const MediumK& m, const float d[3], float& r, float& g,
+                                                float& b)
+{
+    if (!m.env) {
+        r = m.ambient[0];
+        g = m.ambient[1];
+        b = m.ambient[2];
+        return;
+    }
+    const float u = (atan2f(d[2], d[0]) + 3.14159265358979323846f) * 0.159154943091895335769f;
+    const float v = acosf(fminf(fmaxf(d[1], -1.0f), 1.0f)) * 0.318309886183790671538f;
+    const int tx = min(max((int)floorf(u * (float)m.env_w), 0), m.env_w - 1);
+    const int ty = min(max((int)floorf(v * (float)m.env_h), 0), m.env_h - 1);
+    const float* p = m.env + 3 * ((size_t)ty * (size_t)m.env_w + (size_t)tx);
+    r = p[0];
+    g = p[1];
+    b = p[2];
+}
 
 __device__ __forceinline__ float4 tf_eval(const MediumK& m, float s)
 {

@@ -313,9 +313,11 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                 flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
                 shadow = true;
             } else {
-                L0 = fmaf(b0, m.ambient[0], L0);
-                L1 = fmaf(b1, m.ambient[1], L1);
-                L2 = fmaf(b2, m.ambient[2], L2);
+                float e0, e1, e2;
+                escape_radiance(m, f.d, e0, e1, e2);
+                L0 = fmaf(b0, e0, L0);
+                L1 = fmaf(b1, e1, L1);
+                L2 = fmaf(b2, e2, L2);
                 path_done = true;
             }
         } else {

@@ -277,6 +277,13 @@ static vdbc_status make_medium(const vdbc_medium* m, int nx, int ny, int nz, Med
         k->light_E[a] = m->light_E[a];
         k->ambient[a] = m->ambient[a];
     }
+    if (m->env) {
+        if (m->env_w == 0 || m->env_h == 0 || (uint64_t)m->env_w * m->env_h > (1ull << 28))
+            return fail(VDBC_E_INVALID, "env map needs 1 <= env_w * env_h <= 2^28 texels");
+        k->env = m->env;
+        k->env_w = (int)m->env_w;
+        k->env_h = (int)m->env_h;
+    }
     return VDBC_OK;
 }
 

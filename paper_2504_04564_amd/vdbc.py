@@ -59,7 +59,8 @@ class MediumC(C.Structure):
     _fields_ = [("sigma_scale", C.c_float), ("albedo", C.c_float), ("tf_n", C.c_uint32),
                 ("tf", (C.c_float * 4) * 64), ("tf_lo", C.c_float), ("tf_hi", C.c_float),
                 ("light_dir", C.c_float * 3), ("light_E", C.c_float * 3),
-                ("ambient", C.c_float * 3)]
+                ("ambient", C.c_float * 3), ("env", C.c_void_p), ("env_w", C.c_uint32),
+                ("env_h", C.c_uint32)]
 
 
 class RenderParamsC(C.Structure):
@@ -277,6 +278,15 @@ def medium_c(med: dict) -> MediumC:
     m.light_dir[:] = [float(x) for x in med.get("light_dir", (0.0, 0.0, 1.0))]
     m.light_E[:] = [float(x) for x in med.get("light_E", (0.0, 0.0, 0.0))]
     m.ambient[:] = [float(x) for x in med.get("ambient", (0.0, 0.0, 0.0))]
+    env = med.get("env")
+    if env is not None:
+        # device float32 tensor [h][w][3]; kept alive on the struct
+        if env.dim() != 3 or env.shape[2] != 3 or not env.is_cuda:
+            raise ValueError("env must be a device tensor [h][w][3]")
+        e = env.to(_torch().float32).contiguous()
+        m._env = e
+        m.env = e.data_ptr()
+        m.env_h, m.env_w = e.shape[0], e.shape[1]
     return m
 
 

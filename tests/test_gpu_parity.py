@@ -408,3 +408,55 @@ def test_pt_russian_roulette_white_furnace():
                       vdbc.MODE_PT).cpu().numpy()
     np.testing.assert_allclose(img[..., :3], np.broadcast_to([0.25, 0.5, 1.0], img[..., :3].shape),
                                rtol=1e-6)
+
+
+def _env_map(w=64, h=32, seed=4):
+    # smooth sky: brighter towards +y, with a warm patch and mild noise
+    rng = np.random.default_rng(seed)
+    v = (np.arange(h) + 0.5)[:, None] / h
+    u = (np.arange(w) + 0.5)[None, :] / w
+    sky = np.stack([0.3 + 0.7 * (1 - v) + 0 * u, 0.35 + 0.6 * (1 - v) + 0 * u,
+                    0.5 + 0.5 * (1 - v) + 0 * u], -1)
+    sky += 1.5 * np.exp(-((u - 0.3) ** 2 + (v - 0.35) ** 2) / 0.01)[..., None] * [1.0, 0.7, 0.3]
+    sky += 0.02 * rng.random(sky.shape)
+    return sky.astype(np.float32)
+
+
+def test_pt_image_based_light_vs_oracle():
+    v = synth.mid_volume(n=96)
+    buf, _ = vdbc.encode(v, 0.25)
+    cam, med, prm = _pt_scene(96, 48, 40, 4)
+    env = _env_map()
+    want = oracle.render_pt(oracle.VdbField(buf), cam, dict(med, env=env), prm)
+    got = vdbc.render(vdbc.Grid(buf), cam, dict(med, env=_cuda(env)), prm, vdbc.MODE_PT)
+    assert relmse(got.cpu().numpy().reshape(-1, 4), want) <= 1e-4
+    want_d = oracle.render_pt(oracle.DenseField(v, 0.0), cam, dict(med, env=env), prm)
+    got_d = vdbc.render(_dense_t(v), cam, dict(med, env=_cuda(env)), prm, vdbc.MODE_PT,
+                        background=0.0)
+    assert relmse(got_d.cpu().numpy().reshape(-1, 4), want_d) <= 1e-4
+    # a constant map is the ambient term, bit for bit
+    const = np.broadcast_to(np.asarray(med["ambient"], np.float32), (8, 16, 3)).copy()
+    a = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).clone()
+    b = vdbc.render(vdbc.Grid(buf), cam, dict(med, env=_cuda(const)), prm, vdbc.MODE_PT)
+    assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+@pytest.mark.parametrize("direction,texel", [((1, 0, 0), (4, 2)), ((-1, 0, 0), (7, 2)),
+                                             ((0, 1, 0), (4, 0)), ((0, -1, 0), (4, 3)),
+                                             ((0, 0, 1), (6, 2)), ((0, 0, -1), (2, 2))])
+def test_pt_env_map_axis_directions(direction, texel):
+    n = 8
+    env = np.zeros((4, 8, 3), np.float32)
+    for y in range(4):
+        for x in range(8):
+            env[y, x] = (x, y, 100 + x + 8 * y)
+    d = np.asarray(direction, np.float64)
+    a = np.roll(d, 1)
+    b = np.cross(d, a)
+    cam = dict(kind=0, width=4, height=4, lower_left=tuple(-20.0 * d - a - b),
+               du=tuple(0.5 * a), dv=tuple(0.5 * b), dir=tuple(d))
+    med = dict(scenes.pt_medium(16.0), env=_cuda(env))
+    img = vdbc.render(_dense_t(np.zeros((n, n, n), np.float32)), cam, med,
+                      dict(spp=3, max_bounces=2, seed=1), vdbc.MODE_PT, background=0.0)
+    assert np.array_equal(img.cpu().numpy()[..., :3].reshape(-1, 3),
+                          np.tile(env[texel[1], texel[0]], (16, 1)))

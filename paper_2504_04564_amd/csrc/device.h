@@ -374,6 +374,17 @@ __device__ __forceinline__ float4 tf_eval(const MediumK& m, float s)
                        lerp(a.w, b.w, fr));
 }
 
+// tf_alpha with the control points read from `tf` (an LDS copy of m.tf).
+__device__ __forceinline__ float tf_alpha_at(const float4* tf, const MediumK& m, float s)
+{
+    float pos = (s - m.tf_lo) * m.tf_inv;
+    pos = fminf(fmaxf(pos, 0.0f), (float)(m.tf_n - 1));
+    int i = (int)pos;
+    i = i > m.tf_n - 2 ? m.tf_n - 2 : i;
+    const float fr = pos - (float)i;
+    return lerp(tf[i].w, tf[i + 1].w, fr);
+}
+
 __device__ __forceinline__ float tf_alpha(const MediumK& m, float s)
 {
     float pos = (s - m.tf_lo) * m.tf_inv;

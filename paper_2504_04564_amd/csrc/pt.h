@@ -238,11 +238,12 @@ __device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v 
 // otherwise), then its free flights and accept tests; stream 1 of bounce b is
 // the shadow ray from collision b.  Results depend only on the pixel, not on
 // the lane, tile shape or launch.
-template <class Acc, bool AOV>
+template <class Acc, bool AOV, bool ENV>
 __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const CameraK& cam,
                                         const MediumK& m, const PtArgs& g,
                                         const float* __restrict__ maj, const uint32_t* cbits,
-                                        int bx, int by, TileShared& ts, float* __restrict__ image,
+                                        int bx, int by, TileShared& ts, const float4* tf_lds,
+                                        float* __restrict__ image,
                                         float* __restrict__ aov, uint32_t& nsamp, uint32_t& ncell)
 {
     const int tid = threadIdx.x;
@@ -291,7 +292,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
         float sv = 0.0f;
         const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
         if (tentative == kFlightYield) continue;
-        const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha(m, sv);
+        const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha_at(tf_lds, m, sv);
         if (tentative && !hit) continue;    // null collision: keep tracking
         bool path_done = false, next_bounce = false;
         if (!shadow) {
@@ -314,7 +315,13 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                 shadow = true;
             } else {
                 float e0, e1, e2;
-                escape_radiance(m, f.d, e0, e1, e2);
+                if (ENV) {   // the map's lookup only where a map is bound
+                    escape_radiance(m, f.d, e0, e1, e2);
+                } else {
+                    e0 = m.ambient[0];
+                    e1 = m.ambient[1];
+                    e2 = m.ambient[2];
+                }
                 L0 = fmaf(b0, e0, L0);
                 L1 = fmaf(b1, e1, L1);
                 L2 = fmaf(b2, e2, L2);
@@ -390,7 +397,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
     __syncthreads();
 }
 
-template <class Acc, class View, bool COUNT, bool AOV>
+template <class Acc, class View, bool COUNT, bool AOV, bool ENV>
 __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
                                                     const float* __restrict__ maj,
                                                     const uint32_t* __restrict__ coarse,
@@ -402,6 +409,9 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
     extern __shared__ uint32_t cbits[];
     __shared__ TileShared ts;
     for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = coarse[i];
+    // the TF control points in LDS: every tentative collision reads two of them
+    __shared__ float4 tf_lds[64];
+    for (int i = threadIdx.x; i < m.tf_n; i += kBlock) tf_lds[i] = m.tf[i];
     __syncthreads();
     Acc acc{view};
     acc.reset();
@@ -416,8 +426,8 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
         __syncthreads();
         const uint32_t t = s_tile;   // pt_tile's barriers order this read before the next write
         if (t >= tiles) break;
-        pt_tile<Acc, AOV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
-                          (int)(t / tiles_x), ts, image, aov, nsamp, ncell);
+        pt_tile<Acc, AOV, ENV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
+                          (int)(t / tiles_x), ts, tf_lds, image, aov, nsamp, ncell);
     }
     if (COUNT) {
         block_count(nsamp, counter);
@@ -453,6 +463,7 @@ __global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __
     extern __shared__ uint32_t cbits[];
     __shared__ uint32_t s_item;
     __shared__ TileShared ts;
+    __shared__ float4 tf_lds[64];
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1u);
@@ -465,13 +476,14 @@ __global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __
         const PtArgs g = D->g;
         const CameraK cam = D->cam;
         for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = D->coarse[i];
+        for (int i = threadIdx.x; i < D->med.tf_n; i += kBlock) tf_lds[i] = D->med.tf[i];
         __syncthreads();
         VdbAcc acc{D->view};
         acc.reset();
         uint32_t ns = 0, nc = 0;
-        pt_tile<VdbAcc, false>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
+        pt_tile<VdbAcc, false, true>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
                                (int)(tile % (uint32_t)D->tiles_x), (int)(tile / (uint32_t)D->tiles_x), ts,
-                               D->image, nullptr, ns, nc);
+                               tf_lds, D->image, nullptr, ns, nc);
     }
 }
 

@@ -507,16 +507,20 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
         grid = dim3((unsigned)std::min<uint64_t>(tiles, (uint64_t)device_cus() * kPtBlocksPerCu));
     }
     uint32_t* queue = reinterpret_cast<uint32_t*>(counter + 2);
-#define PT_LAUNCH(CNT, AO)                                                                     \
-    hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO>), grid, dim3(kBlock), lds, st, v, cam, m, \
+#define PT_LAUNCH(CNT, AO, EN)                                                                     \
+    hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO, EN>), grid, dim3(kBlock), lds, st, v, cam, m, \
                        g, maj, coarse, image, aov, counter, queue)
+#define PT_LAUNCH_ENV(CNT, AO)           \
+    if (m.env) PT_LAUNCH(CNT, AO, true); \
+    else PT_LAUNCH(CNT, AO, false)
     if (count) {
-        if (aov) PT_LAUNCH(true, true);
-        else PT_LAUNCH(true, false);
+        if (aov) PT_LAUNCH_ENV(true, true);
+        else PT_LAUNCH_ENV(true, false);
     } else {
-        if (aov) PT_LAUNCH(false, true);
-        else PT_LAUNCH(false, false);
+        if (aov) PT_LAUNCH_ENV(false, true);
+        else PT_LAUNCH_ENV(false, false);
     }
+#undef PT_LAUNCH_ENV
 #undef PT_LAUNCH
     return launch_check("pt render");
 }
@@ -719,10 +723,15 @@ static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
         const PtArgs& g = b->gs[i];
         const uint32_t tiles = (uint32_t)(b->tiles_x[i] * b->tiles_y[i]);
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, b->d_counter);
-        hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false>),
-                           dim3(std::min<uint32_t>(tiles, (uint32_t)b->grid_blocks)), dim3(kBlock),
-                           4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                           b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter);
+        const dim3 grid(std::min<uint32_t>(tiles, (uint32_t)b->grid_blocks));
+        if (b->meds[i].env)
+            hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, true>), grid, dim3(kBlock),
+                               4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter);
+        else
+            hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, false>), grid, dim3(kBlock),
+                               4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter);
         if ((s = launch_check("per-volume render"))) return s;
     }
     return VDBC_OK;

@@ -187,7 +187,11 @@ def main():
     encode_s = time.time() - t
     log(f"[bench] encoded {buf.size / 1e6:.1f} MB in {encode_s:.2f}s "
         f"(achieved rate {st['achieved_rate']:.4f})")
+    torch.cuda.synchronize()
+    t = time.time()
     grid = vdbc.Grid(buf)
+    torch.cuda.synchronize()
+    upload_s = time.time() - t
     dense = torch.from_numpy(vol).cuda()
     cam = scenes.orbit_camera((n, n, n), W, H)
     med = scenes.pt_medium(64.0)
@@ -328,6 +332,7 @@ def main():
         "cpu_baseline": cpu,
         "relmse_vs_oracle": rel,
         "encode_s": round(encode_s, 3),
+        "upload_s": round(upload_s, 4),
         "majorant_ms": round(maj_ms, 4),
     }
     line.update(extras)

@@ -272,7 +272,44 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunk
     grad[i] = s;
 }
 
-// db[co] = sum_p dz[p][co]; one workgroup per channel, fixed-order tree sum.
+// partial[chunk][c] = sum of dz[p][c] over the chunk's kWgradChunk output
+// pixels: thread (g, c) takes channel c of every G-th pixel (G = 256 / coutp
+// pixel groups), so a wave reads contiguous channel rows; the G group sums
+// are added in a fixed order.
+__global__ __launch_bounds__(kThreads) void bias_partial_kernel(const uint16_t* __restrict__ dz, int coutp,
+                                                                int64_t P, float* __restrict__ partial)
+{
+    __shared__ float s[kThreads];
+    const int G = kThreads / coutp;
+    const int t = threadIdx.x, c = t % coutp, g = t / coutp;
+    float a = 0.0f;
+    if (g < G) {
+        const int64_t p0 = (int64_t)blockIdx.x * kWgradChunk;
+        const int64_t p1 = p0 + kWgradChunk < P ? p0 + kWgradChunk : P;
+        for (int64_t p = p0 + g; p < p1; p += G) a += bf2f(dz[p * coutp + c]);
+    }
+    s[t] = a;
+    __syncthreads();
+    if (t < coutp) {
+        float r = 0.0f;
+        for (int j = 0; j < G; ++j) r += s[j * coutp + t];
+        partial[(int64_t)blockIdx.x * coutp + t] = r;
+    }
+}
+
+// db[c] = sum over chunks (in order) of partial[chunk][c].
+__global__ __launch_bounds__(kThreads) void bias_reduce_kernel(const float* __restrict__ partial, int chunks,
+                                                               int coutp, int cout, float* __restrict__ db)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cout) return;
+    float r = 0.0f;
+    for (int k = 0; k < chunks; ++k) r += partial[(int64_t)k * coutp + c];
+    db[c] = r;
+}
+
+// db[co] = sum_p dz[p][co]; one workgroup per channel, fixed-order tree sum
+// (for more than 256 padded channels).
 __global__ __launch_bounds__(kThreads) void bias_grad_kernel(const uint16_t* __restrict__ dz, int coutp,
                                                              int64_t P, float* __restrict__ db)
 {
@@ -498,7 +535,15 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
         hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks((uint64_t)cout * K)), dim3(kThreads), 0, st, partial,
                        (int)chunks, mt * 16, cout, K, dw);
-    hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(kThreads), 0, st, dz, coutp, P, db);
+    if (coutp <= kThreads) {
+        // the weight-gradient partials are reduced by now (stream order): the
+        // same buffer holds chunks x coutp bias partials (<= chunks x mpad x K)
+        hipLaunchKernelGGL(bias_partial_kernel, dim3(chunks), dim3(kThreads), 0, st, dz, coutp, P, partial);
+        hipLaunchKernelGGL(bias_reduce_kernel, dim3((unsigned)((cout + kThreads - 1) / kThreads)), dim3(kThreads),
+                           0, st, partial, (int)chunks, coutp, cout, db);
+    } else {
+        hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(kThreads), 0, st, dz, coutp, P, db);
+    }
     return check("conv3x3 weight gradient");
 }
 

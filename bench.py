@@ -130,8 +130,8 @@ def main():
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--train-steps", type=int, default=1500, help="denoiser workload: Adam steps")
     ap.add_argument("--denoiser-full", action="store_true",
-                    help="denoiser workload: the full recipe (2,000 crops of 512^2, 1024-spp targets; "
-                         "about ten minutes) instead of 96 crops of 256^2 with 512-spp targets")
+                    help="denoiser workload: 1,000 crops of 512^2 with 1024-spp targets from 256^3..512^3 "
+                         "clouds (about 14 minutes) instead of 96 crops of 256^2 with 512-spp targets")
     ap.add_argument("--workload", default="mid",
                     choices=("mid", "paper", "denoiser", "batch", "quality", "worstcase", "iso", "ea"),
                     help="mid: the headline 512^3 frame; paper: 1987x1351x2449 rate sweep; "

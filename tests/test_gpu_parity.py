@@ -460,3 +460,16 @@ def test_pt_env_map_axis_directions(direction, texel):
                       dict(spp=3, max_bounces=2, seed=1), vdbc.MODE_PT, background=0.0)
     assert np.array_equal(img.cpu().numpy()[..., :3].reshape(-1, 3),
                           np.tile(env[texel[1], texel[0]], (16, 1)))
+
+
+@pytest.mark.parametrize("C", [4, 32, 64])
+def test_pt_macrocell_sizes_vs_oracle(C):
+    # the coarse-block skip covers 2^lf macrocells with C * 2^lf <= 32: lf = 3
+    # at C = 4, none above C = 32; each must follow the oracle's uniform walk
+    v = synth.mid_volume(n=80)
+    buf, _ = vdbc.encode(v, 0.25)
+    cam, med, prm = _pt_scene(80, 40, 36, 3)
+    prm = dict(prm, macrocell=C)
+    want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm)
+    got = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
+    assert relmse(got, want) <= 1e-4

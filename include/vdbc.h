@@ -204,8 +204,8 @@ enum {
 
 typedef struct {
     uint32_t mode;          /* VDBC_MODE_EA or VDBC_MODE_PT */
-    uint32_t spp;           /* PT samples per pixel (>= 1) */
-    uint32_t max_bounces;   /* PT scattering events per path (>= 1) */
+    uint32_t spp;           /* PT samples per pixel, 1..65536 */
+    uint32_t max_bounces;   /* PT scattering events per path, 1..65535 */
     uint32_t macrocell;     /* PT majorant cell edge in voxels: 4, 8, 16, 32 or 64 */
     uint32_t flags;         /* VDBC_RENDER_* */
     float step;             /* EA step in voxels (> 0) */
@@ -262,7 +262,7 @@ typedef struct {
     vdbc_grid grid;          /* the volume (device buffer + host header copy) */
     vdbc_camera camera;
     vdbc_medium medium;
-    uint32_t spp, max_bounces;
+    uint32_t spp, max_bounces;  /* as in vdbc_render_params: 1..65536, 1..65535 */
     uint64_t seed;
     uint32_t frame;
     float* image;            /* device float32 [height][width][4] */

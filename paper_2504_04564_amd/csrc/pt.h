@@ -8,6 +8,10 @@ namespace vdbc {
 
 // Resident PT workgroups per compute unit (the kernel's launch bounds).
 constexpr int kPtBlocksPerCu = 4;
+// Largest samples per pixel (256 x spp work units per tile fit 32 bits) and
+// bounces per path (the bounce is a 16-bit field of the Philox counter).
+constexpr uint32_t kMaxSpp = 1u << 16;
+constexpr uint32_t kMaxBounces = 0xFFFFu;
 
 // ---------------------------------------------------------------- PT
 

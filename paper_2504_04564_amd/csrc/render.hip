@@ -467,7 +467,10 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
 #undef EA_LAUNCH
         return launch_check("ea render");
     }
-    if (r->spp == 0 || r->max_bounces == 0) return fail(VDBC_E_INVALID, "spp and max_bounces must be >= 1");
+    // the tile's work units (256 x spp) are 32-bit and the bounce is a
+    // 16-bit field of the random-number counter
+    if (r->spp == 0 || r->spp > kMaxSpp || r->max_bounces == 0 || r->max_bounces > kMaxBounces)
+        return fail(VDBC_E_INVALID, "need 1 <= spp <= %u and 1 <= max_bounces <= %u", kMaxSpp, kMaxBounces);
     {
         const double l = std::sqrt((double)med->light_dir[0] * med->light_dir[0] +
                                    (double)med->light_dir[1] * med->light_dir[1] +
@@ -656,8 +659,9 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         if (!s) s = make_camera(&it.camera, &cam);
         if (!s) s = make_medium(&it.medium, v.nx, v.ny, v.nz, &m);
         if (s) return fail(s, "batch item %u: %s", i, vdbc_last_error());
-        if (it.spp == 0 || it.max_bounces == 0 || !it.image)
-            return fail(VDBC_E_INVALID, "batch item %u: spp, max_bounces >= 1 and an image are required", i);
+        if (it.spp == 0 || it.spp > kMaxSpp || it.max_bounces == 0 || it.max_bounces > kMaxBounces || !it.image)
+            return fail(VDBC_E_INVALID, "batch item %u: need 1 <= spp <= %u, 1 <= max_bounces <= %u and an image", i,
+                        kMaxSpp, kMaxBounces);
         const double l = std::sqrt((double)it.medium.light_dir[0] * it.medium.light_dir[0] +
                                    (double)it.medium.light_dir[1] * it.medium.light_dir[1] +
                                    (double)it.medium.light_dir[2] * it.medium.light_dir[2]);

@@ -326,7 +326,7 @@ def test_pt_white_furnace_and_zero_density():
     cam = scenes.orbit_camera((n, n, n), 24, 24)
     med = dict(sigma_scale=40.0, albedo=1.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
                light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(0.25, 0.5, 1.0))
-    img = vdbc.render(vdbc.Grid(buf), cam, med, dict(spp=4, max_bounces=100000, seed=3),
+    img = vdbc.render(vdbc.Grid(buf), cam, med, dict(spp=4, max_bounces=65535, seed=3),
                       vdbc.MODE_PT).cpu().numpy()
     np.testing.assert_allclose(img[..., :3], np.broadcast_to([0.25, 0.5, 1.0], img[..., :3].shape),
                                rtol=1e-6)
@@ -404,7 +404,7 @@ def test_pt_russian_roulette_white_furnace():
     med = dict(sigma_scale=40.0, albedo=1.0, tf=[(1, 1, 1, 0), (1, 1, 1, 1)],
                light_dir=(0, 1, 0), light_E=(0, 0, 0), ambient=(0.25, 0.5, 1.0))
     img = vdbc.render(vdbc.Grid(buf), cam, med,
-                      dict(spp=4, max_bounces=100000, seed=3, flags=vdbc.RENDER_RR),
+                      dict(spp=4, max_bounces=65535, seed=3, flags=vdbc.RENDER_RR),
                       vdbc.MODE_PT).cpu().numpy()
     np.testing.assert_allclose(img[..., :3], np.broadcast_to([0.25, 0.5, 1.0], img[..., :3].shape),
                                rtol=1e-6)

@@ -242,3 +242,23 @@ def test_iso_and_compare_reject_bad_arguments_before_launch(lib):
     assert lib.vdbc_compare_dense(C.byref(g), None, 4096, 8192, 160, None) == vdbc.E_INVALID
     assert lib.vdbc_compare_dense(C.byref(g), 4096, 8192, 8192, 8, None) == vdbc.E_BUFFER_TOO_SMALL
     assert lib.vdbc_compare_dense(C.byref(g), 4096, 8192, 8193, 160, None) == vdbc.E_INVALID
+
+
+def test_path_tracer_limits_rejected_before_launch(lib):
+    g = vdbc.GridC()
+    buf, _ = vdbc.encode(_rand((16, 16, 16), 3), 0.5)
+    assert lib.vdbc_grid_init(C.byref(g), 512, buf.size, buf.ctypes.data) == vdbc.OK
+    cam = vdbc.camera_c(dict(kind=0, width=4, height=4, dir=(0, 0, 1)))
+    med = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)], light_dir=(0, 0, 1)))
+    ws = C.c_uint64(0)
+    for bad in (dict(spp=0), dict(spp=65537), dict(max_bounces=0), dict(max_bounces=65536)):
+        prm = vdbc.params_c(dict(dict(spp=1), **bad), vdbc.MODE_PT)
+        assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
+        assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(prm), 4096, None,
+                               8192, ws.value, None) == vdbc.E_INVALID, bad
+    env_bad = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)],
+                                 light_dir=(0, 0, 1)))
+    env_bad.env, env_bad.env_w, env_bad.env_h = 4096, 0, 4
+    prm = vdbc.params_c(dict(spp=1), vdbc.MODE_PT)
+    assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(env_bad), C.byref(prm), 4096, None,
+                           8192, ws.value, None) == vdbc.E_INVALID

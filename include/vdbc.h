@@ -164,7 +164,7 @@ vdbc_status vdbc_compare_dense(const vdbc_grid* g, const float* dense, double* o
 
 typedef struct {
     uint32_t kind;          /* 0 orthographic, 1 pinhole */
-    uint32_t width, height;
+    uint32_t width, height;  /* pixels; width * height <= 2^31 */
     float origin[3];        /* pinhole eye (index space) */
     float lower_left[3];    /* pinhole: direction towards image point (0,0);
                                orthographic: ray origin of image point (0,0) */

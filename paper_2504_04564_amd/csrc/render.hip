@@ -308,8 +308,9 @@ static vdbc_status make_camera(const vdbc_camera* c, CameraK* k)
             return fail(VDBC_E_INVALID, "non-finite camera vector");
     if (c->kind == 0 && c->dir[0] == 0.0f && c->dir[1] == 0.0f && c->dir[2] == 0.0f)
         return fail(VDBC_E_INVALID, "orthographic camera needs a non-zero direction");
-    if (c->width == 0 || c->height == 0 || c->width > 65536 * kTile || c->height > 65535u * kTile)
-        return fail(VDBC_E_INVALID, "bad image size");
+    if (c->width == 0 || c->height == 0 || c->width > 65536 * kTile || c->height > 65535u * kTile ||
+        (uint64_t)c->width * c->height > (1ull << 31))
+        return fail(VDBC_E_INVALID, "bad image size (1..2^31 pixels)");
     k->kind = (int)c->kind;
     k->width = (int)c->width;
     k->height = (int)c->height;

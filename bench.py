@@ -133,11 +133,12 @@ def main():
                     help="denoiser workload: 1,000 crops of 512^2 with 1024-spp targets from 256^3..512^3 "
                          "clouds (about 14 minutes) instead of 96 crops of 256^2 with 512-spp targets")
     ap.add_argument("--workload", default="mid",
-                    choices=("mid", "paper", "denoiser", "batch", "quality", "worstcase", "iso", "ea"),
+                    choices=("mid", "paper", "denoiser", "batch", "quality", "worstcase", "iso", "ea", "tune"),
                     help="mid: the headline 512^3 frame; paper: 1987x1351x2449 rate sweep; "
                          "denoiser: train and evaluate the learned denoiser; batch: 64 volumes; "
                          "quality: MSE/PSNR vs rate and metric; worstcase: lossless dense noise; "
-                         "iso: iso-surface marcher; ea: emission-absorption marcher")
+                         "iso: iso-surface marcher; ea: emission-absorption marcher; "
+                         "tune: the render autotuner on the headline frame")
     ap.add_argument("--worst-max", type=int, default=1024,
                     help="worstcase workload: largest noise cube edge (2048 = the paper's 34 GB)")
     args = ap.parse_args()

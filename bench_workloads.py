@@ -342,3 +342,26 @@ def ea(args, torch, vdbc, synth, scenes, log):
             "value": rows[best]["fps"],
             "config": {"workload": f"fbm-cloud-{n}^3-1to10-ea-{W}x{H}-step0.5", "vdb_variant": best},
             "vdb_over_dense": round(rows["dense"]["ms"] / rows[best]["ms"], 4), "rows": rows}
+
+
+def tune(args, torch, vdbc, synth, scenes, log):
+    """The render autotuner on the headline frame (512^3 cloud at 1:10,
+    1024^2 x 16 spp, <= 8 bounces): every (macrocell, wave tile, accessor
+    cache policy) candidate timed, the fastest kept."""
+    from paper_2504_04564_amd import autotune
+    n = args.size
+    M = scenes.MID
+    vol = synth.mid_volume(n=n)
+    buf, _ = vdbc.encode(vol, args.rate)
+    g = vdbc.Grid(buf)
+    cam = scenes.orbit_camera((n, n, n), M["width"], M["height"])
+    med = scenes.pt_medium(64.0)
+    prm = dict(spp=M["spp"], max_bounces=M["max_bounces"], seed=M["seed"])
+    best, rows = autotune.tune_render(g, cam, med, prm, reps=5)
+    for r in sorted(rows, key=lambda x: x["ms"]):
+        log(f"[tune] {r}")
+    return {"metric": "render autotuner: fastest PT launch configuration", "unit": "ms",
+            "value": round(best["ms"], 3), "higher_is_better": False,
+            "config": {"workload": f"fbm-cloud-{n}^3-1to10-pt-1024x1024x16spp-8bounces",
+                       "space": {k: list(v) for k, v in autotune.RENDER_SPACE.items()}},
+            "best": best, "candidates": rows}

@@ -195,11 +195,16 @@ enum {
                                      nodes (result-preserving; EA needs alpha_TF(B) == 0) */
     VDBC_RENDER_COUNT = 2u,       /* count trilinear samples into the workspace */
     VDBC_RENDER_KEEP_MAJORANT = 4u, /* PT: reuse the majorant grid already in ws */
-    VDBC_RENDER_RR = 8u            /* PT: Russian roulette (Section 4): from bounce 2 on a
+    VDBC_RENDER_RR = 8u,           /* PT: Russian roulette (Section 4): from bounce 2 on a
                                       path survives with q = min(1, max throughput) and
                                       survivors carry throughput / q; the survival draw
                                       precedes the two direction draws of each segment's
                                       stream (bounce >= 1) */
+    VDBC_RENDER_CACHE_NONE = 16u,  /* PT, VDB: no per-thread cache (every lookup descends
+                                      from the root) */
+    VDBC_RENDER_CACHE_LEAF = 32u   /* PT, VDB: cache the last leaf only (default, neither
+                                      flag: the last leaf and the last lower node).  The
+                                      image does not depend on the cache policy. */
 };
 
 typedef struct {

@@ -4,9 +4,10 @@ Times every candidate of a small search space on the device (one warm-up,
 median of `reps` HIP-event timings) and keeps the fastest; choices are
 persisted to a JSON file keyed by workload class so later runs reuse them.
 Candidates only change launch geometry (wave tile shape, persistent grid
-size) or the majorant cell size; the first two leave every image
-bit-identical, the cell size changes the estimator's random stream but not
-its expectation.
+size), the VDB accessor's per-thread cache policy (none, last leaf, last leaf
+and last lower node) or the majorant cell size; all but the cell size leave
+every image bit-identical, the cell size changes the estimator's random
+stream but not its expectation.
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ import numpy as np
 
 from . import vdbc
 
-RENDER_SPACE = {"macrocell": (8, 16, 32), "tile_w": (8, 16, 32)}
+RENDER_SPACE = {"macrocell": (8, 16, 32), "tile_w": (8, 16, 32), "cache": (0, 1, 2)}
 BATCH_SPACE = {"macrocell": (8, 16), "tile_w": (8, 16), "blocks_per_cu": (2, 4, 8),
                "persistent": (1,)}
 
@@ -61,15 +62,19 @@ def save(path: str, table: dict):
 
 def tune_render(field, camera: dict, medium: dict, params: dict, background=None,
                 space: dict | None = None, reps: int = 5):
-    """Best (macrocell, tile_w) for a path-traced frame; returns (best, all)."""
-    space = space or RENDER_SPACE
+    """Best (macrocell, tile_w, cache) for a path-traced frame; returns
+    (best, all).  The cache policy is searched for VDB grids only."""
+    space = dict(RENDER_SPACE, **(space or {}))
+    caches = space["cache"] if isinstance(field, vdbc.Grid) else (2,)
     results = []
     for C_ in space["macrocell"]:
         for tw in space["tile_w"]:
-            p = dict(params, macrocell=C_, tile_w=tw)
-            r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
-            ms = _median_ms(r.launch, reps)
-            results.append({"macrocell": C_, "tile_w": tw, "ms": ms})
+            for cp in caches:
+                p = dict(params, macrocell=C_, tile_w=tw,
+                         flags=params.get("flags", 0) | vdbc.CACHE_FLAGS[cp])
+                r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
+                ms = _median_ms(r.launch, reps)
+                results.append({"macrocell": C_, "tile_w": tw, "cache": cp, "ms": ms})
     best = min(results, key=lambda x: x["ms"])
     return best, results
 

@@ -93,9 +93,16 @@ struct VdbView {
 __device__ __forceinline__ uint32_t popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ uint64_t below(uint32_t bit) { return (uint64_t(1) << bit) - 1u; }
 
-// Random-access VDB accessor with a per-thread cache of the last lower node
-// and the last leaf, reused across consecutive samples of one thread.
-struct VdbAcc {
+// What a VDB accessor keeps between consecutive lookups of one thread: nothing
+// (every lookup descends from the root), the last leaf region, or the last
+// leaf region and the last lower node.  The policy changes only the work of a
+// lookup, never its value.
+enum CachePolicy { kCacheNone = 0, kCacheLeaf = 1, kCacheLeafLower = 2 };
+
+// Random-access VDB accessor with a per-thread cache (policy CP) of the last
+// lower node and the last leaf, reused across consecutive samples of one thread.
+template <int CP>
+struct VdbAccT {
     VdbView v;
     int clx, cly, clz;       // cached leaf coordinates (voxel >> 3)
     LeafH cleaf;
@@ -141,11 +148,11 @@ struct VdbAcc {
     // voxel read the background.
     __device__ LeafH resolve(int lx, int ly, int lz)
     {
-        if (lx == clx && ly == cly && lz == clz) return cleaf;
+        if (CP >= kCacheLeaf && lx == clx && ly == cly && lz == clz) return cleaf;
         LeafH h{v.bg, 0};
         if ((lx | ly | lz) >= 0) {
             const int Lx = lx >> 4, Ly = ly >> 4, Lz = lz >> 4;
-            if (Lx != cLx || Ly != cLy || Lz != cLz) resolve_lower(Lx, Ly, Lz);
+            if (CP < kCacheLeafLower || Lx != cLx || Ly != cLy || Lz != cLz) resolve_lower(Lx, Ly, Lz);
             if (!cnode) {
                 h.p = cconst;
             } else {
@@ -164,10 +171,12 @@ struct VdbAcc {
                 }
             }
         }
-        clx = lx;
-        cly = ly;
-        clz = lz;
-        cleaf = h;
+        if (CP >= kCacheLeaf) {
+            clx = lx;
+            cly = ly;
+            clz = lz;
+            cleaf = h;
+        }
         return h;
     }
 
@@ -226,7 +235,7 @@ struct VdbAcc {
     // voxels: the sample is then not inside an empty node (no query needed).
     __device__ __forceinline__ bool in_stored_leaf(int i, int j, int k) const
     {
-        return (i >> 3) == clx && (j >> 3) == cly && (k >> 3) == clz && cleaf.m != 0u;
+        return CP >= kCacheLeaf && (i >> 3) == clx && (j >> 3) == cly && (k >> 3) == clz && cleaf.m != 0u;
     }
 
     __device__ int empty_level(int i, int j, int k)
@@ -234,7 +243,7 @@ struct VdbAcc {
         if ((i | j | k) < 0) return 0;
         const int lx = i >> 3, ly = j >> 3, lz = k >> 3;
         const int Lx = lx >> 4, Ly = ly >> 4, Lz = lz >> 4;
-        if (Lx != cLx || Ly != cLy || Lz != cLz) resolve_lower(Lx, Ly, Lz);
+        if (CP < kCacheLeafLower || Lx != cLx || Ly != cLy || Lz != cLz) resolve_lower(Lx, Ly, Lz);
         if (!cnode) {
             if (cconst != v.bg) return 0;                 // an upper tile
             const int Ux = Lx >> 5, Uy = Ly >> 5, Uz = Lz >> 5;
@@ -247,6 +256,8 @@ struct VdbAcc {
         return (((w->child | w->tile) >> bit) & 1u) ? 0 : 3;
     }
 };
+
+using VdbAcc = VdbAccT<kCacheLeafLower>;
 
 struct DenseView {
     const float* data;

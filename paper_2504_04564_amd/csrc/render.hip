@@ -390,7 +390,9 @@ static int device_cus()
     return cus;
 }
 
-template <class Acc, class View>
+// MARCH = false leaves out the EA and ISO kernels (accessor variants that
+// only the path tracer uses).
+template <class Acc, class View, bool MARCH = true>
 static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_medium* med,
                                const vdbc_render_params* r, float* image, float* aov, void* ws,
                                uint64_t ws_bytes, void* stream)
@@ -417,56 +419,60 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     if (ws && reinterpret_cast<uintptr_t>(ws) % 256)
         return fail(VDBC_E_INVALID, "workspace must be 256-byte aligned");
     dim3 grid((cam.width + kTile - 1) / kTile, (cam.height + kTile - 1) / kTile);
-    if (r->mode == VDBC_MODE_ISO) {
-        if (!(r->step > 0.0f) || !std::isfinite(r->step))
-            return fail(VDBC_E_INVALID, "ISO step must be finite and > 0");
-        const double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
-        if (diag / r->step > 16777216.0)
-            return fail(VDBC_E_INVALID, "ISO step too small for this volume (> 2^24 samples per ray)");
-        if (!std::isfinite(r->iso)) return fail(VDBC_E_INVALID, "iso value must be finite");
-        if (r->refine > 64) return fail(VDBC_E_INVALID, "refine must be <= 64");
-        if (count) {
+    if constexpr (MARCH) {
+        if (r->mode == VDBC_MODE_ISO) {
+            if (!(r->step > 0.0f) || !std::isfinite(r->step))
+                return fail(VDBC_E_INVALID, "ISO step must be finite and > 0");
+            const double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
+            if (diag / r->step > 16777216.0)
+                return fail(VDBC_E_INVALID, "ISO step too small for this volume (> 2^24 samples per ray)");
+            if (!std::isfinite(r->iso)) return fail(VDBC_E_INVALID, "iso value must be finite");
+            if (r->refine > 64) return fail(VDBC_E_INVALID, "refine must be <= 64");
+            if (count) {
+                hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
+                if ((s = launch_check("zero counter"))) return s;
+            }
+            const bool hdda = (r->flags & VDBC_RENDER_HDDA) != 0;
+    #define ISO_LAUNCH(H, CNT)                                                                      \
+        hipLaunchKernelGGL((iso_kernel<Acc, View, H, CNT>), grid, dim3(kBlock), 0, st, v, cam, r->iso, \
+                           r->step, (int)r->refine, image, aov, counter)
+            if (hdda) {
+                if (count) ISO_LAUNCH(true, true);
+                else ISO_LAUNCH(true, false);
+            } else {
+                if (count) ISO_LAUNCH(false, true);
+                else ISO_LAUNCH(false, false);
+            }
+    #undef ISO_LAUNCH
+            return launch_check("iso render");
+        }
+        if (count && r->mode == VDBC_MODE_EA) {
             hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
             if ((s = launch_check("zero counter"))) return s;
         }
-        const bool hdda = (r->flags & VDBC_RENDER_HDDA) != 0;
-#define ISO_LAUNCH(H, CNT)                                                                      \
-    hipLaunchKernelGGL((iso_kernel<Acc, View, H, CNT>), grid, dim3(kBlock), 0, st, v, cam, r->iso, \
-                       r->step, (int)r->refine, image, aov, counter)
-        if (hdda) {
-            if (count) ISO_LAUNCH(true, true);
-            else ISO_LAUNCH(true, false);
-        } else {
-            if (count) ISO_LAUNCH(false, true);
-            else ISO_LAUNCH(false, false);
+        if (r->mode == VDBC_MODE_EA) {
+            if (!(r->step > 0.0f) || !std::isfinite(r->step))
+                return fail(VDBC_E_INVALID, "EA step must be finite and > 0");
+            // bound the per-ray loop: box diagonal / step <= 2^24 samples
+            const double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
+            if (diag / r->step > 16777216.0)
+                return fail(VDBC_E_INVALID, "EA step too small for this volume (> 2^24 samples per ray)");
+            const bool hdda = (r->flags & VDBC_RENDER_HDDA) && host_alpha(m, v.background) == 0.0f;
+    #define EA_LAUNCH(H, CNT)                                                                      \
+        hipLaunchKernelGGL((ea_kernel<Acc, View, H, CNT>), grid, dim3(kBlock), 0, st, v, cam, m, \
+                           r->step, r->t_terminate, image, counter)
+            if (hdda) {
+                if (count) EA_LAUNCH(true, true);
+                else EA_LAUNCH(true, false);
+            } else {
+                if (count) EA_LAUNCH(false, true);
+                else EA_LAUNCH(false, false);
+            }
+    #undef EA_LAUNCH
+            return launch_check("ea render");
         }
-#undef ISO_LAUNCH
-        return launch_check("iso render");
-    }
-    if (count && r->mode == VDBC_MODE_EA) {
-        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, st, counter);
-        if ((s = launch_check("zero counter"))) return s;
-    }
-    if (r->mode == VDBC_MODE_EA) {
-        if (!(r->step > 0.0f) || !std::isfinite(r->step))
-            return fail(VDBC_E_INVALID, "EA step must be finite and > 0");
-        // bound the per-ray loop: box diagonal / step <= 2^24 samples
-        const double diag = std::sqrt((double)v.nx * v.nx + (double)v.ny * v.ny + (double)v.nz * v.nz);
-        if (diag / r->step > 16777216.0)
-            return fail(VDBC_E_INVALID, "EA step too small for this volume (> 2^24 samples per ray)");
-        const bool hdda = (r->flags & VDBC_RENDER_HDDA) && host_alpha(m, v.background) == 0.0f;
-#define EA_LAUNCH(H, CNT)                                                                      \
-    hipLaunchKernelGGL((ea_kernel<Acc, View, H, CNT>), grid, dim3(kBlock), 0, st, v, cam, m, \
-                       r->step, r->t_terminate, image, counter)
-        if (hdda) {
-            if (count) EA_LAUNCH(true, true);
-            else EA_LAUNCH(true, false);
-        } else {
-            if (count) EA_LAUNCH(false, true);
-            else EA_LAUNCH(false, false);
-        }
-#undef EA_LAUNCH
-        return launch_check("ea render");
+    } else if (r->mode != VDBC_MODE_PT) {
+        return fail(VDBC_E_UNSUPPORTED, "accessor variant for the path tracer only");
     }
     // the tile's work units (256 x spp) are 32-bit and the bounce is a
     // 16-bit field of the random-number counter
@@ -556,6 +562,16 @@ extern "C" vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, con
     VdbView v;
     vdbc_status s = make_view(g, &v);
     if (s) return s;
+    // path tracer only: the accessor's cache policy (a tuning knob; the image
+    // does not depend on it)
+    const uint32_t pol = r ? (r->flags & (VDBC_RENDER_CACHE_NONE | VDBC_RENDER_CACHE_LEAF)) : 0u;
+    if (pol == (VDBC_RENDER_CACHE_NONE | VDBC_RENDER_CACHE_LEAF))
+        return fail(VDBC_E_INVALID, "at most one cache-policy flag");
+    if (pol && r->mode == VDBC_MODE_PT) {
+        if (pol == VDBC_RENDER_CACHE_NONE)
+            return render_impl<VdbAccT<kCacheNone>, VdbView, false>(v, c, m, r, image, aov, ws, ws_bytes, stream);
+        return render_impl<VdbAccT<kCacheLeaf>, VdbView, false>(v, c, m, r, image, aov, ws, ws_bytes, stream);
+    }
     return render_impl<VdbAcc>(v, c, m, r, image, aov, ws, ws_bytes, stream);
 }
 

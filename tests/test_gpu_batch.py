@@ -94,3 +94,19 @@ def test_autotuner_picks_a_measured_candidate(tmp_path):
                                                 space=dict(macrocell=(8, 16), tile_w=(8, 32)),
                                                 reps=2))
     assert autotune.load(path)[key] == choice
+
+
+def test_cache_policies_give_identical_images():
+    # the accessor's cache policy changes the work of a lookup, never its value
+    items = _items(1, seed=21)
+    it = items[0]
+    base = dict(spp=3, max_bounces=6, seed=it["seed"], macrocell=8)
+    imgs = []
+    for flag in (0, vdbc.RENDER_CACHE_LEAF, vdbc.RENDER_CACHE_NONE):
+        img = vdbc.render(it["grid"], it["camera"], it["medium"], dict(base, flags=flag),
+                          vdbc.MODE_PT).clone()
+        imgs.append(img)
+    assert _same(imgs[0], imgs[1]) and _same(imgs[0], imgs[2])
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.render(it["grid"], it["camera"], it["medium"],
+                    dict(base, flags=vdbc.RENDER_CACHE_LEAF | vdbc.RENDER_CACHE_NONE), vdbc.MODE_PT)

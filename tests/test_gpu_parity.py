@@ -357,13 +357,32 @@ def test_pt_mid_config_sampled_pixels():
     M = scenes.MID
     cam = scenes.orbit_camera((512, 512, 512), M["width"], M["height"])
     med = scenes.pt_medium(64.0)
-    prm = dict(spp=M["spp"], max_bounces=M["max_bounces"], seed=M["seed"], macrocell=8)
+    prm = dict(spp=M["spp"], max_bounces=M["max_bounces"], seed=M["seed"], macrocell=16)
     img = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
     rng = np.random.default_rng(52)
     pix = np.sort(rng.choice(M["width"] * M["height"], 192, replace=False)).astype(np.uint32)
     want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, pixels=pix)
     assert relmse(img[pix], want) <= 1e-4
     assert np.all(np.isfinite(img))
+
+
+def test_pt_paper_launch_configuration_sampled_pixels():
+    # the paper-scale launch (1920x1080, 64 spp, <= 16 bounces, macrocell 16,
+    # 1:10) on the same billowed recipe at 1/8 of the edge lengths; the oracle
+    # renders a sample of the pixels one by one
+    P = scenes.PAPER
+    dims = tuple(d // 8 for d in P["dims"])
+    v = synth.paper_volume(dims=dims)
+    buf, _ = vdbc.encode(v, 0.10)
+    cam = scenes.orbit_camera(dims, P["width"], P["height"])
+    med = scenes.pt_medium(64.0)
+    prm = dict(spp=P["spp"], max_bounces=P["max_bounces"], seed=P["seed"], macrocell=16)
+    img = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
+    rng = np.random.default_rng(53)
+    pix = np.sort(rng.choice(P["width"] * P["height"], 1024, replace=False)).astype(np.uint32)
+    want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, pixels=pix)
+    assert relmse(img[pix], want) <= 1e-4
+    assert np.all(np.isfinite(img)) and np.count_nonzero(want[:, 3] > 0) >= 32
 
 
 def test_pt_image_independent_of_wave_tile_shape():

@@ -107,6 +107,28 @@ vdbc_status vdbc_encode(const float* dense, vdbc_dims dims, const vdbc_encode_pa
  * counts, running popcount prefixes, root table). */
 vdbc_status vdbc_validate(const void* buf_host, uint64_t bytes, vdbc_encode_stats* info);
 
+/* Node layouts (header field `layout`; the encoder writes 0).  Two bits:
+ * VDBC_LAYOUT_MORTON numbers the child slots of upper and lower nodes along a
+ * Morton curve (bit 3b+a of a slot number = bit b of coordinate a), so lower
+ * nodes, leaves and tiles are stored in Z order; VDBC_LAYOUT_SOA stores each
+ * node's masks and index prefixes as four arrays (24 B per 64 slots) instead
+ * of 32-byte word records.  Every layout holds the same tree.  The host calls
+ * (vdbc_validate, vdbc_relayout) accept all four; the device calls read
+ * layout 0 only, and vdbc_grid_init rejects the others with
+ * VDBC_E_UNSUPPORTED. */
+#define VDBC_LAYOUT_V1 0u
+#define VDBC_LAYOUT_MORTON 1u
+#define VDBC_LAYOUT_SOA 2u
+
+/* Host.  Rewrites buffer `src` (any layout, validated first) into `layout`
+ * (0..3) at `out` (host, 256-byte aligned, must not overlap `src`).  Leaf
+ * masks and values are copied unchanged, nodes re-emitted in the canonical
+ * order of the new slot numbering; converting back gives the original bytes.
+ * out == NULL or capacity too small -> VDBC_E_BUFFER_TOO_SMALL with *bytes
+ * set; a malformed source -> VDBC_E_FORMAT; layout > 3 -> VDBC_E_INVALID. */
+vdbc_status vdbc_relayout(const void* src, uint64_t src_bytes, uint32_t layout, void* out,
+                          uint64_t capacity, uint64_t* bytes);
+
 /* ------------------------------------------------------------------------ */
 /* Device buffer handle                                                      */
 /* ------------------------------------------------------------------------ */
@@ -121,7 +143,8 @@ typedef struct {
 } vdbc_grid;
 
 /* Fill *g from a device pointer and the host copy of the buffer's first 256
- * bytes; checks the header (magic, version, offsets within `bytes`). */
+ * bytes; checks the header (magic, version, offsets within `bytes`).  A node
+ * layout other than 0 -> VDBC_E_UNSUPPORTED. */
 vdbc_status vdbc_grid_init(vdbc_grid* g, const void* device, uint64_t bytes,
                            const void* host_header);
 

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libvdbc.so")
 OBJ = os.path.join(HERE, "_obj")
 
-HOST_SOURCES = ["api.cpp", "encode.cpp"]
+HOST_SOURCES = ["api.cpp", "encode.cpp", "layout.cpp"]
 HIP_SOURCES = ["sample.hip", "render.hip", "denoise.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

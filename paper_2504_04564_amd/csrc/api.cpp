@@ -65,7 +65,7 @@ vdbc_status parse_header(const void* header, uint64_t bytes, Header* out)
     h.off_leaf_masks = get<uint64_t>(p, hdr::off_leaf_masks);
     h.off_leaf_values = get<uint64_t>(p, hdr::off_leaf_values);
     h.total_bytes = get<uint64_t>(p, hdr::total_bytes);
-    if (h.layout != 0) return fail(VDBC_E_FORMAT, "unsupported layout %u", h.layout);
+    if (h.layout >= kLayouts) return fail(VDBC_E_FORMAT, "unsupported layout %u", h.layout);
     if (h.nx == 0 || h.ny == 0 || h.nz == 0 || h.nx > 0x7FFFFFFFu || h.ny > 0x7FFFFFFFu ||
         h.nz > 0x7FFFFFFFu)
         return fail(VDBC_E_FORMAT, "bad dims");
@@ -78,9 +78,9 @@ vdbc_status parse_header(const void* header, uint64_t bytes, Header* out)
     if (h.off_root != o) return fail(VDBC_E_FORMAT, "bad root offset");
     o = align256(o + 4 * rn);
     if (h.off_upper != o) return fail(VDBC_E_FORMAT, "bad upper offset");
-    o = align256(o + (uint64_t)h.n_upper * kUpperWords * kWordBytes);
+    o = align256(o + (uint64_t)h.n_upper * node_bytes(h.layout, kUpperWords));
     if (h.off_lower != o) return fail(VDBC_E_FORMAT, "bad lower offset");
-    o = align256(o + (uint64_t)h.n_lower * kLowerWords * kWordBytes);
+    o = align256(o + (uint64_t)h.n_lower * node_bytes(h.layout, kLowerWords));
     if (h.off_upper_tiles != o) return fail(VDBC_E_FORMAT, "bad upper-tile offset");
     o = align256(o + 4ull * h.n_upper_tiles);
     if (h.off_lower_tiles != o) return fail(VDBC_E_FORMAT, "bad lower-tile offset");
@@ -117,17 +117,21 @@ static vdbc_status check_nodes(const uint8_t* p, const Header& h)
         uint32_t nodes, words, children, tiles;
     } levels[2] = {{h.off_upper, h.n_upper, kUpperWords, h.n_lower, h.n_upper_tiles},
                    {h.off_lower, h.n_lower, kLowerWords, h.n_leaf, h.n_lower_tiles}};
+    const bool soa = (h.layout & kLayoutSoA) != 0;
     for (const Level& L : levels) {
         uint64_t c = 0, t = 0;
-        const Word* w = reinterpret_cast<const Word*>(p + L.off);
-        for (uint64_t i = 0; i < (uint64_t)L.nodes * L.words; ++i) {
-            if (w[i].child_index != c || w[i].tile_index != t)
-                return fail(VDBC_E_FORMAT, "node word %llu: prefix mismatch",
-                            (unsigned long long)i);
-            if (w[i].child & w[i].tile) return fail(VDBC_E_FORMAT, "slot both child and tile");
-            if (w[i].reserved) return fail(VDBC_E_FORMAT, "reserved word not zero");
-            c += popc(w[i].child);
-            t += popc(w[i].tile);
+        for (uint64_t n = 0; n < L.nodes; ++n) {
+            const uint8_t* node = p + L.off + n * node_bytes(h.layout, L.words);
+            for (uint32_t i = 0; i < L.words; ++i) {
+                NodeWord w;
+                read_word(node, L.words, i, soa, &w);
+                if (w.child_index != c || w.tile_index != t)
+                    return fail(VDBC_E_FORMAT, "node %llu word %u: prefix mismatch", (unsigned long long)n, i);
+                if (w.child & w.tile) return fail(VDBC_E_FORMAT, "slot both child and tile");
+                if (w.reserved) return fail(VDBC_E_FORMAT, "reserved word not zero");
+                c += popc(w.child);
+                t += popc(w.tile);
+            }
         }
         if (c != L.children || t != L.tiles)
             return fail(VDBC_E_FORMAT, "node masks count %llu children / %llu tiles",
@@ -192,6 +196,9 @@ extern "C" vdbc_status vdbc_grid_init(vdbc_grid* g, const void* device, uint64_t
     Header h;
     vdbc_status s = parse_header(host_header, bytes, &h);
     if (s) return s;
+    if (h.layout != 0)
+        return fail(VDBC_E_UNSUPPORTED, "vdbc_grid_init: the device kernels read node layout 0 only (buffer has %u)",
+                    h.layout);
     g->device = device;
     g->bytes = bytes;
     std::memcpy(g->header, host_header, kHeaderBytes);

@@ -65,4 +65,24 @@ struct Header {
 
 inline uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
 
+// Node layouts (header field `layout`), two independent bits; 0 is the
+// record layout above.
+//   kLayoutMorton: the child slots of upper and lower nodes are numbered along
+//     a Morton (Z-order) curve of the slot coordinates, bit 3b+a of the slot
+//     number being bit b of coordinate a (x=0, y=1, z=2), instead of x-fastest.
+//     Canonical order (children by slot) then stores lower nodes, leaves and
+//     tiles along the curve, and one 64-slot word covers a 4^3 block of
+//     children (for lower nodes: the 64 leaves of one 32^3 brick).
+//   kLayoutSoA: a node of W words stores its fields as four arrays,
+//     child masks u64[W] | tile masks u64[W] | child indices u32[W] | tile
+//     indices u32[W], 24*W bytes, in place of W 32-byte records.
+// Every layout holds the same tree: a lookup returns the same value.
+constexpr uint32_t kLayoutMorton = 1;
+constexpr uint32_t kLayoutSoA = 2;
+constexpr uint32_t kLayouts = 4;
+inline uint64_t node_bytes(uint32_t layout, uint32_t words)
+{
+    return ((layout & kLayoutSoA) ? 24ull : 32ull) * words;
+}
+
 }  // namespace vdbc

@@ -73,6 +73,7 @@ static inline vdbc_status make_view(const vdbc_grid* g, VdbView* v)
     Header h;
     vdbc_status s = parse_header(g->header, g->bytes, &h);
     if (s) return s;
+    if (h.layout != 0) return fail(VDBC_E_UNSUPPORTED, "the device kernels read node layout 0 only");
     const uint8_t* b = static_cast<const uint8_t*>(g->device);
     v->root = reinterpret_cast<const uint32_t*>(b + h.off_root);
     v->upper = reinterpret_cast<const Word*>(b + h.off_upper);

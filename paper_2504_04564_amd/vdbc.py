@@ -22,6 +22,9 @@ RENDER_HDDA, RENDER_COUNT, RENDER_KEEP_MAJORANT, RENDER_RR = 1, 2, 4, 8
 RENDER_CACHE_NONE, RENDER_CACHE_LEAF = 16, 32
 # accessor cache policy -> render flag (2 = last leaf and last lower node, the default)
 CACHE_FLAGS = {0: RENDER_CACHE_NONE, 1: RENDER_CACHE_LEAF, 2: 0}
+# node layouts (bits): Morton child-slot order, SoA node words
+LAYOUT_V1, LAYOUT_MORTON, LAYOUT_SOA = 0, 1, 2
+LAYOUTS = (0, 1, 2, 3)
 
 
 class VdbcError(RuntimeError):
@@ -108,6 +111,7 @@ def load():
     L.vdbc_encode.argtypes = [P, Dims, C.POINTER(EncodeParams), P, u64, C.POINTER(u64),
                               C.POINTER(EncodeStats)]
     L.vdbc_validate.argtypes = [P, u64, C.POINTER(EncodeStats)]
+    L.vdbc_relayout.argtypes = [P, u64, u32, P, u64, C.POINTER(u64)]
     L.vdbc_grid_init.argtypes = [C.POINTER(GridC), P, u64, P]
     L.vdbc_sample.argtypes = [C.POINTER(GridC), P, u64, u32, P, P]
     L.vdbc_sample_dense.argtypes = [P, Dims, f32, P, u64, u32, P, P]
@@ -122,7 +126,7 @@ def load():
     L.vdbc_majorant.argtypes = [C.POINTER(GridC), C.POINTER(MediumC), u32, P, P]
     L.vdbc_majorant_dense.argtypes = [P, Dims, f32, C.POINTER(MediumC), u32, P, P]
     L.vdbc_philox.argtypes = [P, P, u64, P, P]
-    for name in ["vdbc_encode_begin", "vdbc_encode_finish", "vdbc_encode", "vdbc_validate",
+    for name in ["vdbc_encode_begin", "vdbc_encode_finish", "vdbc_encode", "vdbc_validate", "vdbc_relayout",
                  "vdbc_grid_init", "vdbc_sample", "vdbc_sample_dense", "vdbc_lookup",
                  "vdbc_render_workspace", "vdbc_render", "vdbc_render_dense", "vdbc_majorant",
                  "vdbc_majorant_dense", "vdbc_philox"]:
@@ -144,9 +148,17 @@ def _dims_of(shape) -> Dims:
 
 # ------------------------------------------------------------------ encoder
 
+def _aligned(nbytes: int) -> np.ndarray:
+    """Host uint8 array of nbytes starting on a 256-byte boundary."""
+    raw = np.empty(nbytes + 256, dtype=np.uint8)
+    off = (-raw.ctypes.data) % 256
+    return raw[off:off + nbytes]
+
+
 def encode(dense: np.ndarray, rate: float, metric: int = 2, flags: int = 0,
-           background: float = 0.0, threads: int = 0):
-    """Encode a host float32 volume (nz, ny, nx) -> (uint8 buffer, stats)."""
+           background: float = 0.0, threads: int = 0, layout: int = LAYOUT_V1):
+    """Encode a host float32 volume (nz, ny, nx) -> (uint8 buffer, stats);
+    a non-zero node layout is produced from the layout-0 buffer by relayout()."""
     L = load()
     d = np.ascontiguousarray(dense, dtype=np.float32)
     if d.ndim != 3:
@@ -157,13 +169,30 @@ def encode(dense: np.ndarray, rate: float, metric: int = 2, flags: int = 0,
     st = EncodeStats()
     _check(L.vdbc_encode_begin(d.ctypes.data, _dims_of(d.shape), C.byref(p), C.byref(h),
                                C.byref(nbytes), C.byref(st)))
-    # 256-byte aligned host buffer
-    raw = np.empty(nbytes.value + 256, dtype=np.uint8)
-    off = (-raw.ctypes.data) % 256
-    buf = raw[off:off + nbytes.value]
+    buf = _aligned(nbytes.value)
     _check(L.vdbc_encode_finish(h, buf.ctypes.data, nbytes.value))
     stats = {name: getattr(st, name) for name, _ in EncodeStats._fields_}
+    if layout != LAYOUT_V1:
+        buf = relayout(buf, layout)
+        stats["bytes"] = buf.size
     return buf, stats
+
+
+def relayout(buf: np.ndarray, layout: int) -> np.ndarray:
+    """The same tree in node layout `layout` (0..3) as a new host buffer."""
+    L = load()
+    b = np.ascontiguousarray(buf, dtype=np.uint8)
+    need = C.c_uint64(0)
+    st = L.vdbc_relayout(b.ctypes.data, b.size, layout, None, 0, C.byref(need))
+    if st != E_BUFFER_TOO_SMALL:
+        _check(st)
+    out = _aligned(need.value)
+    _check(L.vdbc_relayout(b.ctypes.data, b.size, layout, out.ctypes.data, out.size, C.byref(need)))
+    return out
+
+
+def layout_of(buf: np.ndarray) -> int:
+    return int(np.frombuffer(np.ascontiguousarray(buf[36:40]).tobytes(), "<u4")[0])
 
 
 def validate(buf: np.ndarray) -> dict:
@@ -206,6 +235,7 @@ class Grid:
                                      self.header.ctypes.data))
         self.dims = tuple(int(x) for x in np.frombuffer(self.header[8:20].tobytes(), "<u4"))
         self.background = float(np.frombuffer(self.header[20:24].tobytes(), "<f4")[0])
+        self.layout = layout_of(self.header)
 
 
 def sample(grid: Grid, pos, filter: int = 1, out=None):

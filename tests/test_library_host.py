@@ -129,7 +129,9 @@ def test_validator_rejects_corruption():
     v = _rand((40, 40, 40), 9)
     buf, _ = vdbc.encode(v, 0.5)
     vdbc.validate(buf)
-    for off, val in ((0, 0x58), (4, 2), (36, 1), (152, 1), (104, 1)):
+    # magic, version, an unknown node layout, the SoA layout (its node
+    # sections are smaller, so the offsets no longer match), sizes, offsets
+    for off, val in ((0, 0x58), (4, 2), (36, 4), (36, 2), (152, 1), (104, 1)):
         bad = buf.copy()
         bad[off] = val
         with pytest.raises(vdbc.VdbcError) as e:

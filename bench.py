@@ -242,6 +242,14 @@ def main():
         log(f"[bench] random samples/s: VDB {ns / (sv_ms * 1e-3) / 1e9:.2f} G, "
             f"dense {ns / (sd_ms * 1e-3) / 1e9:.2f} G")
         del pos, out
+        # the HBM bandwidth a plain streaming copy reaches on this GPU (1 GiB
+        # read + 1 GiB written per launch), next to the 8 TB/s datasheet figure
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        copy_ms = time_sampler(torch, lambda: y.copy_(x), 5, 2)
+        extras["hbm_copy_gbs"] = round(2 * x.numel() * 4 / (copy_ms * 1e-3) / 1e9, 1)
+        log(f"[bench] streaming copy: {extras['hbm_copy_gbs']:.0f} GB/s")
+        del x, y
 
     cpu = None
     rel = None
@@ -321,6 +329,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "frac_of_measured_copy": (round(achieved / extras["hbm_copy_gbs"], 5)
+                                      if "hbm_copy_gbs" in extras else None),
             "traffic": prof.get("traffic"),
             "limiter": ({"kind": "VALU issue of divergent lanes (counters of the same kernel build)",
                          "valu_lane_utilisation": prof["valu_lane_utilisation"],

@@ -195,20 +195,11 @@ struct VdbAccT {
         const uint32_t ax = sx ? a0 - 7 : a0 + 1;       // x+1 within its leaf
         const uint32_t ay = sy ? -56u : 8u;              // y step
         const uint32_t az = sz ? -448u : 64u;            // z step
+        // One code path for every footprint: a footprint inside one leaf takes
+        // h000 for all corners through the selects below.  A separate early
+        // return for that case costs more than it saves, since nearly every
+        // wave holds lanes of both kinds and would run both load sequences.
         const LeafH h000 = resolve(lx0, ly0, lz0);
-        if (!(sx | sy | sz)) {
-            const float* p = h000.p;
-            const uint32_t m = h000.m;
-            c[0] = p[a0 & m];
-            c[1] = p[(a0 + 1) & m];
-            c[2] = p[(a0 + 8) & m];
-            c[3] = p[(a0 + 9) & m];
-            c[4] = p[(a0 + 64) & m];
-            c[5] = p[(a0 + 65) & m];
-            c[6] = p[(a0 + 72) & m];
-            c[7] = p[(a0 + 73) & m];
-            return;
-        }
         const LeafH h100 = sx ? resolve(lx0 + 1, ly0, lz0) : h000;
         const LeafH h010 = sy ? resolve(lx0, ly0 + 1, lz0) : h000;
         const LeafH h110 = sy ? (sx ? resolve(lx0 + 1, ly0 + 1, lz0) : h010) : h100;

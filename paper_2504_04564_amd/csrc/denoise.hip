@@ -194,10 +194,14 @@ __global__ void transpose_weights_kernel(const uint16_t* __restrict__ w, int cin
 // dz[p][co] * A[p][k] with A the forward operand (k = tap * cin + ci).
 // M = co (MT tiles of 16), N = k (64 per workgroup, 16 per wave), K = pixels
 // staged 32 at a time through LDS (dz rows and im2col rows, both contiguous).
+// The workgroups of the first k tile also sum the staged dz rows per channel:
+// bpart[chunk][c] = sum over the chunk's pixels of dz[p][c] (thread (w, c)
+// adds pixels w, w + 4, ... of each staged block, then the four wave sums in
+// order), the bias gradient's partials.
 template <int MT>
 __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int stride, int ho, int wo,
                                                               const uint16_t* __restrict__ dz, int coutp,
-                                                              float* __restrict__ partial)
+                                                              float* __restrict__ partial, float* __restrict__ bpart)
 {
     __shared__ uint16_t sA[32][64 + 8];
     __shared__ uint16_t sB[32][64 + 8];
@@ -211,6 +215,8 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     const int cg = coutp / 8;
+    const bool bias = blockIdx.y == 0;   // uniform per workgroup
+    float bsum = 0.0f;
     for (int64_t pb = p0; pb < p1; pb += 32) {
         // dz rows: 32 pixels x coutp channels
         for (int idx = tid; idx < 32 * cg; idx += kThreads) {
@@ -235,6 +241,11 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
             *reinterpret_cast<uint4*>(&sB[px][kg * 8]) = __builtin_bit_cast(uint4, v);
         }
         __syncthreads();
+        if (bias && lane < coutp) {
+            // rows past the chunk's end were staged as zeros
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bsum += bf2f(sA[wave + 4 * j][lane]);
+        }
         bf16x8 B;
 #pragma unroll
         for (int j = 0; j < 8; ++j) B[j] = __builtin_bit_cast(__bf16, sB[8 * g + j][16 * wave + r]);
@@ -249,6 +260,13 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
         }
         __syncthreads();
     }
+    if (bias) {
+        __shared__ float sred[4][64];
+        sred[wave][lane] = bsum;
+        __syncthreads();
+        if (tid < coutp)
+            bpart[(int64_t)blockIdx.x * coutp + tid] = ((sred[0][tid] + sred[1][tid]) + sred[2][tid]) + sred[3][tid];
+    }
     const int k = kbase + 16 * wave + r;
     if (k >= K) return;
 #pragma unroll
@@ -260,70 +278,38 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
         }
 }
 
-// grad[co][k] = sum over chunks (in order) of partial[chunk][co][k].
-__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks, int mpad, int cout,
-                                    int K, float* __restrict__ grad)
+// grad[co][k] = sum over chunks of partial[chunk][co][k]: a workgroup takes
+// 64 consecutive (co, k) entries, wave w adds chunks w, w + 4, ... in order,
+// then the four wave sums are added in order (deterministic).
+__global__ __launch_bounds__(kThreads) void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks,
+                                                                int mpad, int cout, int K, float* __restrict__ grad)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cout * K) return;
-    const int co = i / K, k = i - co * K;
-    float s = 0.0f;
-    for (int c = 0; c < chunks; ++c) s += partial[((int64_t)c * mpad + co) * K + k];
-    grad[i] = s;
-}
-
-// partial[chunk][c] = sum of dz[p][c] over the chunk's kWgradChunk output
-// pixels: thread (g, c) takes channel c of every G-th pixel (G = 256 / coutp
-// pixel groups), so a wave reads contiguous channel rows; the G group sums
-// are added in a fixed order.
-__global__ __launch_bounds__(kThreads) void bias_partial_kernel(const uint16_t* __restrict__ dz, int coutp,
-                                                                int64_t P, float* __restrict__ partial)
-{
-    __shared__ float s[kThreads];
-    const int G = kThreads / coutp;
-    const int t = threadIdx.x, c = t % coutp, g = t / coutp;
-    float a = 0.0f;
-    if (g < G) {
-        const int64_t p0 = (int64_t)blockIdx.x * kWgradChunk;
-        const int64_t p1 = p0 + kWgradChunk < P ? p0 + kWgradChunk : P;
-        for (int64_t p = p0 + g; p < p1; p += G) a += bf2f(dz[p * coutp + c]);
+    __shared__ float s[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    float r = 0.0f;
+    if (i < cout * K) {
+        const int co = i / K, k = i - co * K;
+        for (int c = w; c < chunks; c += 4) r += partial[((int64_t)c * mpad + co) * K + k];
     }
-    s[t] = a;
+    s[w][lane] = r;
     __syncthreads();
-    if (t < coutp) {
-        float r = 0.0f;
-        for (int j = 0; j < G; ++j) r += s[j * coutp + t];
-        partial[(int64_t)blockIdx.x * coutp + t] = r;
-    }
+    if (w == 0 && i < cout * K) grad[i] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
 }
 
-// db[c] = sum over chunks (in order) of partial[chunk][c].
-__global__ __launch_bounds__(kThreads) void bias_reduce_kernel(const float* __restrict__ partial, int chunks,
+// db[c] = sum over chunks of bpart[chunk][c] (c < cout <= 64), in the same
+// order as wgrad_reduce_kernel.
+__global__ __launch_bounds__(kThreads) void bias_reduce_kernel(const float* __restrict__ bpart, int chunks,
                                                                int coutp, int cout, float* __restrict__ db)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cout) return;
+    __shared__ float s[4][64];
+    const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
     float r = 0.0f;
-    for (int k = 0; k < chunks; ++k) r += partial[(int64_t)k * coutp + c];
-    db[c] = r;
-}
-
-// db[co] = sum_p dz[p][co]; one workgroup per channel, fixed-order tree sum
-// (for more than 256 padded channels).
-__global__ __launch_bounds__(kThreads) void bias_grad_kernel(const uint16_t* __restrict__ dz, int coutp,
-                                                             int64_t P, float* __restrict__ db)
-{
-    __shared__ float s[kThreads];
-    const int co = blockIdx.x;
-    float a = 0.0f;
-    for (int64_t p = threadIdx.x; p < P; p += kThreads) a += bf2f(dz[p * coutp + co]);
-    s[threadIdx.x] = a;
+    if (c < cout)
+        for (int k = w; k < chunks; k += 4) r += bpart[(int64_t)k * coutp + c];
+    s[w][c] = r;
     __syncthreads();
-    for (int h = kThreads / 2; h > 0; h >>= 1) {
-        if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[co] = s[0];
+    if (threadIdx.x < cout) db[c] = ((s[0][c] + s[1][c]) + s[2][c]) + s[3][c];
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -508,13 +494,15 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
     return check("conv3x3 data gradient");
 }
 
+// Floats of the weight-gradient partials followed by the bias partials
+// (chunks x coutp, coutp <= 64).
 uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
 {
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const uint64_t P = (uint64_t)in.n * ((hv - 1) / stride + 1) * ((wv - 1) / stride + 1);
     const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
     const int mpad = (cout + 15) / 16 * 16;
-    return chunks * mpad * 9ull * (in.ca + in.cb);
+    return chunks * mpad * 9ull * (in.ca + in.cb) + chunks * 64ull;
 }
 
 vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int coutp, int cout, float* dw,
@@ -527,23 +515,19 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     const unsigned chunks = (unsigned)((P + kWgradChunk - 1) / kWgradChunk);
     const int mt = (cout + 15) / 16;
     dim3 grid(chunks, (K + 63) / 64);
+    float* bpart = partial + (uint64_t)chunks * (mt * 16) * K;
     if (mt == 1)
-        hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
+        hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
+                           bpart);
     else if (mt == 2)
-        hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
+        hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
+                           bpart);
     else
-        hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks((uint64_t)cout * K)), dim3(kThreads), 0, st, partial,
-                       (int)chunks, mt * 16, cout, K, dw);
-    if (coutp <= kThreads) {
-        // the weight-gradient partials are reduced by now (stream order): the
-        // same buffer holds chunks x coutp bias partials (<= chunks x mpad x K)
-        hipLaunchKernelGGL(bias_partial_kernel, dim3(chunks), dim3(kThreads), 0, st, dz, coutp, P, partial);
-        hipLaunchKernelGGL(bias_reduce_kernel, dim3((unsigned)((cout + kThreads - 1) / kThreads)), dim3(kThreads),
-                           0, st, partial, (int)chunks, coutp, cout, db);
-    } else {
-        hipLaunchKernelGGL(bias_grad_kernel, dim3(cout), dim3(kThreads), 0, st, dz, coutp, P, db);
-    }
+        hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
+                           bpart);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)(((uint64_t)cout * K + 63) / 64)), dim3(kThreads), 0, st,
+                       partial, (int)chunks, mt * 16, cout, K, dw);
+    hipLaunchKernelGGL(bias_reduce_kernel, dim3(1), dim3(kThreads), 0, st, bpart, (int)chunks, coutp, cout, db);
     return check("conv3x3 weight gradient");
 }
 
@@ -592,7 +576,7 @@ NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
         L.dz1 = take(P * 32 * 2);
         L.wt = take(64 * 9 * 64 * 2);
         const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
-        L.partial = take(chunks * 64 * 9 * 64 * 4);
+        L.partial = take(chunks * (64 * 9 * 64 + 64) * 4);
         L.lpart = take((P + kThreads - 1) / kThreads * 4 + 16);
         L.grad = take(nn::param_count() * 4);
     }
@@ -802,7 +786,7 @@ extern "C" vdbc_status vdbc_conv3x3_grad_workspace(uint32_t cin, uint32_t cout, 
     if (!bytes || cin == 0 || cin > 64 || cout == 0 || cout > 64) return fail(VDBC_E_INVALID, "bad argument");
     const uint64_t P = (uint64_t)n * ho * wo;
     const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
-    *bytes = al(64ull * 9 * 64 * 2) + al(chunks * 64ull * 9 * cin * 4);
+    *bytes = al(64ull * 9 * 64 * 2) + al(chunks * (64ull * 9 * cin + 64) * 4);
     return VDBC_OK;
 }
 

@@ -47,8 +47,13 @@ def train(dn: "vdbc.Denoiser", xs, ts, steps: int, batch: int, lr: float, seed: 
     rng = np.random.default_rng(seed)
     n = xs.shape[0]
     losses = torch.empty(steps, dtype=torch.float32, device=xs.device)
+    # every step's batch drawn up front and uploaded once: a per-step upload
+    # from pageable host memory would wait for the previous step's kernels
+    picks = np.stack([rng.choice(n, size=min(batch, n), replace=False) for _ in range(steps)]) \
+        if steps else np.zeros((0, min(batch, n)), np.int64)
+    all_idx = torch.from_numpy(picks).to(xs.device)
     for s in range(steps):
-        idx = torch.from_numpy(rng.choice(n, size=min(batch, n), replace=False)).to(xs.device)
+        idx = all_idx[s]
         loss = dn.train_step(xs.index_select(0, idx).contiguous(),
                              ts.index_select(0, idx).contiguous(), lr)
         losses[s] = loss[0]

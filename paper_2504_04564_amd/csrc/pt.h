@@ -120,19 +120,17 @@ __device__ __forceinline__ int cell_exit(const Flight& f, float edge, int cx, in
     return axis;
 }
 
-// Advances the flight to its next tentative collision: returns 1 with the
-// density `sv` sampled there (the caller makes the accept test), 0 when the
-// segment leaves the grid without one, or kFlightYield after entering
-// kWalkCells macrocells without a collision (call again to continue; the
-// walk and its random draws are the same as without the pause).  Empty cells draw no random
+// Advances the flight to its next tentative collision: returns 1 with f.t
+// at the collision (the caller samples the density there and makes the
+// accept test), 0 when the segment leaves the grid without one, or
+// kFlightYield after entering kWalkCells macrocells without a collision (call
+// again to continue; the walk and its random draws are the same as without
+// the pause).  Empty cells draw no random
 // numbers and coarse-block faces are macrocell faces, so the tentative
 // collisions are those of a uniform walk over every macrocell; a flight that
 // overshoots a cell restarts at its exit (memorylessness).
-template <class Acc>
-__device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK& m,
-                                              const float* __restrict__ maj,
-                                              const uint32_t* cbits, const PtArgs& g, Rng& rng,
-                                              float& sv, uint32_t& nsamp, uint32_t& ncell)
+__device__ __forceinline__ int flight_advance(Flight& f, const float* __restrict__ maj, const uint32_t* cbits,
+                                              const PtArgs& g, Rng& rng, uint32_t& ncell)
 {
     if (!f.ok) return 0;
     const float C = (float)g.C;
@@ -143,9 +141,6 @@ __device__ __forceinline__ int flight_advance(Flight& f, Acc& acc, const MediumK
             f.t = fmaf(-__logf(1.0f - rng.next()), f.imu, f.t);
             if (f.t < f.te) {
                 if (--f.budget == 0) return 0;
-                sv = trilinear(acc, fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]),
-                               fmaf(f.t, f.d[2], f.o[2]));
-                ++nsamp;
                 return 1;
             }
             f.incell = false;
@@ -293,9 +288,16 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
             b0 = b1 = b2 = 1.0f;
             flight_begin(f, g, nx, ny, nz, o, d, t0p);
         }
-        float sv = 0.0f;
-        const int tentative = flight_advance(f, acc, m, maj, cbits, g, rng, sv, nsamp, ncell);
+        const int tentative = flight_advance(f, maj, cbits, g, rng, ncell);
         if (tentative == kFlightYield) continue;
+        // the density at the tentative collision is taken here, after the walk
+        // loop, so that the lanes of a wave that reached one in different
+        // steps of the walk sample in one pass
+        float sv = 0.0f;
+        if (tentative) {
+            sv = trilinear(acc, fmaf(f.t, f.d[0], f.o[0]), fmaf(f.t, f.d[1], f.o[1]), fmaf(f.t, f.d[2], f.o[2]));
+            ++nsamp;
+        }
         const bool hit = tentative && rng.next() * f.mu < m.ds * tf_alpha_at(tf_lds, m, sv);
         if (tentative && !hit) continue;    // null collision: keep tracking
         bool path_done = false, next_bounce = false;

@@ -25,6 +25,8 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
 constexpr int kWgradChunk = 2048;   // output pixels per weight-gradient partial
+constexpr int kConvTiles = 4;       // 16-pixel tiles per wave in the forward and data-gradient kernels
+constexpr int kWgradStage = 128;    // output pixels staged in LDS per step of the weight-gradient kernel
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -62,9 +64,10 @@ __device__ __forceinline__ bf16x8 gather8(const ConvIn& in, int n, int iy, int i
 }
 
 // ---------------------------------------------------------------- forward
-// out[p][co] = act(bias[co] + sum_k A[p][k] W[co][k]), k = tap * cin + ci;
-// 64 output pixels per workgroup, 16 per wave, NT tiles of 16 channels.
-template <int NT>
+// out[p][co] = act(bias[co] + sum_k A[p][k] W[co][k]), k = tap * cin + ci.
+// A wave computes MB tiles of 16 output pixels x NT tiles of 16 channels
+// (64 MB pixels per workgroup): each weight fragment it loads feeds MB MFMAs.
+template <int NT, int MB>
 __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uint16_t* __restrict__ w,
                                                             const float* __restrict__ bias, int cout,
                                                             int stride, int ho, int wo, int relu,
@@ -75,28 +78,40 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
     const int cin = in.ca + in.cb, K = 9 * cin;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
     const int64_t P = (int64_t)in.n * ho * wo;
-    const int64_t p = (int64_t)blockIdx.x * 64 + wave * 16 + r;
-    const bool pv = p < P;
-    int n = 0, oy = 0, ox = 0;
-    if (pv) {
-        ox = (int)(p % wo);
-        const int64_t q = p / wo;
-        oy = (int)(q % ho);
-        n = (int)(q / ho);
-    }
-    f4 acc[NT];
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16 * MB;   // first pixel of the wave
+    bool pv[MB];
+    int n[MB], oy[MB], ox[MB];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int m = 0; m < MB; ++m) {
+        const int64_t p = p0 + 16 * m + r;
+        pv[m] = p < P;
+        const int64_t pc = pv[m] ? p : 0;
+        ox[m] = (int)(pc % wo);
+        const int64_t q = pc / wo;
+        oy[m] = (int)(q % ho);
+        n[m] = (int)(q / ho);
+    }
+    f4 acc[MB][NT];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int kb = 0; kb < K; kb += 32) {
         const int k = kb + 8 * g;
         const int tap = k / cin, c0 = k - tap * cin;
-        bf16x8 A = zero8();
-        if (pv && tap < 9) A = gather8(in, n, oy * stride + tap / 3 - 1, ox * stride + tap % 3 - 1, c0);
+        bf16x8 B[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int co = t * 16 + r;
-            const bf16x8 B = (co < cout && tap < 9) ? load8(w + (int64_t)co * K + k) : zero8();
-            acc[t] = mfma(A, B, acc[t]);
+            B[t] = (co < cout && tap < 9) ? load8(w + (int64_t)co * K + k) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            bf16x8 A = zero8();
+            if (pv[m] && tap < 9)
+                A = gather8(in, n[m], oy[m] * stride + tap / 3 - 1, ox[m] * stride + tap % 3 - 1, c0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A, B[t], acc[m][t]);
         }
     }
 #pragma unroll
@@ -105,18 +120,20 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
         if (co >= cout) continue;
         const float bb = bias[co];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t pp = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * g + i;
-            if (pp >= P) continue;
-            float v = acc[t][i] + bb;
-            if (relu) v = fmaxf(v, 0.0f);
-            if (out_f) {
-                if (resid) v += bf2f(resid[pp * 8 + co]);
-                out_f[pp * cout + co] = v;
-            } else {
-                out_bf[pp * cout + co] = f2bf(v);
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t pp = p0 + 16 * m + 4 * g + i;
+                if (pp >= P) continue;
+                float v = acc[m][t][i] + bb;
+                if (relu) v = fmaxf(v, 0.0f);
+                if (out_f) {
+                    if (resid) v += bf2f(resid[pp * 8 + co]);
+                    out_f[pp * cout + co] = v;
+                } else {
+                    out_bf[pp * cout + co] = f2bf(v);
+                }
             }
-        }
     }
 }
 
@@ -124,8 +141,9 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
 // dx[q][c] (+)= sum_{tap, co} dz[p(q, tap)][co] Wt[c][tap][co] over the input
 // pixels q of the (virtual) input; p = ((y+1-ky)/s, (x+1-kx)/s) when that is
 // an integer output position.  dz has channel stride coutp (multiple of 8),
-// Wt is the transposed weight [cin][9][coutp].
-template <int NT>
+// Wt is the transposed weight [cin][9][coutp].  A wave computes MB tiles of
+// 16 input pixels x NT tiles of 16 channels, as the forward kernel.
+template <int NT, int MB>
 __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __restrict__ dz, int coutp,
                                                               int n_img, int ho, int wo,
                                                               const uint16_t* __restrict__ wt, int cin,
@@ -135,34 +153,45 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __
     const int K = 9 * coutp;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
     const int64_t Q = (int64_t)n_img * hv * wv;
-    const int64_t q = (int64_t)blockIdx.x * 64 + wave * 16 + r;
-    const bool qv = q < Q;
-    int n = 0, iy = 0, ix = 0;
-    if (qv) {
-        ix = (int)(q % wv);
-        const int64_t t = q / wv;
-        iy = (int)(t % hv);
-        n = (int)(t / hv);
-    }
-    f4 acc[NT];
+    const int64_t q0 = ((int64_t)blockIdx.x * 4 + wave) * 16 * MB;   // first pixel of the wave
+    bool qv[MB];
+    int n[MB], iy[MB], ix[MB];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int m = 0; m < MB; ++m) {
+        const int64_t q = q0 + 16 * m + r;
+        qv[m] = q < Q;
+        const int64_t qc = qv[m] ? q : 0;
+        ix[m] = (int)(qc % wv);
+        const int64_t t = qc / wv;
+        iy[m] = (int)(t % hv);
+        n[m] = (int)(t / hv);
+    }
+    f4 acc[MB][NT];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     for (int kb = 0; kb < K; kb += 32) {
         const int k = kb + 8 * g;
         const int tap = k / coutp, co0 = k - tap * coutp;
-        bf16x8 A = zero8();
-        if (qv && tap < 9) {
-            const int ty = iy + 1 - tap / 3, tx = ix + 1 - tap % 3;
-            if (ty >= 0 && tx >= 0 && ty % stride == 0 && tx % stride == 0) {
-                const int oy = ty / stride, ox = tx / stride;
-                if (oy < ho && ox < wo) A = load8(dz + (((int64_t)n * ho + oy) * wo + ox) * coutp + co0);
-            }
-        }
+        bf16x8 B[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int c = t * 16 + r;
-            const bf16x8 B = (c < cin && tap < 9) ? load8(wt + (int64_t)c * K + k) : zero8();
-            acc[t] = mfma(A, B, acc[t]);
+            B[t] = (c < cin && tap < 9) ? load8(wt + (int64_t)c * K + k) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            bf16x8 A = zero8();
+            if (qv[m] && tap < 9) {
+                const int ty = iy[m] + 1 - tap / 3, tx = ix[m] + 1 - tap % 3;
+                if (ty >= 0 && tx >= 0 && ty % stride == 0 && tx % stride == 0) {
+                    const int oy = ty / stride, ox = tx / stride;
+                    if (oy < ho && ox < wo) A = load8(dz + (((int64_t)n[m] * ho + oy) * wo + ox) * coutp + co0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A, B[t], acc[m][t]);
         }
     }
 #pragma unroll
@@ -170,12 +199,14 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __
         const int c = t * 16 + r;
         if (c >= cin) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t qq = (int64_t)blockIdx.x * 64 + wave * 16 + 4 * g + i;
-            if (qq >= Q) continue;
-            float* o = dx + qq * cin + c;
-            *o = accumulate ? *o + acc[t][i] : acc[t][i];
-        }
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t qq = q0 + 16 * m + 4 * g + i;
+                if (qq >= Q) continue;
+                float* o = dx + qq * cin + c;
+                *o = accumulate ? *o + acc[m][t][i] : acc[m][t][i];
+            }
     }
 }
 
@@ -193,7 +224,8 @@ __global__ void transpose_weights_kernel(const uint16_t* __restrict__ w, int cin
 // partial[chunk][co][k] = sum over the chunk's output pixels p of
 // dz[p][co] * A[p][k] with A the forward operand (k = tap * cin + ci).
 // M = co (MT tiles of 16), N = k (64 per workgroup, 16 per wave), K = pixels
-// staged 32 at a time through LDS (dz rows and im2col rows, both contiguous).
+// staged kWgradStage at a time through LDS (dz rows and im2col rows, both
+// contiguous) and consumed 32 per MFMA in pixel order.
 // The workgroups of the first k tile also sum the staged dz rows per channel:
 // bpart[chunk][c] = sum over the chunk's pixels of dz[p][c] (thread (w, c)
 // adds pixels w, w + 4, ... of each staged block, then the four wave sums in
@@ -203,8 +235,8 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
                                                               const uint16_t* __restrict__ dz, int coutp,
                                                               float* __restrict__ partial, float* __restrict__ bpart)
 {
-    __shared__ uint16_t sA[32][64 + 8];
-    __shared__ uint16_t sB[32][64 + 8];
+    __shared__ uint16_t sA[kWgradStage][64 + 8];
+    __shared__ uint16_t sB[kWgradStage][64 + 8];
     const int cin = in.ca + in.cb, K = 9 * cin;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
     const int kbase = blockIdx.y * 64;
@@ -216,26 +248,37 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
     for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     const int cg = coutp / 8;
     const bool bias = blockIdx.y == 0;   // uniform per workgroup
+    const bool small = P <= 0x7FFFFFFF;  // pixel indices fit 31 bits
     float bsum = 0.0f;
-    for (int64_t pb = p0; pb < p1; pb += 32) {
-        // dz rows: 32 pixels x coutp channels
-        for (int idx = tid; idx < 32 * cg; idx += kThreads) {
+    for (int64_t pb = p0; pb < p1; pb += kWgradStage) {
+        // dz rows: kWgradStage pixels x coutp channels
+        for (int idx = tid; idx < kWgradStage * cg; idx += kThreads) {
             const int px = idx / cg, c8 = (idx - px * cg) * 8;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (pb + px < p1) v = *reinterpret_cast<const uint4*>(dz + (pb + px) * coutp + c8);
             *reinterpret_cast<uint4*>(&sA[px][c8]) = v;
         }
-        // im2col rows: 32 pixels x 64 values of k
-        {
-            const int px = tid >> 3, kg = tid & 7;
+        // im2col rows: kWgradStage pixels x 64 values of k
+#pragma unroll
+        for (int it = 0; it < kWgradStage / 32; ++it) {
+            const int px = (tid >> 3) + 32 * it, kg = tid & 7;
             const int k = kbase + kg * 8;
             bf16x8 v = zero8();
             const int64_t p = pb + px;
             if (p < p1 && k < K) {
                 const int tap = k / cin, c0 = k - tap * cin;
-                const int ox = (int)(p % wo);
-                const int64_t q = p / wo;
-                const int oy = (int)(q % ho), n = (int)(q / ho);
+                int ox, oy, n;
+                if (small) {   // 32-bit division (uniform branch)
+                    const uint32_t pu = (uint32_t)p, q = pu / (uint32_t)wo, nn = q / (uint32_t)ho;
+                    ox = (int)(pu - q * (uint32_t)wo);
+                    oy = (int)(q - nn * (uint32_t)ho);
+                    n = (int)nn;
+                } else {
+                    ox = (int)(p % wo);
+                    const int64_t q = p / wo;
+                    oy = (int)(q % ho);
+                    n = (int)(q / ho);
+                }
                 v = gather8(in, n, oy * stride + tap / 3 - 1, ox * stride + tap % 3 - 1, c0);
             }
             *reinterpret_cast<uint4*>(&sB[px][kg * 8]) = __builtin_bit_cast(uint4, v);
@@ -243,20 +286,23 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
         __syncthreads();
         if (bias && lane < coutp) {
             // rows past the chunk's end were staged as zeros
-#pragma unroll
-            for (int j = 0; j < 8; ++j) bsum += bf2f(sA[wave + 4 * j][lane]);
+#pragma unroll 8
+            for (int j = 0; j < kWgradStage / 4; ++j) bsum += bf2f(sA[wave + 4 * j][lane]);
         }
-        bf16x8 B;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) B[j] = __builtin_bit_cast(__bf16, sB[8 * g + j][16 * wave + r]);
+        for (int sub = 0; sub < kWgradStage; sub += 32) {
+            bf16x8 B;
 #pragma unroll
-        for (int t = 0; t < MT; ++t) {
-            bf16x8 A;
-            const int co = t * 16 + r;
+            for (int j = 0; j < 8; ++j) B[j] = __builtin_bit_cast(__bf16, sB[sub + 8 * g + j][16 * wave + r]);
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                A[j] = co < coutp ? __builtin_bit_cast(__bf16, sA[8 * g + j][co]) : (__bf16)0.0f;
-            acc[t] = mfma(A, B, acc[t]);
+            for (int t = 0; t < MT; ++t) {
+                bf16x8 A;
+                const int co = t * 16 + r;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    A[j] = co < coutp ? __builtin_bit_cast(__bf16, sA[sub + 8 * g + j][co]) : (__bf16)0.0f;
+                acc[t] = mfma(A, B, acc[t]);
+            }
         }
         __syncthreads();
     }
@@ -461,16 +507,16 @@ vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const floa
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
     const uint64_t P = (uint64_t)in.n * ho * wo;
-    const unsigned gb = blocks(P, 64);
-    if (cout <= 16)
-        hipLaunchKernelGGL(conv_fwd_kernel<1>, dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout, stride, ho,
-                           wo, relu, out_bf, out_f, resid);
+    const unsigned gb = blocks(P, 64 * kConvTiles);
+    if (cout <= 16)   // one channel tile: one pixel tile per wave keeps more workgroups in flight
+        hipLaunchKernelGGL((conv_fwd_kernel<1, 1>), dim3(blocks(P, 64)), dim3(kThreads), 0, st, in, w, bias, cout,
+                           stride, ho, wo, relu, out_bf, out_f, resid);
     else if (cout <= 32)
-        hipLaunchKernelGGL(conv_fwd_kernel<2>, dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout, stride, ho,
-                           wo, relu, out_bf, out_f, resid);
+        hipLaunchKernelGGL((conv_fwd_kernel<2, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout,
+                           stride, ho, wo, relu, out_bf, out_f, resid);
     else
-        hipLaunchKernelGGL(conv_fwd_kernel<4>, dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout, stride, ho,
-                           wo, relu, out_bf, out_f, resid);
+        hipLaunchKernelGGL((conv_fwd_kernel<4, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, in, w, bias, cout,
+                           stride, ho, wo, relu, out_bf, out_f, resid);
     return check("conv3x3 forward");
 }
 
@@ -481,16 +527,16 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
     hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks((uint64_t)cin * 9 * coutp)), dim3(kThreads), 0, st,
                        w, cin, cout, coutp, wt);
     const uint64_t Q = (uint64_t)n * hv * wv;
-    const unsigned gb = blocks(Q, 64);
+    const unsigned gb = blocks(Q, 64 * kConvTiles);
     if (cin <= 16)
-        hipLaunchKernelGGL(conv_dgrad_kernel<1>, dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho, wo, wt, cin,
-                           stride, hv, wv, dx, accumulate);
+        hipLaunchKernelGGL((conv_dgrad_kernel<1, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
+                           wo, wt, cin, stride, hv, wv, dx, accumulate);
     else if (cin <= 32)
-        hipLaunchKernelGGL(conv_dgrad_kernel<2>, dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho, wo, wt, cin,
-                           stride, hv, wv, dx, accumulate);
+        hipLaunchKernelGGL((conv_dgrad_kernel<2, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
+                           wo, wt, cin, stride, hv, wv, dx, accumulate);
     else
-        hipLaunchKernelGGL(conv_dgrad_kernel<4>, dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho, wo, wt, cin,
-                           stride, hv, wv, dx, accumulate);
+        hipLaunchKernelGGL((conv_dgrad_kernel<4, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
+                           wo, wt, cin, stride, hv, wv, dx, accumulate);
     return check("conv3x3 data gradient");
 }
 

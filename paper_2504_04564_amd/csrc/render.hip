@@ -331,8 +331,8 @@ static uint64_t majorant_bytes(uint32_t C, int nx, int ny, int nz)
 }
 
 // Majorant grid and coarse occupancy geometry.  Coarse blocks are 2^lf
-// macrocells per axis, the largest power of two spanning at most 32 voxels (one
-// brick), doubled until the bit mask fits in 32 KB of LDS.
+// macrocells per axis, the largest power of two spanning at most 64 voxels
+// (2^3 bricks), doubled until the bit mask fits in 32 KB of LDS.
 static void pt_geometry(uint32_t C, int nx, int ny, int nz, PtArgs* g)
 {
     g->C = (int)C;
@@ -341,7 +341,7 @@ static void pt_geometry(uint32_t C, int nx, int ny, int nz, PtArgs* g)
     g->gy = (ny + g->C - 1) / g->C;
     g->gz = (nz + g->C - 1) / g->C;
     int lf = 0;
-    while ((C << (lf + 1)) <= 32) ++lf;      // block edge C * 2^lf <= 32 voxels
+    while ((C << (lf + 1)) <= 64) ++lf;      // block edge C * 2^lf <= 64 voxels
     for (;;) {
         const int F = 1 << lf;
         g->lf = lf;

@@ -69,7 +69,7 @@ __device__ __forceinline__ void flight_begin(Flight& f, const PtArgs& g, int nx,
     for (int a = 0; a < 3; ++a) {
         f.o[a] = o[a];
         f.d[a] = d[a];
-        f.id[a] = 1.0f / d[a];
+        f.id[a] = __builtin_amdgcn_rcpf(d[a]);   // hardware reciprocal (<= 1 ulp; 1/0 -> inf)
     }
     f.incell = false;
     f.budget = kMaxFlightSamples;
@@ -194,7 +194,7 @@ __device__ __forceinline__ int flight_advance(Flight& f, const float* __restrict
         f.mu = maj[f.cx + g.gx * (f.cy + g.gy * f.cz)];
         if (f.mu > 0.0f && f.t < f.te) {
             f.incell = true;
-            f.imu = 1.0f / f.mu;
+            f.imu = __builtin_amdgcn_rcpf(f.mu);   // hardware reciprocal (<= 1 ulp)
             continue;
         }
         if (f.axis < 0) return 0;

@@ -26,7 +26,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int kThreads = 256;
 constexpr int kWgradChunk = 2048;   // output pixels per weight-gradient partial
 constexpr int kConvTiles = 4;       // 16-pixel tiles per wave in the forward and data-gradient kernels
-constexpr int kWgradStage = 128;    // output pixels staged in LDS per step of the weight-gradient kernel
+constexpr int kWgradStage = 64;     // output pixels staged in LDS per step of the weight-gradient kernel
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -250,15 +250,19 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
     const bool bias = blockIdx.y == 0;   // uniform per workgroup
     const bool small = P <= 0x7FFFFFFF;  // pixel indices fit 31 bits
     float bsum = 0.0f;
-    for (int64_t pb = p0; pb < p1; pb += kWgradStage) {
-        // dz rows: kWgradStage pixels x coutp channels
-        for (int idx = tid; idx < kWgradStage * cg; idx += kThreads) {
-            const int px = idx / cg, c8 = (idx - px * cg) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (pb + px < p1) v = *reinterpret_cast<const uint4*>(dz + (pb + px) * coutp + c8);
-            *reinterpret_cast<uint4*>(&sA[px][c8]) = v;
+    // The global loads of the next stage are issued before the MFMAs of the
+    // current one and land in registers; they are written to LDS at the top
+    // of the next step, so each step waits on loads issued a step earlier.
+    uint4 ra[kWgradStage * 8 / kThreads];   // dz rows: kWgradStage pixels x coutp (<= 64) channels
+    uint4 rb[kWgradStage / 32];             // im2col rows: kWgradStage pixels x 64 values of k
+    auto fetch = [&](int64_t pb) {
+#pragma unroll
+        for (int i = 0; i < kWgradStage * 8 / kThreads; ++i) {
+            const int idx = tid + kThreads * i, px = idx / cg, c8 = (idx - px * cg) * 8;
+            ra[i] = make_uint4(0, 0, 0, 0);
+            if (idx < kWgradStage * cg && pb + px < p1)
+                ra[i] = *reinterpret_cast<const uint4*>(dz + (pb + px) * coutp + c8);
         }
-        // im2col rows: kWgradStage pixels x 64 values of k
 #pragma unroll
         for (int it = 0; it < kWgradStage / 32; ++it) {
             const int px = (tid >> 3) + 32 * it, kg = tid & 7;
@@ -281,9 +285,21 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
                 }
                 v = gather8(in, n, oy * stride + tap / 3 - 1, ox * stride + tap % 3 - 1, c0);
             }
-            *reinterpret_cast<uint4*>(&sB[px][kg * 8]) = __builtin_bit_cast(uint4, v);
+            rb[it] = __builtin_bit_cast(uint4, v);
         }
+    };
+    fetch(p0);
+    for (int64_t pb = p0; pb < p1; pb += kWgradStage) {
+#pragma unroll
+        for (int i = 0; i < kWgradStage * 8 / kThreads; ++i) {
+            const int idx = tid + kThreads * i, px = idx / cg, c8 = (idx - px * cg) * 8;
+            if (idx < kWgradStage * cg) *reinterpret_cast<uint4*>(&sA[px][c8]) = ra[i];
+        }
+#pragma unroll
+        for (int it = 0; it < kWgradStage / 32; ++it)
+            *reinterpret_cast<uint4*>(&sB[(tid >> 3) + 32 * it][(tid & 7) * 8]) = rb[it];
         __syncthreads();
+        if (pb + kWgradStage < p1) fetch(pb + kWgradStage);
         if (bias && lane < coutp) {
             // rows past the chunk's end were staged as zeros
 #pragma unroll 8

@@ -96,23 +96,35 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
     for (int m = 0; m < MB; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int kb = 0; kb < K; kb += 32) {
+    // operands of k step kb + 32 are loaded while the MFMAs of step kb run
+    bf16x8 Bn[NT], An[MB];
+    auto fetch = [&](int kb) {
         const int k = kb + 8 * g;
         const int tap = k / cin, c0 = k - tap * cin;
-        bf16x8 B[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const int co = t * 16 + r;
-            B[t] = (co < cout && tap < 9) ? load8(w + (int64_t)co * K + k) : zero8();
+            Bn[t] = (co < cout && tap < 9) ? load8(w + (int64_t)co * K + k) : zero8();
         }
 #pragma unroll
         for (int m = 0; m < MB; ++m) {
-            bf16x8 A = zero8();
+            An[m] = zero8();
             if (pv[m] && tap < 9)
-                A = gather8(in, n[m], oy[m] * stride + tap / 3 - 1, ox[m] * stride + tap % 3 - 1, c0);
-#pragma unroll
-            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A, B[t], acc[m][t]);
+                An[m] = gather8(in, n[m], oy[m] * stride + tap / 3 - 1, ox[m] * stride + tap % 3 - 1, c0);
         }
+    };
+    fetch(0);
+    for (int kb = 0; kb < K; kb += 32) {
+        bf16x8 B[NT], A[MB];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) B[t] = Bn[t];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) A[m] = An[m];
+        if (kb + 32 < K) fetch(kb + 32);
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -342,36 +354,36 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
 
 // grad[co][k] = sum over chunks of partial[chunk][co][k]: a workgroup takes
 // 64 consecutive (co, k) entries, wave w adds chunks w, w + 4, ... in order,
-// then the four wave sums are added in order (deterministic).
+// then the four wave sums are added in order (deterministic).  The last
+// workgroup does the same for the bias: db[c] = sum over chunks of
+// bpart[chunk][c] (c < cout <= 64).
 __global__ __launch_bounds__(kThreads) void wgrad_reduce_kernel(const float* __restrict__ partial, int chunks,
-                                                                int mpad, int cout, int K, float* __restrict__ grad)
+                                                                int mpad, int cout, int K, float* __restrict__ grad,
+                                                                const float* __restrict__ bpart, int coutp,
+                                                                float* __restrict__ db)
 {
     __shared__ float s[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (blockIdx.x == gridDim.x - 1) {
+        float r = 0.0f;
+        if (lane < cout)
+#pragma unroll 8
+            for (int k = w; k < chunks; k += 4) r += bpart[(int64_t)k * coutp + lane];
+        s[w][lane] = r;
+        __syncthreads();
+        if (threadIdx.x < cout) db[lane] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
+        return;
+    }
     const int i = blockIdx.x * 64 + lane;
     float r = 0.0f;
     if (i < cout * K) {
         const int co = i / K, k = i - co * K;
+#pragma unroll 8
         for (int c = w; c < chunks; c += 4) r += partial[((int64_t)c * mpad + co) * K + k];
     }
     s[w][lane] = r;
     __syncthreads();
     if (w == 0 && i < cout * K) grad[i] = ((s[0][lane] + s[1][lane]) + s[2][lane]) + s[3][lane];
-}
-
-// db[c] = sum over chunks of bpart[chunk][c] (c < cout <= 64), in the same
-// order as wgrad_reduce_kernel.
-__global__ __launch_bounds__(kThreads) void bias_reduce_kernel(const float* __restrict__ bpart, int chunks,
-                                                               int coutp, int cout, float* __restrict__ db)
-{
-    __shared__ float s[4][64];
-    const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float r = 0.0f;
-    if (c < cout)
-        for (int k = w; k < chunks; k += 4) r += bpart[(int64_t)k * coutp + c];
-    s[w][c] = r;
-    __syncthreads();
-    if (threadIdx.x < cout) db[c] = ((s[0][c] + s[1][c]) + s[2][c]) + s[3][c];
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -587,9 +599,8 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     else
         hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
                            bpart);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)(((uint64_t)cout * K + 63) / 64)), dim3(kThreads), 0, st,
-                       partial, (int)chunks, mt * 16, cout, K, dw);
-    hipLaunchKernelGGL(bias_reduce_kernel, dim3(1), dim3(kThreads), 0, st, bpart, (int)chunks, coutp, cout, db);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)(((uint64_t)cout * K + 63) / 64) + 1), dim3(kThreads), 0, st,
+                       partial, (int)chunks, mt * 16, cout, K, dw, bpart, coutp, db);
     return check("conv3x3 weight gradient");
 }
 

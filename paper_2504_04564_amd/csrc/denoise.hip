@@ -24,9 +24,23 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kWgradChunk = 2048;   // output pixels per weight-gradient partial
+constexpr int kWgradChunkMax = 2048;   // output pixels per weight-gradient partial, at most
+constexpr int kWgradChunkMin = 256;    // ... and at least
+constexpr uint64_t kWgradGroups = 2048;   // workgroups a weight-gradient launch aims for (8 per CU)
 constexpr int kConvTiles = 4;       // 16-pixel tiles per wave in the forward and data-gradient kernels
 constexpr int kWgradStage = 64;     // output pixels staged in LDS per step of the weight-gradient kernel
+
+// Output pixels per weight-gradient partial for P output pixels and a
+// contraction of K: halved from the maximum while the launch (partials x
+// 64-wide k tiles) would have fewer than kWgradGroups workgroups, so that
+// the half-resolution layers and the narrow first layer fill the chip.
+int wgrad_chunk(uint64_t P, int K)
+{
+    const uint64_t kb = (uint64_t)(K + 63) / 64;
+    int c = kWgradChunkMax;
+    while (c > kWgradChunkMin && (P + c - 1) / c * kb < kWgradGroups) c /= 2;
+    return c;
+}
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -244,7 +258,7 @@ __global__ void transpose_weights_kernel(const uint16_t* __restrict__ w, int cin
 // order), the bias gradient's partials.
 template <int MT>
 __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int stride, int ho, int wo,
-                                                              const uint16_t* __restrict__ dz, int coutp,
+                                                              const uint16_t* __restrict__ dz, int coutp, int chunk,
                                                               float* __restrict__ partial, float* __restrict__ bpart)
 {
     __shared__ uint16_t sA[kWgradStage][64 + 8];
@@ -253,8 +267,8 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
     const int kbase = blockIdx.y * 64;
     const int64_t P = (int64_t)in.n * ho * wo;
-    const int64_t p0 = (int64_t)blockIdx.x * kWgradChunk;
-    const int64_t p1 = p0 + kWgradChunk < P ? p0 + kWgradChunk : P;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk;
+    const int64_t p1 = p0 + chunk < P ? p0 + chunk : P;
     f4 acc[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -574,7 +588,7 @@ uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
 {
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const uint64_t P = (uint64_t)in.n * ((hv - 1) / stride + 1) * ((wv - 1) / stride + 1);
-    const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
+    const uint64_t c = wgrad_chunk(P, 9 * (in.ca + in.cb)), chunks = (P + c - 1) / c;
     const int mpad = (cout + 15) / 16 * 16;
     return chunks * mpad * 9ull * (in.ca + in.cb) + chunks * 64ull;
 }
@@ -586,18 +600,19 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
     const int64_t P = (int64_t)in.n * ho * wo;
-    const unsigned chunks = (unsigned)((P + kWgradChunk - 1) / kWgradChunk);
+    const int chunk = wgrad_chunk(P, K);
+    const unsigned chunks = (unsigned)((P + chunk - 1) / chunk);
     const int mt = (cout + 15) / 16;
     dim3 grid(chunks, (K + 63) / 64);
     float* bpart = partial + (uint64_t)chunks * (mt * 16) * K;
     if (mt == 1)
-        hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
+        hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, chunk, partial,
                            bpart);
     else if (mt == 2)
-        hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
+        hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, chunk, partial,
                            bpart);
     else
-        hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, partial,
+        hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, chunk, partial,
                            bpart);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)(((uint64_t)cout * K + 63) / 64) + 1), dim3(kThreads), 0, st,
                        partial, (int)chunks, mt * 16, cout, K, dw, bpart, coutp, db);
@@ -618,6 +633,23 @@ struct NetLayout {
 };
 
 uint64_t al(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
+
+// The largest weight-gradient partials of the network's six layers, with the
+// inputs, strides and output channels of the training step's backward pass.
+uint64_t net_partial_floats(uint32_t n, uint32_t h, uint32_t w)
+{
+    const int N = (int)n, H = (int)h, W = (int)w;
+    const uint64_t f[6] = {
+        wgrad_partial_floats(ConvIn{nullptr, nullptr, 32, 0, 0, N, H, W}, 1, 3),
+        wgrad_partial_floats(ConvIn{nullptr, nullptr, 32, 32, 0, N, H, W}, 1, 32),
+        wgrad_partial_floats(ConvIn{nullptr, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, 32),
+        wgrad_partial_floats(ConvIn{nullptr, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, 64),
+        wgrad_partial_floats(ConvIn{nullptr, nullptr, 32, 0, 0, N, H, W}, 2, 64),
+        wgrad_partial_floats(ConvIn{nullptr, nullptr, 8, 0, 0, N, H, W}, 1, 32)};
+    uint64_t m = 0;
+    for (uint64_t x : f) m = x > m ? x : m;
+    return m;
+}
 
 NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
 {
@@ -648,8 +680,7 @@ NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
         L.dy1 = take(P * 32 * 4);
         L.dz1 = take(P * 32 * 2);
         L.wt = take(64 * 9 * 64 * 2);
-        const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
-        L.partial = take(chunks * (64 * 9 * 64 + 64) * 4);
+        L.partial = take(net_partial_floats(n, h, w) * 4);
         L.lpart = take((P + kThreads - 1) / kThreads * 4 + 16);
         L.grad = take(nn::param_count() * 4);
     }
@@ -858,7 +889,7 @@ extern "C" vdbc_status vdbc_conv3x3_grad_workspace(uint32_t cin, uint32_t cout, 
     clear_error();
     if (!bytes || cin == 0 || cin > 64 || cout == 0 || cout > 64) return fail(VDBC_E_INVALID, "bad argument");
     const uint64_t P = (uint64_t)n * ho * wo;
-    const uint64_t chunks = (P + kWgradChunk - 1) / kWgradChunk;
+    const uint64_t c = wgrad_chunk(P, 9 * (int)cin), chunks = (P + c - 1) / c;
     *bytes = al(64ull * 9 * 64 * 2) + al(chunks * (64ull * 9 * cin + 64) * 4);
     return VDBC_OK;
 }

@@ -576,8 +576,8 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
     else if (cin <= 32)
         hipLaunchKernelGGL((conv_dgrad_kernel<2, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
                            wo, wt, cin, stride, hv, wv, dx, accumulate);
-    else
-        hipLaunchKernelGGL((conv_dgrad_kernel<4, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
+    else   // four channel tiles: two pixel tiles per wave (fewer registers, more waves in flight)
+        hipLaunchKernelGGL((conv_dgrad_kernel<4, 2>), dim3(blocks(Q, 128)), dim3(kThreads), 0, st, dz, coutp, n, ho,
                            wo, wt, cin, stride, hv, wv, dx, accumulate);
     return check("conv3x3 data gradient");
 }

@@ -85,6 +85,26 @@ def test_conv_gradients(ca, cb, up, stride, cout, n, hs, ws):
     assert rel(db.cpu().numpy(), rdb) <= 1e-5
 
 
+# Sizes at which a weight-gradient partial covers more than the smallest
+# pixel chunk: 64 input channels over 257 x 511 pixels (partials of 512
+# pixels, eight LDS stages each, the last partial ragged) and the first
+# layer's 8 input channels at batch 8 x 512^2 (partials of 2048 pixels).
+WGRAD_LARGE = [(64, 0, 0, 1, 64, 1, 257, 511), (8, 0, 0, 1, 32, 8, 512, 512)]
+
+
+@pytest.mark.parametrize("ca,cb,up,stride,cout,n,hs,ws", WGRAD_LARGE)
+def test_conv_weight_gradient_large(ca, cb, up, stride, cout, n, hs, ws):
+    rng = np.random.default_rng(ca + cout + hs)
+    a, a64 = _bf(rng, (n, hs, ws, ca))
+    dz_np = rng.normal(size=(n, hs, ws, cout)).astype(np.float32)
+    dz = torch.from_numpy(dz_np).to(torch.bfloat16)
+    dz64 = dz.to(torch.float64).numpy()
+    dw, db = vdbc.conv3x3_wgrad(a, None, up, stride, dz.cuda(), cout)
+    rdw, rdb = nn.conv_wgrad(a64, dz64, stride)
+    assert rel(dw.cpu().numpy(), rdw) <= 1e-5
+    assert rel(db.cpu().numpy(), rdb) <= 1e-5
+
+
 def _batch(rng, n, h, w):
     x = np.zeros((n, h, w, 8), np.float32)
     x[..., :3] = rng.uniform(0, 1.2, size=(n, h, w, 3))

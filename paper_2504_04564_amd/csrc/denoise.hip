@@ -594,8 +594,12 @@ uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
 }
 
 vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int coutp, int cout, float* dw,
-                       float* db, float* partial, hipStream_t st)
+                       float* db, float* partial, uint64_t partial_floats, hipStream_t st)
 {
+    const uint64_t need = wgrad_partial_floats(in, stride, cout);
+    if (need > partial_floats)
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "weight-gradient partials need %llu floats, the workspace holds %llu",
+                    (unsigned long long)need, (unsigned long long)partial_floats);
     const int cin = in.ca + in.cb, K = 9 * cin;
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
@@ -823,24 +827,25 @@ extern "C" vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, f
     auto gB = [&](int l) { return grad + bias_offset(l); };
     uint16_t *c1 = U(L.c1), *c2 = U(L.c2), *c3 = U(L.c3), *c4 = U(L.c4), *c5 = U(L.c5);
     float* part = F(L.partial);
+    const uint64_t pf = net_partial_floats(N, H, W);
     uint16_t* wt = U(L.wt);
     // c6: 32 -> 3 (dz6 padded to 8 channels)
-    if ((s = conv_wgrad(ConvIn{c5, nullptr, 32, 0, 0, N, H, W}, 1, U(L.dz6), 8, 3, gW(5), gB(5), part, st))) return s;
+    if ((s = conv_wgrad(ConvIn{c5, nullptr, 32, 0, 0, N, H, W}, 1, U(L.dz6), 8, 3, gW(5), gB(5), part, pf, st))) return s;
     if ((s = conv_dgrad(U(L.dz6), 8, 3, N, H, W, Wl(5), 32, 1, H, W, F(L.dy5), 0, wt, st))) return s;
     if ((s = relu_back(ReluBack{F(L.dy5), 32, 0, nullptr, 0, 0, c5, 32, 32, 0, N, H, W}, U(L.dz5), st))) return s;
     // c5: concat(c1, c4) 64 -> 32
-    if ((s = conv_wgrad(ConvIn{c1, c4, 32, 32, 0, N, H, W}, 1, U(L.dz5), 32, 32, gW(4), gB(4), part, st))) return s;
+    if ((s = conv_wgrad(ConvIn{c1, c4, 32, 32, 0, N, H, W}, 1, U(L.dz5), 32, 32, gW(4), gB(4), part, pf, st))) return s;
     if ((s = conv_dgrad(U(L.dz5), 32, 32, N, H, W, Wl(4), 64, 1, H, W, F(L.dcat), 0, wt, st))) return s;
     if ((s = relu_back(ReluBack{F(L.dcat), 64, 32, nullptr, 0, 0, c4, 32, 32, 0, N, H, W}, U(L.dz4), st))) return s;
     // c4: up2(c3) 64 -> 32
-    if ((s = conv_wgrad(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, U(L.dz4), 32, 32, gW(3), gB(3), part,
+    if ((s = conv_wgrad(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, U(L.dz4), 32, 32, gW(3), gB(3), part, pf,
                         st)))
         return s;
     if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, F(L.du), 0, wt, st))) return s;
     if ((s = relu_back(ReluBack{F(L.du), 64, 0, nullptr, 0, 0, c3, 64, 64, 1, N, H / 2, W / 2}, U(L.dz3), st)))
         return s;
     // c3: 64 -> 64 at half resolution
-    if ((s = conv_wgrad(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, U(L.dz3), 64, 64, gW(2), gB(2), part,
+    if ((s = conv_wgrad(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, U(L.dz3), 64, 64, gW(2), gB(2), part, pf,
                         st)))
         return s;
     if ((s = conv_dgrad(U(L.dz3), 64, 64, N, H / 2, W / 2, Wl(2), 64, 1, H / 2, W / 2, F(L.dy2), 0, wt, st)))
@@ -848,13 +853,13 @@ extern "C" vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, f
     if ((s = relu_back(ReluBack{F(L.dy2), 64, 0, nullptr, 0, 0, c2, 64, 64, 0, N, H / 2, W / 2}, U(L.dz2), st)))
         return s;
     // c2: 32 -> 64, stride 2
-    if ((s = conv_wgrad(ConvIn{c1, nullptr, 32, 0, 0, N, H, W}, 2, U(L.dz2), 64, 64, gW(1), gB(1), part, st)))
+    if ((s = conv_wgrad(ConvIn{c1, nullptr, 32, 0, 0, N, H, W}, 2, U(L.dz2), 64, 64, gW(1), gB(1), part, pf, st)))
         return s;
     if ((s = conv_dgrad(U(L.dz2), 64, 64, N, H / 2, W / 2, Wl(1), 32, 2, H, W, F(L.dy1), 0, wt, st))) return s;
     if ((s = relu_back(ReluBack{F(L.dcat), 64, 0, F(L.dy1), 32, 0, c1, 32, 32, 0, N, H, W}, U(L.dz1), st)))
         return s;
     // c1: 8 -> 32 (no data gradient needed)
-    if ((s = conv_wgrad(ConvIn{x, nullptr, 8, 0, 0, N, H, W}, 1, U(L.dz1), 32, 32, gW(0), gB(0), part, st)))
+    if ((s = conv_wgrad(ConvIn{x, nullptr, 8, 0, 0, N, H, W}, 1, U(L.dz1), 32, 32, gW(0), gB(0), part, pf, st)))
         return s;
     if (lr > 0.0f) {
         const double c1d = 1.0 - std::pow(0.9, (double)step), c2d = 1.0 - std::pow(0.999, (double)step);
@@ -925,5 +930,6 @@ extern "C" vdbc_status vdbc_conv3x3_wgrad(const uint16_t* a, uint32_t ca, const 
     if (ws_bytes < need) return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace needs %llu bytes", (unsigned long long)need);
     if (!aligned16(a) || !aligned16(b) || !aligned16(dz)) return fail(VDBC_E_INVALID, "operands must be 16-byte aligned");
     float* part = reinterpret_cast<float*>(static_cast<uint8_t*>(ws) + al(64ull * 9 * 64 * 2));
-    return conv_wgrad(in, (int)stride, dz, (int)coutp, (int)cout, dw, db, part, static_cast<hipStream_t>(stream));
+    return conv_wgrad(in, (int)stride, dz, (int)coutp, (int)cout, dw, db, part, wgrad_partial_floats(in, (int)stride, (int)cout),
+                      static_cast<hipStream_t>(stream));
 }

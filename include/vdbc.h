@@ -51,6 +51,11 @@ const char* vdbc_status_string(vdbc_status s);
 const char* vdbc_last_error(void);
 uint32_t vdbc_abi_version(void);
 
+/* Hash (16 hex digits, static string) of the sources, header and flags the
+ * library was built from.  Loaders compare it with the tree they run from
+ * and refuse a stale build. */
+const char* vdbc_source_hash(void);
+
 typedef struct {
     uint32_t nx, ny, nz;
 } vdbc_dims;
@@ -241,7 +246,8 @@ typedef struct {
     uint64_t seed;          /* PT Philox key material */
     uint32_t frame;         /* PT counter word 3 */
     uint32_t tile_w;        /* PT pixels per wave row: 8 (default; 0 = 8), 16, 32, 64;
-                               the image does not depend on it */
+                               any other value -> VDBC_E_INVALID; the image does not
+                               depend on it */
     float iso;              /* ISO: iso value */
     uint32_t refine;        /* ISO: bisection steps on the crossing interval (<= 64) */
 } vdbc_render_params;

@@ -23,15 +23,37 @@ REF_NO_CORNERS = 2
 REF_NO_PRUNE = 4
 
 
+_HASH_PATH = _LIB_PATH + ".hash"
+
+
+def _source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for s in sorted(_SOURCES + ["oracle.h"]):
+        with open(os.path.join(_HERE, s), "rb") as fh:
+            h.update(s.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (-O2, IEEE arithmetic, no contraction)."""
-    if force or not os.path.exists(_LIB_PATH):
+    """Compile liboracle.so with gcc (-O2, IEEE arithmetic, no contraction);
+    without `force`, only when it is missing or was built from other
+    sources (the hash of the sources is kept beside the library)."""
+    want = _source_hash()
+    have = None
+    if os.path.exists(_HASH_PATH):
+        with open(_HASH_PATH) as fh:
+            have = fh.read().strip()
+    if force or not os.path.exists(_LIB_PATH) or have != want:
         srcs = [os.path.join(_HERE, s) for s in _SOURCES]
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
                "-fPIC", "-shared", "-Wall", "-o", tmp] + srcs + ["-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
+        with open(_HASH_PATH + ".tmp%d" % os.getpid(), "w") as fh:
+            fh.write(want + "\n")
+        os.replace(_HASH_PATH + ".tmp%d" % os.getpid(), _HASH_PATH)
     return _LIB_PATH
 
 

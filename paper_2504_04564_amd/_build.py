@@ -26,6 +26,22 @@ HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra",
               "-Wno-unused-parameter", "-I", os.path.join(ROOT, "include")]
 
 
+def source_hash() -> str:
+    """Hash of everything the library is built from: the sources under
+    csrc/, the public header and the compiler flags (16 hex digits)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".cpp", ".h", ".hip")))
+    for f in files:
+        h.update(f.encode() + b"\0")
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(ROOT, "include", "vdbc.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(HIP_FLAGS[:1] + HOST_FLAGS[:1] + [ARCH]).encode())
+    return h.hexdigest()[:16]
+
+
 def _run(cmd):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -38,9 +54,11 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libvdbc.so (always rebuilds)."""
     os.makedirs(OBJ, exist_ok=True)
     jobs = []
+    stamp = [f'-DVDBC_SOURCE_HASH="{source_hash()}"']
     for s in HOST_SOURCES:
         o = os.path.join(OBJ, s + ".o")
-        jobs.append(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        jobs.append(["g++"] + HOST_FLAGS + (stamp if s == "api.cpp" else []) +
+                    ["-c", os.path.join(CSRC, s), "-o", o])
     for s in HIP_SOURCES:
         o = os.path.join(OBJ, s + ".o")
         jobs.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
@@ -55,10 +73,29 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def built_hash(path: str = LIB) -> str:
+    """Source hash recorded in a built library (vdbc_source_hash)."""
+    import ctypes
+    L = ctypes.CDLL(path)
+    L.vdbc_source_hash.restype = ctypes.c_char_p
+    return L.vdbc_source_hash().decode()
+
+
+class StaleLibrary(RuntimeError):
+    pass
+
+
 def ensure_built() -> str:
-    """Builds only when no library exists yet."""
+    """Builds when no library exists yet; refuses (StaleLibrary) a library
+    built from sources other than the ones in the tree, so a stale binary is
+    never tested or measured."""
     if not os.path.exists(LIB):
         build()
+        return LIB
+    have, want = built_hash(), source_hash()
+    if have != want:
+        raise StaleLibrary(f"{LIB} was built from sources {have}, the tree holds {want}: "
+                           "rebuild with `python -m paper_2504_04564_amd._build`")
     return LIB
 
 

@@ -162,6 +162,11 @@ extern "C" const char* vdbc_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" uint32_t vdbc_abi_version(void) { return VDBC_ABI_VERSION; }
 
+#ifndef VDBC_SOURCE_HASH
+#define VDBC_SOURCE_HASH "unknown"
+#endif
+extern "C" const char* vdbc_source_hash(void) { return VDBC_SOURCE_HASH; }
+
 extern "C" vdbc_status vdbc_validate(const void* buf, uint64_t bytes, vdbc_encode_stats* info)
 {
     clear_error();

@@ -582,6 +582,11 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
     return check("conv3x3 data gradient");
 }
 
+// 16-channel output tiles of the weight-gradient kernel launched for `cout`
+// output channels: 1, 2 or 4 (33..64 channels take the four-tile kernel, so
+// its partial rows are 64 apart).
+int wgrad_mt(int cout) { return cout <= 16 ? 1 : cout <= 32 ? 2 : 4; }
+
 // Floats of the weight-gradient partials followed by the bias partials
 // (chunks x coutp, coutp <= 64).
 uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
@@ -589,7 +594,7 @@ uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const uint64_t P = (uint64_t)in.n * ((hv - 1) / stride + 1) * ((wv - 1) / stride + 1);
     const uint64_t c = wgrad_chunk(P, 9 * (in.ca + in.cb)), chunks = (P + c - 1) / c;
-    const int mpad = (cout + 15) / 16 * 16;
+    const int mpad = wgrad_mt(cout) * 16;
     return chunks * mpad * 9ull * (in.ca + in.cb) + chunks * 64ull;
 }
 
@@ -606,7 +611,7 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     const int64_t P = (int64_t)in.n * ho * wo;
     const int chunk = wgrad_chunk(P, K);
     const unsigned chunks = (unsigned)((P + chunk - 1) / chunk);
-    const int mt = (cout + 15) / 16;
+    const int mt = wgrad_mt(cout);
     dim3 grid(chunks, (K + 63) / 64);
     float* bpart = partial + (uint64_t)chunks * (mt * 16) * K;
     if (mt == 1)
@@ -615,7 +620,7 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     else if (mt == 2)
         hipLaunchKernelGGL(conv_wgrad_kernel<2>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, chunk, partial,
                            bpart);
-    else
+    else   // mt == 4
         hipLaunchKernelGGL(conv_wgrad_kernel<4>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, chunk, partial,
                            bpart);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)(((uint64_t)cout * K + 63) / 64) + 1), dim3(kThreads), 0, st,

@@ -478,6 +478,8 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     // 16-bit field of the random-number counter
     if (r->spp == 0 || r->spp > kMaxSpp || r->max_bounces == 0 || r->max_bounces > kMaxBounces)
         return fail(VDBC_E_INVALID, "need 1 <= spp <= %u and 1 <= max_bounces <= %u", kMaxSpp, kMaxBounces);
+    if (r->tile_w != 0 && r->tile_w != 8 && r->tile_w != 16 && r->tile_w != 32 && r->tile_w != 64)
+        return fail(VDBC_E_INVALID, "tile_w must be 0 (default 8), 8, 16, 32 or 64");
     {
         const double l = std::sqrt((double)med->light_dir[0] * med->light_dir[0] +
                                    (double)med->light_dir[1] * med->light_dir[1] +
@@ -497,7 +499,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     pt_geometry(r->macrocell, v.nx, v.ny, v.nz, &g);
     g.spp = (int)r->spp;
     g.max_bounces = (int)r->max_bounces;
-    g.tw = (r->tile_w == 16 || r->tile_w == 32 || r->tile_w == 64) ? (int)r->tile_w : 8;
+    g.tw = r->tile_w == 0 ? 8 : (int)r->tile_w;
     g.seed_lo = (uint32_t)r->seed;
     g.seed_hi = (uint32_t)(r->seed >> 32);
     g.frame = r->frame;

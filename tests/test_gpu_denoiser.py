@@ -39,6 +39,7 @@ CONV_CASES = [  # (ca, cb, up, stride, cout, n, hs, ws)
     (64, 0, 1, 1, 32, 1, 7, 11),
     (32, 32, 0, 1, 32, 2, 14, 10),
     (32, 0, 0, 1, 3, 1, 17, 19),
+    (32, 0, 0, 1, 40, 1, 12, 15),   # 33..48 output channels take the four-tile kernel
 ]
 
 

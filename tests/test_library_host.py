@@ -31,6 +31,16 @@ def test_exports_every_declared_symbol(lib):
     assert lib.vdbc_abi_version() == 1
 
 
+def test_library_records_its_sources_and_stale_builds_are_refused(lib, monkeypatch):
+    # the loaded library was built from the sources in the tree ...
+    assert _build.built_hash() == _build.source_hash()
+    assert len(_build.source_hash()) == 16
+    # ... and a library built from other sources is refused, not loaded
+    monkeypatch.setattr(_build, "source_hash", lambda: "0" * 16)
+    with pytest.raises(_build.StaleLibrary):
+        _build.ensure_built()
+
+
 def _rand(shape, seed, zero=0.6):
     rng = np.random.default_rng(seed)
     v = rng.random(shape, dtype=np.float32)
@@ -253,7 +263,8 @@ def test_path_tracer_limits_rejected_before_launch(lib):
     cam = vdbc.camera_c(dict(kind=0, width=4, height=4, dir=(0, 0, 1)))
     med = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)], light_dir=(0, 0, 1)))
     ws = C.c_uint64(0)
-    for bad in (dict(spp=0), dict(spp=65537), dict(max_bounces=0), dict(max_bounces=65536)):
+    for bad in (dict(spp=0), dict(spp=65537), dict(max_bounces=0), dict(max_bounces=65536),
+                dict(tile_w=4), dict(tile_w=12), dict(tile_w=128)):
         prm = vdbc.params_c(dict(dict(spp=1), **bad), vdbc.MODE_PT)
         assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
         assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(prm), 4096, None,

@@ -103,6 +103,8 @@ def lib():
         P = C.c_void_p
         u32, u64, f32 = C.c_uint32, C.c_uint64, C.c_float
         L.ref_philox4x32_10.argtypes = [P, P, P]
+        L.ref_philox_many.argtypes = [P, P, u64, P]
+        L.ref_philox_many.restype = None
         L.ref_u01.argtypes = [u32]
         L.ref_u01.restype = C.c_double
         L.ref_background.argtypes = [P, u64]
@@ -161,6 +163,17 @@ def philox(ctr, key) -> np.ndarray:
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, dtype=np.uint32)
     lib().ref_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def philox_many(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of n counters (n x 4) under n keys (n x 2)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    if len(c) != len(k):
+        raise ValueError("one key per counter")
+    out = np.zeros_like(c)
+    lib().ref_philox_many(_ptr(c), _ptr(k), len(c), _ptr(out))
     return out
 
 

@@ -43,6 +43,7 @@ typedef struct {
 
 /* ---- Philox4x32-10 (Salmon et al., SC'11), the counter-based RNG ---- */
 void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void ref_philox_many(const uint32_t* ctr, const uint32_t* key, uint64_t n, uint32_t* out);
 double ref_u01(uint32_t x);
 
 /* ---- Alg. 1 "Compress", steps in the paper's order ---- */

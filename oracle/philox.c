@@ -36,5 +36,11 @@ void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[3] = c[3];
 }
 
+/* The generator applied to n (counter, key) pairs, one after another. */
+void ref_philox_many(const uint32_t* ctr, const uint32_t* key, uint64_t n, uint32_t* out)
+{
+    for (uint64_t i = 0; i < n; ++i) ref_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+}
+
 /* 24 high bits -> [0, 1) with spacing 2^-24. */
 double ref_u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }

@@ -72,6 +72,20 @@ def pt_medium(sigma_scale: float = 64.0, albedo: float = 0.9) -> dict:
                 ambient=(0.06, 0.07, 0.10))
 
 
+# Five coloured control points over densities [0.1, 0.9] with alpha
+# 0, 0.8, 0.3, 1, 0.5: every interval of the transfer function has its own
+# colour and slope, so a wrong interval, channel or colour shows.
+TF5 = [(0.2, 0.3, 0.9, 0.0), (0.9, 0.1, 0.2, 0.8), (0.4, 0.4, 0.4, 0.3),
+       (1.0, 1.0, 0.0, 1.0), (0.0, 1.0, 1.0, 0.5)]
+TF5_RANGE = (0.1, 0.9)
+
+
+def pt_medium_tf5(sigma_scale: float = 64.0, albedo: float = 0.9) -> dict:
+    """The scattering medium of pt_medium() with the coloured five-point
+    transfer function TF5 (alpha = extinction, RGB = scattering colour)."""
+    return dict(pt_medium(sigma_scale, albedo), tf=list(TF5), tf_range=TF5_RANGE)
+
+
 TINY = dict(name="tiny-64^3-ea-128x128", rate=0.25, width=128, height=128, step=0.5)
 MID = dict(name="mid-512^3-pt-1024x1024x16spp", rates=(0.25, 0.10, 0.05), width=1024,
            height=1024, spp=16, max_bounces=8, seed=0x5EED)

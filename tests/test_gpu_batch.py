@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import synth
 from paper_2504_04564_amd import _build, autotune, vdbc
 from synth import scenes
@@ -30,8 +31,15 @@ def _items(count=10, seed=3):
         w, h = 40 + 8 * (i % 4), 36 + 5 * (i % 3)
         items.append(dict(grid=g, camera=scenes.orbit_camera(g.dims, w, h, azimuth_deg=20 * i),
                           medium=scenes.pt_medium(48.0), spp=min(spp, 4), max_bounces=6,
-                          seed=0x1234 + i, frame=i))
+                          seed=0x1234 + i, frame=i, host=buf))
     return items
+
+
+def _coloured_tf(i):
+    # the five-point transfer function with its colour channels rotated by i
+    # and its alpha scaled: every volume of the batch has its own colours
+    sc = 1.0 - 0.1 * (i % 4)
+    return [(c[i % 3], c[(i + 1) % 3], c[(i + 2) % 3], a * sc) for *c, a in scenes.TF5]
 
 
 def _single(it, macrocell, tile_w=8):
@@ -55,6 +63,28 @@ def test_batch_equals_single_launches(tuning):
     torch.cuda.synchronize()
     for img, r in zip(b.images, ref):
         assert _same(img, r)
+    b.close()
+
+
+def test_batch_images_match_oracle_with_coloured_tfs():
+    # the persistent batched launch against the oracle, volume by volume:
+    # uneven sizes, rates, images and spp, a different coloured transfer
+    # function, extinction and frame per volume
+    items = _items(6, seed=13)
+    for i, it in enumerate(items):
+        it["medium"] = dict(scenes.pt_medium_tf5(32.0 + 8.0 * i), tf=_coloured_tf(i))
+    C = 16
+    b = vdbc.Batch(items, dict(macrocell=C, tile_w=8, blocks_per_cu=4, persistent=1))
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (it, img) in enumerate(zip(items, b.images)):
+        prm = dict(spp=it["spp"], max_bounces=it["max_bounces"], seed=it["seed"], frame=it["frame"],
+                   macrocell=C)
+        want = oracle.render_pt(oracle.VdbField(it["host"]), it["camera"], it["medium"], prm)
+        got = img.cpu().numpy().reshape(-1, 4).astype(np.float64)
+        rel = float(np.mean((got - want) ** 2 / (want * want + 0.01)))
+        assert rel <= 1e-4, (i, rel)
+        assert np.count_nonzero(want[:, 3] > 0) >= 16, i
     b.close()
 
 

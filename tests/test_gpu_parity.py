@@ -59,6 +59,18 @@ def test_philox_bit_exact():
         assert np.array_equal(got[i], oracle.philox(ctr[i], key[i])), i
 
 
+def test_philox_bit_exact_1e8_counters():
+    # 12 chunks of 2^23 seeded (counter, key) pairs: 100,663,296 counters
+    n = 1 << 23
+    for c in range(12):
+        rng = np.random.default_rng([11, c])
+        ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint32)
+        key = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint32)
+        got = vdbc.philox(_cuda(ctr.view(np.int32)), _cuda(key.view(np.int32)))
+        got = got.cpu().numpy().view(np.uint32).reshape(-1, 4)
+        assert np.array_equal(got, oracle.philox_many(ctr, key)), c
+
+
 # ---------------------------------------------------------------- lookups
 
 LOOKUP_CASES = [((64, 64, 64), 0.25, 2, 0), ((37, 50, 70), 0.3, 1, 0),
@@ -292,7 +304,7 @@ def _pt_scene(n, w, h, spp, seed=0x5EED, bounces=8):
     return cam, med, prm
 
 
-@pytest.mark.parametrize("q", [0.25, 0.10])
+@pytest.mark.parametrize("q", [0.25, 0.10, 0.05])
 def test_pt_small_relmse(q):
     v = synth.mid_volume(n=96)
     buf, st = vdbc.encode(v, q)
@@ -305,6 +317,65 @@ def test_pt_small_relmse(q):
     want_d = oracle.render_pt(oracle.DenseField(v, 0.0), cam, med, prm)
     got_d = vdbc.render(_dense_t(v), cam, med, prm, vdbc.MODE_PT, background=0.0)
     assert relmse(got_d.cpu().numpy().reshape(-1, 4), want_d) <= 1e-4
+
+
+@pytest.mark.parametrize("q,C", [(0.25, 8), (0.10, 8), (0.05, 8), (0.10, 16)])
+def test_pt_coloured_five_point_tf_vs_oracle(q, C):
+    # the coloured five-point transfer function: alpha interval search in the
+    # LDS copy of the control points, throughput weighted by the interpolated
+    # colour per channel; 1:4, 1:10 and 1:20
+    v = synth.mid_volume(n=96)
+    buf, _ = vdbc.encode(v, q)
+    cam = scenes.orbit_camera((96, 96, 96), 52, 44)
+    med = scenes.pt_medium_tf5(64.0)
+    prm = dict(spp=4, max_bounces=8, seed=0x5EED, macrocell=C)
+    want, want_aov = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, aov=True)
+    img, aov = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT, aov=True)
+    got = img.cpu().numpy().reshape(-1, 4)
+    assert relmse(got, want) <= 1e-4
+    assert relmse(aov.cpu().numpy().reshape(-1, 2), want_aov) <= 1e-4
+    # the image is coloured: red and blue differ by much more than the noise
+    assert np.abs(want[:, 0] - want[:, 2]).max() > 0.05
+    want_d = oracle.render_pt(oracle.DenseField(v, 0.0), cam, med, prm)
+    got_d = vdbc.render(_dense_t(v), cam, med, prm, vdbc.MODE_PT, background=0.0)
+    assert relmse(got_d.cpu().numpy().reshape(-1, 4), want_d) <= 1e-4
+
+
+def test_pt_mid_config_coloured_1to20_sampled_pixels():
+    # the mid configuration at 1:20 (512^3, 1024x1024, 16 spp, 8 bounces) with
+    # the coloured five-point transfer function, on sampled pixels
+    v = synth.mid_volume()
+    buf, _ = vdbc.encode(v, 0.05)
+    M = scenes.MID
+    cam = scenes.orbit_camera((512, 512, 512), M["width"], M["height"])
+    med = scenes.pt_medium_tf5(64.0)
+    prm = dict(spp=M["spp"], max_bounces=M["max_bounces"], seed=M["seed"], macrocell=16)
+    img = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
+    rng = np.random.default_rng(54)
+    pix = np.sort(rng.choice(M["width"] * M["height"], 192, replace=False)).astype(np.uint32)
+    want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, pixels=pix)
+    assert relmse(img[pix], want) <= 1e-4
+    assert np.all(np.isfinite(img)) and np.count_nonzero(want[:, 3] > 0) >= 32
+
+
+@pytest.mark.parametrize("kind", ["vdb", "dense"])
+def test_pt_pinhole_camera_rays_see_their_texels(kind):
+    # the pinhole camera's ray directions through the image-based light:
+    # every pixel whose whole footprint (and a 10 % margin) sees one texel of
+    # the map returns exactly that texel (texels from the camera definition
+    # in float64 on the host)
+    from tests.test_oracle_render import pinhole_texel_cases
+    n, env, cam, want = pinhole_texel_cases()
+    z = np.zeros((n, n, n), np.float32)
+    med = dict(scenes.pt_medium(16.0), env=_cuda(env))
+    prm = dict(spp=5, max_bounces=2, seed=2)
+    if kind == "vdb":
+        img = vdbc.render(vdbc.Grid(vdbc.encode(z, 0.5)[0]), cam, med, prm, vdbc.MODE_PT)
+    else:
+        img = vdbc.render(_dense_t(z), cam, med, prm, vdbc.MODE_PT, background=0.0)
+    ok = want >= 0
+    got = img.cpu().numpy()[..., :3]
+    assert np.array_equal(got[ok], env.reshape(-1, 3)[want[ok]])
 
 
 def test_pt_lossless_vdb_equals_dense_bitwise_and_deterministic():

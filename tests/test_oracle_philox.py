@@ -48,3 +48,20 @@ def test_uniformity_chi_square():
     assert chi2 < 37.7
     r = np.corrcoef(u[:-1], u[1:])[0, 1]
     assert abs(r) < 4.0 / np.sqrt(len(u))
+
+
+def test_many_is_the_generator_applied_per_pair():
+    # the batched entry point applies the generator to pair i alone: the
+    # known-answer vectors at shuffled positions among other pairs
+    rows = _kat()
+    rng = np.random.default_rng(3)
+    ctr = rng.integers(0, 2 ** 32, size=(11, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(11, 2), dtype=np.uint64).astype(np.uint32)
+    at = [7, 0, 10]
+    for (c, k, _), i in zip(rows, at):
+        ctr[i], key[i] = c, k
+    got = oracle.philox_many(ctr, key)
+    for (_, _, want), i in zip(rows, at):
+        assert [int(x) for x in got[i]] == want
+    for i in range(11):
+        assert np.array_equal(got[i], oracle.philox(ctr[i], key[i]))

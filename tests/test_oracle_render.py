@@ -270,6 +270,59 @@ def test_pt_single_scatter_closed_form():
     assert abs(rgba[:, 1].mean() - k * p) < 4 * se
 
 
+def _single_scatter_channels(med, s0, n, spp, seed):
+    """Oracle image of a homogeneous cube of value s0 lit from the camera
+    side with one scattering event, and the per-channel closed form
+    E[L_ch] = albedo * c_ch(s0) * E_ch / (4 pi) * (1 - exp(-2 sigma d)) / 2,
+    sigma d = sigma_scale * alpha(s0); colour and alpha by np.interp."""
+    f = _homog(n, s0)
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    rgba = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=1, seed=seed))
+    sd = float(np.float32(med["sigma_scale"])) * _alpha(med, float(np.float32(s0)))
+    p = (1 - math.exp(-2 * sd)) / 2
+    k = (float(np.float32(med["albedo"])) * _rgb(med, float(np.float32(s0))) *
+         _f32(med["light_E"]) / (4 * math.pi))
+    return rgba, k, p
+
+
+def test_pt_single_scatter_coloured_closed_form():
+    # a constant TF colour c and a coloured light: channel ch carries
+    # albedo * c_ch * E_ch of the same single-scatter indicator, so the three
+    # channels of every pixel are that indicator times their own constant and
+    # their means follow the per-channel closed form (a swapped or dropped
+    # colour channel, or alpha used as colour, fails)
+    c = (0.9, 0.5, 0.2)
+    med = dict(sigma_scale=12.0, albedo=0.8, tf=[c + (0.0,), c + (1.0,)],
+               light_dir=(0, 0, -1), light_E=(2.0, 1.0, 3.0), ambient=(0, 0, 0))
+    n, spp = 16, 64
+    rgba, k, p = _single_scatter_channels(med, 1.0, n, spp, 6)
+    ind = rgba[:, 0] / k[0]
+    for ch in range(3):
+        np.testing.assert_allclose(rgba[:, ch] / k[ch], ind, rtol=1e-12, atol=1e-15)
+        se = k[ch] * math.sqrt(p * (1 - p) / (256 * spp))
+        assert abs(rgba[:, ch].mean() - k[ch] * p) < 4 * se, ch
+    assert np.all(rgba[:, :3] >= 0) and ind.max() > 0.5
+
+
+@pytest.mark.parametrize("s0", [0.15, 0.45, 0.62, 0.85])
+def test_pt_single_scatter_five_point_tf_at_density(s0):
+    # TF5: five coloured control points with alpha 0, .8, .3, 1, .5 over
+    # [0.1, 0.9]; a homogeneous cube of value s0 in each interval: extinction
+    # from the interpolated alpha, throughput from the interpolated colour
+    med = dict(TF5, sigma_scale=12.0, albedo=0.9, light_dir=(0, 0, -1),
+               light_E=(1.5, 2.5, 1.0), ambient=(0, 0, 0))
+    n, spp = 16, 64
+    rgba, k, p = _single_scatter_channels(med, s0, n, spp, 60 + int(100 * s0))
+    ind = rgba[:, 1] / k[1]
+    for ch in range(3):
+        if k[ch] == 0.0:
+            assert np.all(rgba[:, ch] == 0.0)
+            continue
+        np.testing.assert_allclose(rgba[:, ch] / k[ch], ind, rtol=1e-12, atol=1e-15)
+        se = k[ch] * math.sqrt(p * (1 - p) / (256 * spp))
+        assert abs(rgba[:, ch].mean() - k[ch] * p) < 4 * se, (ch, rgba[:, ch].mean(), k[ch] * p)
+
+
 def _numpy_homog_pt(n, sigma, albedo, E, ldir, amb, bounces, N, seed):
     """Independent analytic estimator for a homogeneous cube: exponential
     free flights, exact shadow transmittance, isotropic scattering."""
@@ -329,6 +382,90 @@ def test_pt_multiple_scattering_matches_analytic_estimator():
     # multiple scattering matters at this albedo: single scattering differs
     S = _numpy_homog_pt(n, sigma_scale / n, albedo, E, ld32, amb, 1, 400_000, 9)
     assert abs(S.mean() - Ln.mean()) > 10 * se
+
+
+def test_pt_multiple_scattering_coloured_matches_analytic_estimator():
+    # a constant TF colour scales each channel's throughput by albedo * c_ch
+    # at every real collision: channel ch must match the analytic estimator
+    # run with albedo * c_ch, E_ch and ambient_ch
+    n, sigma_scale, albedo, bounces = 16, 32.0, 0.9, 8
+    c = np.array([1.0, 0.7, 0.35])
+    E = np.array([3.0, 2.0, 4.0])
+    amb = np.array([0.1, 0.3, 0.05])
+    ldir = np.array([-0.4, 0.8, 0.45])
+    ldir /= np.linalg.norm(ldir)
+    f = _homog(n)
+    med = dict(sigma_scale=sigma_scale, albedo=albedo, tf=[tuple(c) + (0.0,), tuple(c) + (1.0,)],
+               light_dir=tuple(ldir), light_E=tuple(E), ambient=tuple(amb))
+    cam = scenes.ortho_z_camera(n, n, 16, 16)
+    spp = 256
+    L1 = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=bounces, seed=17))[:, :3]
+    L2 = oracle.render_pt(f, cam, med, dict(spp=spp, max_bounces=bounces, seed=18))[:, :3]
+    ld32 = np.asarray(ldir, np.float32).astype(np.float64)
+    c32, E32, a32 = _f32(c), _f32(E), _f32(amb)
+    means = []
+    for ch in range(3):
+        Lo = 0.5 * (L1[:, ch] + L2[:, ch])
+        se_o = math.sqrt(np.var(L1[:, ch] - L2[:, ch]) / 4 / len(Lo))
+        Ln = _numpy_homog_pt(n, sigma_scale / n, float(np.float32(albedo)) * c32[ch], E32[ch], ld32,
+                             a32[ch], bounces, 400_000, 30 + ch)
+        se = math.sqrt(se_o ** 2 + Ln.var() / len(Ln))
+        assert abs(Lo.mean() - Ln.mean()) < 4 * se, (ch, Lo.mean(), Ln.mean(), se)
+        means.append(Ln.mean())
+    # the channels differ by far more than the noise: the colour matters
+    assert abs(means[0] - means[2]) > 0.05
+
+
+def _texel_of(d, w, h):
+    u = (np.arctan2(d[..., 2], d[..., 0]) + math.pi) / (2 * math.pi)
+    v = np.arccos(np.clip(d[..., 1], -1, 1)) / math.pi
+    return (np.clip(np.floor(v * h), 0, h - 1).astype(int),
+            np.clip(np.floor(u * w), 0, w - 1).astype(int))
+
+
+def pinhole_texel_cases():
+    """A pinhole camera looking through an empty volume at a lat-long map
+    with distinguishable texels, and for every pixel the texel its rays see
+    (or -1 where the pixel's footprint straddles two texels): directions of
+    17 x 17 points spanning each pixel square widened by 10 % on every side,
+    from the camera's definition (lower_left + x du + y dv, normalised), in
+    float64."""
+    n = 8
+    w, h = 32, 16
+    env = np.zeros((h, w, 3), np.float32)
+    for y in range(h):
+        for x in range(w):
+            env[y, x] = (x, y, 100 + x + w * y)
+    # off-centre, non-square, tilted view so that a du/dv swap or a missing
+    # normalisation moves pixels to other texels
+    cam = scenes.pinhole_camera((3.5, 2.0, -30.0), (9.0, 8.5, 3.5), (0.2, 1.0, 0.1), 60.0, 40, 26)
+    ll, du, dv = (np.asarray(cam[k], np.float32).astype(np.float64) for k in ("lower_left", "du", "dv"))
+    sub = np.linspace(-0.1, 1.1, 17)   # the pixel square and a 10 % margin
+    want = np.full((cam["height"], cam["width"]), -1, np.int64)
+    for py in range(cam["height"]):
+        for px in range(cam["width"]):
+            x = px + sub[:, None]
+            y = py + sub[None, :]
+            d = ll + x[..., None] * du + y[..., None] * dv
+            d /= np.linalg.norm(d, axis=-1, keepdims=True)
+            ty, tx = _texel_of(d, w, h)
+            if np.all(ty == ty.flat[0]) and np.all(tx == tx.flat[0]):
+                want[py, px] = ty.flat[0] * w + tx.flat[0]
+    return n, env, cam, want
+
+
+def test_pt_pinhole_camera_rays_see_their_texels():
+    # the pinhole camera's ray directions, pinned through the image-based
+    # light: every escaping camera ray returns the texel of its own direction
+    n, env, cam, want = pinhole_texel_cases()
+    f = oracle.DenseField(np.zeros((n, n, n), np.float32), 0.0)
+    med = dict(scenes.pt_medium(16.0), env=env)
+    rgba = oracle.render_pt(f, cam, med, dict(spp=5, max_bounces=2, seed=2))
+    ok = want >= 0
+    assert ok.sum() >= 0.4 * ok.size and len(np.unique(want[ok])) >= 8
+    flat = env.reshape(-1, 3).astype(np.float64)
+    got = rgba[:, :3].reshape(cam["height"], cam["width"], 3)
+    assert np.array_equal(got[ok], flat[want[ok]])
 
 
 def test_pt_deterministic_per_pixel():

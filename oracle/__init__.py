@@ -128,6 +128,9 @@ def lib():
         L.ref_sample_many.argtypes = [C.POINTER(Field), P, u64, u32, P]
         L.ref_sample_many.restype = None
         L.ref_majorant.argtypes = [C.POINTER(Field), C.POINTER(Medium), u32, P]
+        L.ref_majorant_cells.argtypes = [C.POINTER(Field), C.POINTER(Medium), u32, u64, u64, P]
+        L.ref_render_pt_majorant.argtypes = [C.POINTER(Field), C.POINTER(Camera), C.POINTER(Medium),
+                                             C.POINTER(Params), P, P, u64, P, P]
         L.ref_render_ea.argtypes = [C.POINTER(Field), C.POINTER(Camera), C.POINTER(Medium),
                                     C.POINTER(Params), P]
         L.ref_render_pt.argtypes = [C.POINTER(Field), C.POINTER(Camera), C.POINTER(Medium),
@@ -331,12 +334,35 @@ def make_params(p: dict) -> Params:
     return r
 
 
-def majorant(fld, medium: dict, C_: int = 8) -> np.ndarray:
+def majorant(fld, medium: dict, C_: int = 8, cells=None, out=None) -> np.ndarray:
+    """Majorant grid (nz/C, ny/C, nx/C); with cells=(begin, end) only the
+    cells of that flat-index range are computed (into `out` if given)."""
+    f = fld.f
+    g = [(-(-n // C_)) for n in (f.nz, f.ny, f.nx)]
+    if out is None:
+        out = np.zeros(g, np.float64)
+    assert out.shape == tuple(g) and out.dtype == np.float64 and out.flags.c_contiguous
+    m = make_medium(medium)
+    if cells is None:
+        _check(lib().ref_majorant(C.byref(f), C.byref(m), C_, _ptr(out)), "ref_majorant")
+    else:
+        _check(lib().ref_majorant_cells(C.byref(f), C.byref(m), C_, int(cells[0]), int(cells[1]),
+                                        _ptr(out)), "ref_majorant_cells")
+    return out
+
+
+def majorant_threads(fld, medium: dict, C_: int, threads: int) -> np.ndarray:
+    """The same majorant grid computed by `threads` concurrent calls of the
+    single-threaded oracle on disjoint cell ranges (ctypes releases the GIL
+    during each call)."""
+    from concurrent.futures import ThreadPoolExecutor
     f = fld.f
     g = [(-(-n // C_)) for n in (f.nz, f.ny, f.nx)]
     out = np.zeros(g, np.float64)
-    m = make_medium(medium)
-    _check(lib().ref_majorant(C.byref(f), C.byref(m), C_, _ptr(out)), "ref_majorant")
+    n = out.size
+    cuts = np.linspace(0, n, 8 * threads + 1).astype(np.int64)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda i: majorant(fld, medium, C_, (cuts[i], cuts[i + 1]), out), range(len(cuts) - 1)))
     return out
 
 
@@ -359,17 +385,29 @@ def render_iso(fld, camera: dict, iso: float, step: float, refine: int = 12, aux
     return (img, ax) if aux else img
 
 
-def render_pt(fld, camera: dict, medium: dict, params: dict, pixels=None, aov=False):
-    """Path-traced RGBA for `pixels` (flat indices py*W+px; default all)."""
+def render_pt(fld, camera: dict, medium: dict, params: dict, pixels=None, aov=False, majorant=None):
+    """Path-traced RGBA for `pixels` (flat indices py*W+px; default all);
+    `majorant`: a grid from majorant() at params' macrocell, used instead of
+    building one."""
     c, m, r = make_camera(camera), make_medium(medium), make_params(params)
     if pixels is None:
         pixels = np.arange(c.width * c.height, dtype=np.uint32)
     pix = np.ascontiguousarray(pixels, dtype=np.uint32)
     rgba = np.zeros((len(pix), 4), np.float64)
     a = np.zeros((len(pix), 2), np.float64) if aov else None
-    _check(lib().ref_render_pt(C.byref(fld.f), C.byref(c), C.byref(m), C.byref(r), _ptr(pix),
-                               len(pix), _ptr(rgba), _ptr(a) if aov else None),
-           "ref_render_pt")
+    if majorant is None:
+        _check(lib().ref_render_pt(C.byref(fld.f), C.byref(c), C.byref(m), C.byref(r), _ptr(pix),
+                                   len(pix), _ptr(rgba), _ptr(a) if aov else None),
+               "ref_render_pt")
+    else:
+        f = fld.f
+        g = tuple(-(-n // r.macrocell) for n in (f.nz, f.ny, f.nx))
+        mj = np.ascontiguousarray(majorant, dtype=np.float64)
+        if mj.shape != g:
+            raise ValueError(f"majorant grid {mj.shape} does not match macrocell {r.macrocell}: {g}")
+        _check(lib().ref_render_pt_majorant(C.byref(fld.f), C.byref(c), C.byref(m), C.byref(r),
+                                            _ptr(mj), _ptr(pix), len(pix), _ptr(rgba),
+                                            _ptr(a) if aov else None), "ref_render_pt_majorant")
     return (rgba, a) if aov else rgba
 
 

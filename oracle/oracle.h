@@ -127,6 +127,10 @@ typedef struct {
 /* Majorant grid (Section 4, macrocells): per cell the extinction max over the
  * one-voxel-dilated footprint.  Grid ceil(n/C) per axis, x-fastest. */
 int ref_majorant(const ref_field* f, const ref_medium* m, uint32_t C, double* maj);
+/* The majorant of the cells with flat index (x-fastest) in [begin, end)
+ * only; ref_majorant is [0, cells). */
+int ref_majorant_cells(const ref_field* f, const ref_medium* m, uint32_t C, uint64_t begin,
+                       uint64_t end, double* maj);
 /* Emission-absorption ray marching; image RGBA double [h][w][4]. */
 int ref_render_ea(const ref_field* f, const ref_camera* c, const ref_medium* m,
                   const ref_render_params* r, double* image);
@@ -136,6 +140,11 @@ int ref_render_ea(const ref_field* f, const ref_camera* c, const ref_medium* m,
 int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                   const ref_render_params* r, const uint32_t* pixels,
                   uint64_t n_pixels, double* rgba, double* aov);
+/* ref_render_pt over a majorant grid the caller computed with ref_majorant
+ * (or ref_majorant_cells over every cell) at r->macrocell. */
+int ref_render_pt_majorant(const ref_field* f, const ref_camera* c, const ref_medium* m,
+                           const ref_render_params* r, const double* maj, const uint32_t* pixels,
+                           uint64_t n_pixels, double* rgba, double* aov);
 /* Implicit iso-surface ray marcher (the interval-based marcher of Section
  * 5.4, reading R22): one ray per pixel centre, field samples at
  * t0 + (k + 1/2) step; the first interval between consecutive samples whose

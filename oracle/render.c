@@ -168,25 +168,33 @@ static double alpha_max(const ref_medium* m, double a, double b)
     return best;
 }
 
-int ref_majorant(const ref_field* f, const ref_medium* m, uint32_t C, double* maj)
+int ref_majorant_cells(const ref_field* f, const ref_medium* m, uint32_t C, uint64_t begin,
+                       uint64_t end, double* maj)
 {
     if (C == 0 || m->tf_n < 2 || m->tf_n > 64) return REF_E_INVALID;
-    uint32_t gx = (f->nx + C - 1) / C, gy = (f->ny + C - 1) / C, gz = (f->nz + C - 1) / C;
+    uint64_t gx = (f->nx + C - 1) / C, gy = (f->ny + C - 1) / C, gz = (f->nz + C - 1) / C;
+    if (begin > end || end > gx * gy * gz) return REF_E_INVALID;
     double ds = density_scale(f, m);
-    for (uint32_t cz = 0; cz < gz; ++cz)
-        for (uint32_t cy = 0; cy < gy; ++cy)
-            for (uint32_t cx = 0; cx < gx; ++cx) {
-                double vmin = INFINITY, vmax = -INFINITY;
-                for (int64_t k = (int64_t)C * cz - 1; k <= (int64_t)C * cz + C; ++k)
-                    for (int64_t j = (int64_t)C * cy - 1; j <= (int64_t)C * cy + C; ++j)
-                        for (int64_t i = (int64_t)C * cx - 1; i <= (int64_t)C * cx + C; ++i) {
-                            double v = (double)ref_lookup(f, i, j, k);
-                            if (v < vmin) vmin = v;
-                            if (v > vmax) vmax = v;
-                        }
-                maj[cx + (uint64_t)gx * (cy + (uint64_t)gy * cz)] = ds * alpha_max(m, vmin, vmax);
-            }
+    for (uint64_t cell = begin; cell < end; ++cell) {
+        int64_t cx = (int64_t)(cell % gx), cy = (int64_t)((cell / gx) % gy), cz = (int64_t)(cell / (gx * gy));
+        double vmin = INFINITY, vmax = -INFINITY;
+        for (int64_t k = (int64_t)C * cz - 1; k <= (int64_t)C * cz + C; ++k)
+            for (int64_t j = (int64_t)C * cy - 1; j <= (int64_t)C * cy + C; ++j)
+                for (int64_t i = (int64_t)C * cx - 1; i <= (int64_t)C * cx + C; ++i) {
+                    double v = (double)ref_lookup(f, i, j, k);
+                    if (v < vmin) vmin = v;
+                    if (v > vmax) vmax = v;
+                }
+        maj[cell] = ds * alpha_max(m, vmin, vmax);
+    }
     return REF_OK;
+}
+
+int ref_majorant(const ref_field* f, const ref_medium* m, uint32_t C, double* maj)
+{
+    if (C == 0) return REF_E_INVALID;
+    uint64_t cells = (uint64_t)((f->nx + C - 1) / C) * ((f->ny + C - 1) / C) * ((f->nz + C - 1) / C);
+    return ref_majorant_cells(f, m, C, 0, cells, maj);
 }
 
 /* --------------------------- emission-absorption --------------------------- */
@@ -376,16 +384,21 @@ static int free_flight(const tracker* tk, const double o[3], const double d[3], 
     }
 }
 
-static int make_tracker(tracker* tk, const ref_field* f, const ref_medium* m, uint32_t C,
-                        double** maj_out)
+static void tracker_grid(tracker* tk, const ref_field* f, const ref_medium* m, uint32_t C)
 {
-    if (C == 0) return REF_E_INVALID;
     tk->f = f;
     tk->m = m;
     tk->C = C;
     tk->g[0] = (f->nx + C - 1) / C;
     tk->g[1] = (f->ny + C - 1) / C;
     tk->g[2] = (f->nz + C - 1) / C;
+}
+
+static int make_tracker(tracker* tk, const ref_field* f, const ref_medium* m, uint32_t C,
+                        double** maj_out)
+{
+    if (C == 0) return REF_E_INVALID;
+    tracker_grid(tk, f, m, C);
     double* maj = (double*)malloc(sizeof(double) * tk->g[0] * tk->g[1] * tk->g[2]);
     if (!maj) return REF_E_NOMEM;
     int rc = ref_majorant(f, m, C, maj);
@@ -441,6 +454,10 @@ static void escape_radiance(const ref_medium* m, const double d[3], double out[3
     for (int ch = 0; ch < 3; ++ch) out[ch] = (double)p[ch];
 }
 
+static int render_pt(const tracker* tkp, const ref_camera* c, const ref_medium* m,
+                     const ref_render_params* r, const uint32_t* pixels, uint64_t n_pixels,
+                     double* rgba, double* aov);
+
 int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
                   const ref_render_params* r, const uint32_t* pixels, uint64_t n_pixels,
                   double* rgba, double* aov)
@@ -450,6 +467,29 @@ int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
     double* maj = NULL;
     int rc = make_tracker(&tk, f, m, r->macrocell, &maj);
     if (rc) return rc;
+    rc = render_pt(&tk, c, m, r, pixels, n_pixels, rgba, aov);
+    free(maj);
+    return rc;
+}
+
+int ref_render_pt_majorant(const ref_field* f, const ref_camera* c, const ref_medium* m,
+                           const ref_render_params* r, const double* maj, const uint32_t* pixels,
+                           uint64_t n_pixels, double* rgba, double* aov)
+{
+    if (r->spp == 0 || r->max_bounces == 0 || m->tf_n < 2 || m->tf_n > 64 || r->macrocell == 0 || !maj)
+        return REF_E_INVALID;
+    tracker tk;
+    tracker_grid(&tk, f, m, r->macrocell);
+    tk.maj = maj;
+    return render_pt(&tk, c, m, r, pixels, n_pixels, rgba, aov);
+}
+
+static int render_pt(const tracker* tkp, const ref_camera* c, const ref_medium* m,
+                     const ref_render_params* r, const uint32_t* pixels, uint64_t n_pixels,
+                     double* rgba, double* aov)
+{
+    const tracker tk = *tkp;
+    const ref_field* f = tk.f;
     const double inv4pi = 1.0 / (4.0 * PI_D);
     double ld[3] = {m->light_dir[0], m->light_dir[1], m->light_dir[2]};
     for (uint64_t q = 0; q < n_pixels; ++q) {
@@ -526,6 +566,5 @@ int ref_render_pt(const ref_field* f, const ref_camera* c, const ref_medium* m,
             aov[2 * q + 1] = trans * inv;
         }
     }
-    free(maj);
     return REF_OK;
 }

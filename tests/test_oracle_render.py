@@ -68,6 +68,22 @@ def test_majorant_bruteforce(C):
                 assert maj[cz, cy, cx] == pytest.approx(ds * _alpha(med, s).max(), abs=1e-15)
 
 
+def test_majorant_cell_ranges_and_threads_assemble_the_grid():
+    # the cell-range entry point computes each cell by the same definition:
+    # ragged ranges and the threaded split reassemble the whole grid bitwise
+    v = _vol((21, 30, 37), 8, zero=0.4)
+    buf, _ = oracle.encode(v, 0.5)
+    f = oracle.VdbField(buf)
+    med = dict(sigma_scale=20.0, tf=[(0, 0, 0, 0.1), (1, 1, 1, 0.9), (1, 1, 1, 0.4)])
+    full = oracle.majorant(f, med, 4)
+    part = np.full_like(full, -1.0)
+    cuts = [0, 1, 17, 200, 201, full.size]
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        oracle.majorant(f, med, 4, cells=(a, b), out=part)
+    assert np.array_equal(part.view(np.uint64), full.view(np.uint64))
+    assert np.array_equal(oracle.majorant_threads(f, med, 4, 3).view(np.uint64), full.view(np.uint64))
+
+
 def test_majorant_bounds_every_sample():
     v = _vol((40, 33, 27), 2)
     buf, _ = oracle.encode(v, 0.3)
@@ -481,6 +497,23 @@ def test_pt_deterministic_per_pixel():
     full = oracle.render_pt(f, cam, med, prm)
     sub = oracle.render_pt(f, cam, med, prm, pixels=np.array([119, 5, 60], np.uint32))
     assert np.array_equal(sub, full[[119, 5, 60]])
+
+
+def test_pt_with_a_given_majorant_equals_the_built_one():
+    # the entry point that takes a precomputed majorant walks the same grid
+    n = 16
+    v = _vol((n, n, n), 13, zero=0.4)
+    buf, _ = oracle.encode(v, 0.5)
+    f = oracle.VdbField(buf)
+    med = scenes.pt_medium_tf5(32.0)
+    cam = scenes.orbit_camera((n, n, n), 12, 10)
+    prm = dict(spp=3, max_bounces=5, seed=99, macrocell=4)
+    a, aa = oracle.render_pt(f, cam, med, prm, aov=True)
+    maj = oracle.majorant(f, med, 4)
+    b, ba = oracle.render_pt(f, cam, med, prm, aov=True, majorant=maj)
+    assert np.array_equal(a, b) and np.array_equal(aa, ba)
+    with pytest.raises(ValueError):
+        oracle.render_pt(f, cam, med, dict(prm, macrocell=8), majorant=maj)
 
 
 def test_pt_russian_roulette_is_unbiased():

@@ -117,6 +117,11 @@ def lib():
         L.ref_encode.argtypes = [P, u32, u32, u32, f32, u32, u32, f32,
                                  C.POINTER(C.POINTER(C.c_uint8)), C.POINTER(u64),
                                  C.POINTER(Stats)]
+        L.ref_reconstruct_partial.argtypes = [P, u32, u32, u32, f32, u32, u32, f32, f32, f32, P]
+        L.ref_encode_partial.argtypes = [P, u32, u32, u32, f32, u32, u32, f32, f32, f32,
+                                         C.POINTER(C.POINTER(C.c_uint8)), C.POINTER(u64),
+                                         C.POINTER(Stats)]
+        L.ref_active_mask.argtypes = [P, u32, u32, u32, f32, u32, u32, f32, f32, f32, P]
         L.ref_free.argtypes = [P]
         L.ref_field_vdb.argtypes = [C.POINTER(Field), P, u64]
         L.ref_field_dense.argtypes = [C.POINTER(Field), P, u32, u32, u32, f32]
@@ -223,26 +228,56 @@ def brick_order(dense: np.ndarray, rate: float, metric: int = 2, B: float | None
     return order, int(k.value)
 
 
+PARTIAL = 8   # REF_PARTIAL
+
+
 def reconstruct(dense: np.ndarray, rate: float, metric: int = 2, flags: int = 0,
-                bg: float = 0.0) -> np.ndarray:
+                bg: float = 0.0, partial=None) -> np.ndarray:
+    """Reconstructed grid; `partial` = (fraction, threshold) selects the
+    partial-brick activation (sets REF_PARTIAL)."""
     d = np.ascontiguousarray(dense, dtype=np.float32)
     nx, ny, nz = _dims(d)
     R = np.empty_like(d)
-    _check(lib().ref_reconstruct(_ptr(d), nx, ny, nz, rate, metric, flags, bg, _ptr(R)),
-           "ref_reconstruct")
+    if partial is None:
+        _check(lib().ref_reconstruct(_ptr(d), nx, ny, nz, rate, metric, flags, bg, _ptr(R)),
+               "ref_reconstruct")
+    else:
+        _check(lib().ref_reconstruct_partial(_ptr(d), nx, ny, nz, rate, metric, flags | PARTIAL,
+                                             bg, partial[0], partial[1], _ptr(R)),
+               "ref_reconstruct_partial")
     return R
 
 
+def active_mask(dense: np.ndarray, rate: float, metric: int = 2, flags: int = 0,
+                bg: float = 0.0, partial=None) -> np.ndarray:
+    """Boolean activation mask of the encoder's selection (shape of dense)."""
+    d = np.ascontiguousarray(dense, dtype=np.float32)
+    nx, ny, nz = _dims(d)
+    m = np.zeros(d.shape, np.uint8)
+    pf, pt = (1.0, 0.0) if partial is None else partial
+    fl = flags | (PARTIAL if partial is not None else 0)
+    _check(lib().ref_active_mask(_ptr(d), nx, ny, nz, rate, metric, fl, bg, pf, pt, _ptr(m)),
+           "ref_active_mask")
+    return m.astype(bool)
+
+
 def encode(dense: np.ndarray, rate: float, metric: int = 2, flags: int = 0,
-           bg: float = 0.0):
-    """Canonical buffer (numpy uint8) and encoder statistics (dict)."""
+           bg: float = 0.0, partial=None):
+    """Canonical buffer (numpy uint8) and encoder statistics (dict);
+    `partial` = (fraction, threshold) as in reconstruct()."""
     d = np.ascontiguousarray(dense, dtype=np.float32)
     nx, ny, nz = _dims(d)
     out = C.POINTER(C.c_uint8)()
     nbytes = C.c_uint64(0)
     st = Stats()
-    _check(lib().ref_encode(_ptr(d), nx, ny, nz, rate, metric, flags, bg, C.byref(out),
-                            C.byref(nbytes), C.byref(st)), "ref_encode")
+    if partial is None:
+        rc = lib().ref_encode(_ptr(d), nx, ny, nz, rate, metric, flags, bg, C.byref(out),
+                              C.byref(nbytes), C.byref(st))
+    else:
+        rc = lib().ref_encode_partial(_ptr(d), nx, ny, nz, rate, metric, flags | PARTIAL, bg,
+                                      partial[0], partial[1], C.byref(out), C.byref(nbytes),
+                                      C.byref(st))
+    _check(rc, "ref_encode")
     try:
         buf = np.ctypeslib.as_array(out, shape=(nbytes.value,)).copy()
     finally:

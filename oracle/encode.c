@@ -16,6 +16,17 @@
  *    K = min(N, floor(q*N + 0.5));
  *  - corners: voxels (0,0,0) and (nx-1,ny-1,nz-1) are always active
  *    (Section 3.2.1) unless REF_NO_CORNERS;
+ *  - partial-brick activation (REF_PARTIAL; the variant Section 3.2.1 leaves
+ *    as future work, no rule given there): with fraction p and similarity
+ *    threshold tau, the first F = #{r < K : f_r >= tau} ranked bricks are
+ *    activated whole and the voxels of the bricks ranked K..F-1 under plain
+ *    Alg. 1, R = sum of their in-volume voxel counts, are spent instead along
+ *    the bricks ranked F, F+1, ...: first ceil(p * v_r) voxels of each brick
+ *    (v_r = its in-volume voxels), then, once every brick had its share, the
+ *    rest of each brick in rank order; inside a brick voxels go by |value - B|
+ *    descending (double), ties by linear voxel index ascending.  The first R
+ *    voxels of that sequence are activated.  p = 1 or tau below every
+ *    similarity gives Alg. 1 itself;
  *  - inactive voxels inside a leaf store B; prune at tolerance 0: a leaf whose
  *    512 voxels are all active and bitwise equal becomes a lower-node tile, a
  *    lower node whose 4096 slots are all such tiles of one value becomes an
@@ -154,14 +165,64 @@ int ref_brick_order(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
     return REF_OK;
 }
 
-/* Activation mask: all in-volume voxels of the first K bricks + corners. */
+typedef struct {
+    double d;       /* |value - B| */
+    uint64_t idx;   /* linear voxel index */
+} voxel_key;
+
+static int cmp_voxel(const void* a, const void* b)
+{
+    const voxel_key* x = (const voxel_key*)a;
+    const voxel_key* y = (const voxel_key*)b;
+    if (x->d > y->d) return -1;
+    if (x->d < y->d) return 1;
+    return (x->idx < y->idx) ? -1 : (x->idx > y->idx) ? 1 : 0;
+}
+
+static uint64_t brick_voxels(uint32_t b, uint32_t nbx, uint32_t nby, uint32_t nx, uint32_t ny,
+                             uint32_t nz)
+{
+    uint32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    uint64_t ex = nx - bx * BRICK < BRICK ? nx - bx * BRICK : BRICK;
+    uint64_t ey = ny - by * BRICK < BRICK ? ny - by * BRICK : BRICK;
+    uint64_t ez = nz - bz * BRICK < BRICK ? nz - bz * BRICK : BRICK;
+    return ex * ey * ez;
+}
+
+/* The in-volume voxels of brick b ordered by |value - B| descending, ties by
+ * linear index ascending (the voxel order inside a partially active brick). */
+static voxel_key* brick_voxel_order(const float* dense, uint32_t b, uint32_t nbx, uint32_t nby,
+                                    uint32_t nx, uint32_t ny, uint32_t nz, float B, uint64_t* count)
+{
+    uint32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    uint64_t v = brick_voxels(b, nbx, nby, nx, ny, nz), c = 0;
+    voxel_key* keys = (voxel_key*)malloc(v * sizeof(voxel_key));
+    if (!keys) return NULL;
+    for (uint32_t z = bz * BRICK; z < nz && z < (bz + 1) * BRICK; ++z)
+        for (uint32_t y = by * BRICK; y < ny && y < (by + 1) * BRICK; ++y)
+            for (uint32_t x = bx * BRICK; x < nx && x < (bx + 1) * BRICK; ++x) {
+                uint64_t i = x + (uint64_t)nx * (y + (uint64_t)ny * z);
+                keys[c].d = fabs((double)dense[i] - (double)B);
+                keys[c].idx = i;
+                ++c;
+            }
+    qsort(keys, c, sizeof(voxel_key), cmp_voxel);
+    *count = c;
+    return keys;
+}
+
+/* Activation mask: all in-volume voxels of the first K bricks + corners, or
+ * with REF_PARTIAL the partial-brick rule described at the top of the file. */
 static int activation(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
                       float rate, uint32_t metric, uint32_t flags, float bg,
+                      float pfrac, float ptau,
                       uint8_t** active_out, float* B_out, uint64_t* N_out,
                       uint64_t* K_out)
 {
     int rc = check_input(dense, nx, ny, nz, rate, metric);
     if (rc) return rc;
+    if ((flags & REF_PARTIAL) && (!(pfrac > 0.0f && pfrac <= 1.0f) || isnan(ptau)))
+        return REF_E_INVALID;
     uint64_t n = (uint64_t)nx * ny * nz;
     float B;
     if (flags & REF_BG_EXPLICIT) {
@@ -186,13 +247,54 @@ static int activation(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
         free(active);
         return rc;
     }
-    for (uint64_t s = 0; s < K; ++s) {
+    /* bricks activated whole: the first K, or with REF_PARTIAL the first F */
+    uint64_t F = K;
+    if (flags & REF_PARTIAL) {
+        /* similarities of the ranked bricks, recomputed as in ref_brick_order */
+        float* lo = (float*)malloc(N * sizeof(float));
+        float* hi = (float*)malloc(N * sizeof(float));
+        if (!lo || !hi) {
+            free(lo);
+            free(hi);
+            free(order);
+            free(active);
+            return REF_E_NOMEM;
+        }
+        ref_brick_ranges(dense, nx, ny, nz, lo, hi);
+        F = 0;
+        while (F < K && ref_similarity(metric, lo[order[F]], hi[order[F]], B) >= (double)ptau) ++F;
+        free(lo);
+        free(hi);
+    }
+    for (uint64_t s = 0; s < F; ++s) {
         uint32_t b = order[s];
         uint32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
         for (uint32_t z = bz * BRICK; z < nz && z < (bz + 1) * BRICK; ++z)
             for (uint32_t y = by * BRICK; y < ny && y < (by + 1) * BRICK; ++y)
                 for (uint32_t x = bx * BRICK; x < nx && x < (bx + 1) * BRICK; ++x)
                     active[x + (uint64_t)nx * (y + (uint64_t)ny * z)] = 1;
+    }
+    if (F < K) {
+        /* the budget: the voxels of the bricks ranked F..K-1 */
+        uint64_t R = 0;
+        for (uint64_t s = F; s < K; ++s) R += brick_voxels(order[s], nbx, nby, nx, ny, nz);
+        /* first sweep: ceil(p v) voxels of each brick from rank F on;
+         * second sweep: the rest of each brick, in the same rank order */
+        for (int sweep = 0; sweep < 2 && R > 0; ++sweep)
+            for (uint64_t s = F; s < N && R > 0; ++s) {
+                uint64_t cnt = 0;
+                voxel_key* keys = brick_voxel_order(dense, order[s], nbx, nby, nx, ny, nz, B, &cnt);
+                if (!keys) {
+                    free(order);
+                    free(active);
+                    return REF_E_NOMEM;
+                }
+                uint64_t share = (uint64_t)ceil((double)pfrac * (double)cnt);
+                if (share > cnt) share = cnt;
+                uint64_t a = sweep == 0 ? 0 : share, e = sweep == 0 ? share : cnt;
+                for (uint64_t j = a; j < e && R > 0; ++j, --R) active[keys[j].idx] = 1;
+                free(keys);
+            }
     }
     if (!(flags & REF_NO_CORNERS)) {
         active[0] = 1;
@@ -206,16 +308,38 @@ static int activation(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
     return REF_OK;
 }
 
-int ref_reconstruct(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
-                    float rate, uint32_t metric, uint32_t flags, float bg, float* R)
+int ref_reconstruct_partial(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
+                            float rate, uint32_t metric, uint32_t flags, float bg, float pfrac,
+                            float ptau, float* R)
 {
     uint8_t* active = NULL;
     float B;
     uint64_t N, K;
-    int rc = activation(dense, nx, ny, nz, rate, metric, flags, bg, &active, &B, &N, &K);
+    int rc = activation(dense, nx, ny, nz, rate, metric, flags, bg, pfrac, ptau, &active, &B, &N, &K);
     if (rc) return rc;
     uint64_t n = (uint64_t)nx * ny * nz;
     for (uint64_t i = 0; i < n; ++i) R[i] = active[i] ? dense[i] : B;
+    free(active);
+    return REF_OK;
+}
+
+int ref_reconstruct(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
+                    float rate, uint32_t metric, uint32_t flags, float bg, float* R)
+{
+    if (flags & REF_PARTIAL) return REF_E_INVALID;
+    return ref_reconstruct_partial(dense, nx, ny, nz, rate, metric, flags, bg, 1.0f, 0.0f, R);
+}
+
+int ref_active_mask(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz, float rate,
+                    uint32_t metric, uint32_t flags, float bg, float pfrac, float ptau,
+                    uint8_t* mask)
+{
+    uint8_t* active = NULL;
+    float B;
+    uint64_t N, K;
+    int rc = activation(dense, nx, ny, nz, rate, metric, flags, bg, pfrac, ptau, &active, &B, &N, &K);
+    if (rc) return rc;
+    memcpy(mask, active, (uint64_t)nx * ny * nz);
     free(active);
     return REF_OK;
 }
@@ -234,10 +358,18 @@ int ref_encode(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
                float rate, uint32_t metric, uint32_t flags, float bg,
                uint8_t** out, uint64_t* bytes, ref_stats* st)
 {
+    if (flags & REF_PARTIAL) return REF_E_INVALID;
+    return ref_encode_partial(dense, nx, ny, nz, rate, metric, flags, bg, 1.0f, 0.0f, out, bytes, st);
+}
+
+int ref_encode_partial(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
+                       float rate, uint32_t metric, uint32_t flags, float bg, float pfrac,
+                       float ptau, uint8_t** out, uint64_t* bytes, ref_stats* st)
+{
     uint8_t* active = NULL;
     float B;
     uint64_t N, K;
-    int rc = activation(dense, nx, ny, nz, rate, metric, flags, bg, &active, &B, &N, &K);
+    int rc = activation(dense, nx, ny, nz, rate, metric, flags, bg, pfrac, ptau, &active, &B, &N, &K);
     if (rc) return rc;
     const int prune = !(flags & REF_NO_PRUNE);
     uint64_t n = (uint64_t)nx * ny * nz;
@@ -395,6 +527,10 @@ int ref_encode(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
     put64(buf + 136, off_lmask);
     put64(buf + 144, off_lval);
     put64(buf + 152, total);
+    if (flags & REF_PARTIAL) {
+        putf(buf + 160, pfrac);
+        putf(buf + 164, ptau);
+    }
 
     uint32_t up_i = 0, lo_i = 0, leaf_i = 0, ut_i = 0, lt_i = 0;
     for (uint32_t uz = 0; uz < Uz; ++uz)

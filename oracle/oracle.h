@@ -32,7 +32,7 @@ extern "C" {
 #endif
 
 enum { REF_OK = 0, REF_E_INVALID = 1, REF_E_NOMEM = 2, REF_E_FORMAT = 4 };
-enum { REF_BG_EXPLICIT = 1u, REF_NO_CORNERS = 2u, REF_NO_PRUNE = 4u };
+enum { REF_BG_EXPLICIT = 1u, REF_NO_CORNERS = 2u, REF_NO_PRUNE = 4u, REF_PARTIAL = 8u };
 
 typedef struct {
     float background;
@@ -69,6 +69,21 @@ int ref_reconstruct(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
 int ref_encode(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
                float rate, uint32_t metric, uint32_t flags, float bg,
                uint8_t** out, uint64_t* bytes, ref_stats* st);
+/* Partial-brick activation (Section 3.2.1 names it as future work; the rule
+ * is stated in encode.c): flags must include REF_PARTIAL, pfrac in (0, 1] is
+ * the share of a brick's voxels activated first, ptau the similarity from
+ * which down bricks are activated partially.  The header records pfrac and
+ * ptau at bytes 160 and 164. */
+int ref_reconstruct_partial(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
+                            float rate, uint32_t metric, uint32_t flags, float bg, float pfrac,
+                            float ptau, float* R);
+int ref_encode_partial(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz,
+                       float rate, uint32_t metric, uint32_t flags, float bg, float pfrac,
+                       float ptau, uint8_t** out, uint64_t* bytes, ref_stats* st);
+/* The activation itself: mask[i] = 1 where voxel i is active (any flags). */
+int ref_active_mask(const float* dense, uint32_t nx, uint32_t ny, uint32_t nz, float rate,
+                    uint32_t metric, uint32_t flags, float bg, float pfrac, float ptau,
+                    uint8_t* mask);
 void ref_free(void* p);
 
 /* ---- Field access (Section 3.2.2): lookup, nearest, trilinear ---- */

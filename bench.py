@@ -3,15 +3,21 @@
 dense float32 baseline on one MI355X, plus trilinear samples/s, the roofline
 of the dominant kernel and the CPU oracle timed on a sample of the same work.
 
-One step = one frame of the hot path on the resident 512^3 cloud: majorant
-grid rebuild (the transfer function may change per frame) + delta-tracking
-path tracer, 1024x1024 pixels x 16 samples, <= 8 bounces.  Prints one JSON
-line on stdout; progress goes to stderr.
+Headline (default, ``--workload paper``): the paper-scale frame.  A
+1987x1351x2449 billowed fBm cloud (26.3 GB of float32, the WDAS cloud's
+resolution), encoded at 1:10 and resident in HBM; one step = majorant grid
+rebuild (the transfer function may change per frame) + delta-tracking path
+tracer, 1920x1080 pixels x 64 samples, <= 16 bounces.  The dense array is
+rendered on the same GPU with the same kernels as the baseline.
+``--workload mid`` runs the same step on the 512^3 cloud (1024x1024 x 16 spp,
+<= 8 bounces).  Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -25,6 +31,17 @@ METRIC = "VDB vs dense samples/s & path-traced Mrays/s at 1:10; relMSE vs oracle
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_RENDER_SAMPLE = 32      # 8 float32 corners of one trilinear sample
 BYTES_PER_RANDOM_SAMPLE = 48      # + 12 B position + 4 B result (vdbc_sample)
+BRICK = 32                        # brick edge of the encoder (Alg. 1)
+
+# committed rocprofv3 counter summaries of pt_kernel<VdbAcc>, one per frame
+PROFILES = {"paper": os.path.join(ROOT, "profiles", "pt_kernel_vdb_paper_1to10.md"),
+            "mid": os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")}
+PROFILE = PROFILES["paper"]
+# sources of the PT kernel and its launch: the committed counters are valid
+# while these files are unchanged
+KERNEL_SOURCES = ["paper_2504_04564_amd/csrc/pt.h", "paper_2504_04564_amd/csrc/render.hip",
+                  "paper_2504_04564_amd/csrc/kcommon.h", "paper_2504_04564_amd/csrc/device.h",
+                  "paper_2504_04564_amd/csrc/format.h"]
 
 
 def log(*a):
@@ -37,31 +54,27 @@ def relmse(x, y):
     return float(np.mean((x - y) ** 2 / (y * y + 0.01)))
 
 
-PROFILE = os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")
-# sources of the PT kernel and its launch: the committed counters are valid
-# while these files are unchanged
-KERNEL_SOURCES = ["paper_2504_04564_amd/csrc/pt.h", "paper_2504_04564_amd/csrc/render.hip",
-                  "paper_2504_04564_amd/csrc/kcommon.h", "paper_2504_04564_amd/csrc/device.h",
-                  "paper_2504_04564_amd/csrc/format.h"]
-
-
-def profile_values():
-    """Figures of the committed rocprofv3 counter summary of the PT kernel
-    (HBM bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the
-    kernel sources changed since the counters were taken."""
-    import hashlib
-    if not os.path.exists(PROFILE):
-        return {}
+def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_values(path: str | None = None):
+    """Figures of a committed rocprofv3 counter summary of the PT kernel (HBM
+    bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the kernel
+    sources changed since the counters were taken."""
+    path = path or PROFILE
+    if not os.path.exists(path):
+        return {}
     vals = {}
-    for line in open(PROFILE):
+    for line in open(path):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != h.hexdigest()[:16]:
+    if vals.get("source_hash") != kernel_source_hash():
         return {}
     try:
         return {"traffic": int(float(vals["traffic_bytes_per_launch"])),
@@ -69,6 +82,28 @@ def profile_values():
                 "l2_hit_rate": float(vals["l2_hit_rate"])}
     except (KeyError, ValueError):
         return {}
+
+
+def host_cpu():
+    """CPU model, `nproc` and the cores this process may run on (affinity
+    and cgroup quota)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else nproc
+    try:
+        q, p = open("/sys/fs/cgroup/cpu.max").read().split()
+        if q != "max":
+            usable = min(usable, max(1, math.ceil(int(q) / int(p))))
+    except (OSError, ValueError):
+        pass
+    return {"cpu_model": model, "nproc": nproc, "usable_cores": usable}
 
 
 def time_frames(torch, r, steps, warmup):
@@ -111,18 +146,109 @@ def time_sampler(torch, fn, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
+def occupied_bricks(vol: np.ndarray, background: float, threads: int) -> np.ndarray:
+    """(bx, by, bz) of every 32^3 brick holding a voxel other than the
+    background (input preparation for the random-position microbenchmark)."""
+    from concurrent.futures import ThreadPoolExecutor
+    nz, ny, nx = vol.shape
+    nbx, nby, nbz = -(-nx // BRICK), -(-ny // BRICK), -(-nz // BRICK)
+
+    def slab(bz):
+        s = vol[bz * BRICK:(bz + 1) * BRICK]
+        nzs = s.shape[0]
+        occ = np.zeros((nby, nbx), bool)
+        for by in range(nby):
+            row = s[:, by * BRICK:(by + 1) * BRICK, :] != background
+            cols = row.reshape(nzs * row.shape[1], nx).any(axis=0)
+            pad = np.zeros(nbx * BRICK, bool)
+            pad[:nx] = cols
+            occ[by] = pad.reshape(nbx, BRICK).any(axis=1)
+        return occ
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        occ = np.stack(list(ex.map(slab, range(nbz))))       # (nbz, nby, nbx)
+    bz, by, bx = np.nonzero(occ)
+    return np.stack([bx, by, bz], axis=1).astype(np.int64)
+
+
+def oracle_baseline(fld, cam, med, prm, img, W, H, spp, pixels, threads, cpu):
+    """The CPU oracle timed on the GPU host: majorant grid over the whole
+    volume (disjoint cell ranges on `threads` concurrent calls; its
+    single-core time is the sum of the calls' thread CPU times), then the
+    path tracer on `pixels` random pixels on one core and on `threads` x
+    `pixels` more pixels in concurrent calls.  Returns (cpu_baseline, relMSE
+    of the GPU image against the oracle on every oracle pixel)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    C = prm["macrocell"]
+    f = fld.f
+    g = [(-(-n // C)) for n in (f.nz, f.ny, f.nx)]
+    mj = np.zeros(g, np.float64)
+    cuts = np.linspace(0, mj.size, 8 * threads + 1).astype(np.int64)
+
+    def chunk(i):
+        t0 = time.thread_time()
+        oracle.majorant(fld, med, C, (cuts[i], cuts[i + 1]), mj)
+        return time.thread_time() - t0
+
+    t = time.time()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        maj_cpu = float(sum(ex.map(chunk, range(len(cuts) - 1))))
+    maj_wall = time.time() - t
+    log(f"[bench] oracle majorant: {maj_wall:.1f}s on {threads} threads ({maj_cpu:.1f} core-s)")
+    rng = np.random.default_rng(52)
+    pix_all = np.sort(rng.choice(W * H, pixels * (threads + 1), replace=False)).astype(np.uint32)
+    pix1 = pix_all[::threads + 1]
+    rest = np.setdiff1d(pix_all, pix1)
+    t = time.time()
+    ref1 = oracle.render_pt(fld, cam, med, prm, pixels=pix1, majorant=mj)
+    t1 = time.time() - t
+    rays = W * H * spp
+    frame1 = maj_cpu + t1 * (W * H / len(pix1))
+    out = {"value": round(rays / frame1 / 1e6, 6), "unit": "Mrays/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{len(pix1)} random pixels x {spp} spp of the same frame on one core "
+                     f"({t1:.1f}s) plus the majorant grid of the whole volume ({maj_cpu:.1f} "
+                     f"core-s); frame time extrapolated as majorant + paths x {W * H}/{len(pix1)}",
+           **cpu}
+    errs = [relmse(img[pix1], ref1) * len(pix1)]
+    log(f"[bench] oracle 1 core: {out['value']:.4f} Mrays/s ({len(pix1)} pixels in {t1:.1f}s)")
+    if threads > 1 and len(rest):
+        parts = np.array_split(rest, threads)
+        t = time.time()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            refs = list(ex.map(lambda pp: oracle.render_pt(fld, cam, med, prm, pixels=pp,
+                                                           majorant=mj), parts))
+        tp = time.time() - t
+        frame_p = maj_wall + tp * (W * H / len(rest))
+        out["all_cores"] = {
+            "value": round(rays / frame_p / 1e6, 6), "unit": "Mrays/s", "cores": threads,
+            "sample": f"{len(rest)} random pixels x {spp} spp in {threads} concurrent oracle "
+                      f"calls ({tp:.1f}s) after the threaded majorant ({maj_wall:.1f}s); frame "
+                      f"time extrapolated as majorant + paths x {W * H}/{len(rest)}"}
+        errs += [relmse(img[pp], rr) * len(pp) for pp, rr in zip(parts, refs)]
+        log(f"[bench] oracle {threads} threads: {out['all_cores']['value']:.3f} Mrays/s")
+    rel = float(sum(errs) / len(pix_all if threads > 1 else pix1))
+    out["relmse_pixels"] = int(len(pix_all) if threads > 1 else len(pix1))
+    return out, rel
+
+
 def main():
+    cpu = host_cpu()
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rate", type=float, default=0.10)
-    ap.add_argument("--size", type=int, default=512, help="cloud edge (512 = the workload)")
-    ap.add_argument("--cpu-pixels", type=int, default=65536,
-                    help="pixels of the frame the CPU oracle renders for its baseline")
+    ap.add_argument("--size", type=int, default=512, help="mid workload: cloud edge")
+    ap.add_argument("--cpu-pixels", type=int, default=None,
+                    help="pixels the single-core CPU oracle renders (default 32768 on the "
+                         "paper frame, 65536 on the mid frame)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
-                    help="host threads for the all-core oracle figure (1 = single-core only)")
+    ap.add_argument("--cpu-threads", type=int, default=cpu["usable_cores"],
+                    help="host threads for the majorant and the all-core oracle figure "
+                         "(default: the cores this process may use)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the dense renderer and the random-sample microbenchmark")
     ap.add_argument("--macrocell", type=int, default=16, help="majorant cell edge in voxels")
@@ -132,13 +258,19 @@ def main():
     ap.add_argument("--denoiser-full", action="store_true",
                     help="denoiser workload: 1,000 crops of 512^2 with 1024-spp targets from 256^3..512^3 "
                          "clouds (about 14 minutes) instead of 96 crops of 256^2 with 512-spp targets")
-    ap.add_argument("--workload", default="mid",
-                    choices=("mid", "paper", "denoiser", "batch", "quality", "worstcase", "iso", "ea", "tune"),
-                    help="mid: the headline 512^3 frame; paper: 1987x1351x2449 rate sweep; "
+    ap.add_argument("--workload", default="paper",
+                    choices=("paper", "mid", "sweep", "denoiser", "batch", "quality", "worstcase",
+                             "iso", "ea", "tune"),
+                    help="paper: the headline 1987x1351x2449 frame at --rate; mid: the same step "
+                         "on the 512^3 cloud; sweep: paper-scale rates 1:20..1:4 and dense; "
                          "denoiser: train and evaluate the learned denoiser; batch: 64 volumes; "
                          "quality: MSE/PSNR vs rate and metric; worstcase: lossless dense noise; "
                          "iso: iso-surface marcher; ea: emission-absorption marcher; "
-                         "tune: the render autotuner on the headline frame")
+                         "tune: the render autotuner on the mid frame")
+    ap.add_argument("--vdb-cache", default=None,
+                    help="paper/mid frame: file holding the encoded buffer.  Written after "
+                         "encoding; with --no-extras an existing file is read instead of "
+                         "generating and encoding the volume (profiling passes)")
     ap.add_argument("--worst-max", type=int, default=1024,
                     help="worstcase workload: largest noise cube edge (2048 = the paper's 34 GB)")
     args = ap.parse_args()
@@ -170,34 +302,67 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
                           "launches": 3}))
         return
-    if args.workload != "mid":
+    if args.workload not in ("paper", "mid"):
         import bench_workloads
         line = getattr(bench_workloads, args.workload)(args, torch, vdbc, synth, scenes, log)
         print(json.dumps(line), flush=True)
         return
-    M = scenes.MID
-    n = args.size
-    W, H, spp, bounces = M["width"], M["height"], M["spp"], M["max_bounces"]
 
-    log(f"[bench] generating {n}^3 cloud")
-    t = time.time()
-    vol = synth.mid_volume(n=n)
-    log(f"[bench] volume ready in {time.time() - t:.1f}s; encoding at rate {args.rate}")
-    t = time.time()
-    buf, st = vdbc.encode(vol, args.rate)
-    encode_s = time.time() - t
-    log(f"[bench] encoded {buf.size / 1e6:.1f} MB in {encode_s:.2f}s "
-        f"(achieved rate {st['achieved_rate']:.4f})")
+    threads = max(1, args.cpu_threads)
+    if args.workload == "paper":
+        S = scenes.PAPER
+        nx, ny, nz = S["dims"]
+        name = f"fbm-cloud-{nx}x{ny}x{nz}-billowed"
+        cpu_pixels = args.cpu_pixels or 32768
+    else:
+        S = scenes.MID
+        nx = ny = nz = args.size
+        name = f"fbm-cloud-{nx}^3"
+        cpu_pixels = args.cpu_pixels or 65536
+    dims = (nx, ny, nz)
+    W, H, spp, bounces = S["width"], S["height"], S["spp"], S["max_bounces"]
+    vol_bytes = 4 * nx * ny * nz
+    cached = bool(args.vdb_cache and args.no_extras and os.path.exists(args.vdb_cache))
+    if cached:
+        # a profiling pass: the buffer an earlier run of this workload encoded
+        raw = np.fromfile(args.vdb_cache, dtype=np.uint8)
+        buf = vdbc._aligned(raw.size)
+        buf[:] = raw
+        del raw
+        st = vdbc.validate(buf)
+        st["achieved_rate"] = st["active_voxels"] / (nx * ny * nz)
+        h = tuple(int(x) for x in np.frombuffer(buf[8:20].tobytes(), "<u4"))
+        if h != dims:
+            raise SystemExit(f"{args.vdb_cache} holds a {h} volume, not {dims}")
+        vol = None
+        encode_s = 0.0
+        log(f"[bench] read the encoded buffer from {args.vdb_cache} ({buf.size / 1e6:.1f} MB)")
+    else:
+        log(f"[bench] generating the {name} cloud on {threads} threads")
+        t = time.time()
+        vol = (synth.paper_volume(dims=S["dims"], threads=threads) if args.workload == "paper"
+               else synth.mid_volume(n=nx))
+        log(f"[bench] volume ready in {time.time() - t:.1f}s ({vol.nbytes / 1e9:.2f} GB); "
+            f"encoding at rate {args.rate}")
+        t = time.time()
+        buf, st = vdbc.encode(vol, args.rate)
+        encode_s = time.time() - t
+        log(f"[bench] encoded {buf.size / 1e6:.1f} MB in {encode_s:.2f}s "
+            f"(achieved rate {st['achieved_rate']:.4f})")
+        if args.vdb_cache:
+            buf.tofile(args.vdb_cache)
+            if args.no_extras:
+                del vol
+                vol = None
     torch.cuda.synchronize()
     t = time.time()
     grid = vdbc.Grid(buf)
     torch.cuda.synchronize()
     upload_s = time.time() - t
-    dense = torch.from_numpy(vol).cuda()
-    cam = scenes.orbit_camera((n, n, n), W, H)
+    cam = scenes.orbit_camera(dims, W, H)
     med = scenes.pt_medium(64.0)
     C = args.macrocell
-    prm = dict(spp=spp, max_bounces=bounces, seed=M["seed"], macrocell=C,
+    prm = dict(spp=spp, max_bounces=bounces, seed=S["seed"], macrocell=C,
                flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
     rays = W * H * spp
 
@@ -205,21 +370,35 @@ def main():
     ms_step, maj_ms, pt_ms = time_frames(torch, r_vdb, args.steps, args.warmup)
     samples = r_vdb.sample_count()
     img = r_vdb.image.cpu().numpy().reshape(-1, 4)
+    del r_vdb
     vdb_mrays = rays / (ms_step * 1e-3) / 1e6
     log(f"[bench] VDB PT: {ms_step:.2f} ms/frame (majorant {maj_ms:.2f} ms, PT {pt_ms:.2f} ms), "
         f"{vdb_mrays:.1f} Mrays/s, {samples / 1e6:.1f} M samples/frame")
 
     extras = {}
-    if not args.no_extras:
+    if not args.no_extras and vol is not None:
+        t = time.time()
+        dense = torch.from_numpy(vol).cuda()
+        torch.cuda.synchronize()
+        log(f"[bench] dense array uploaded in {time.time() - t:.1f}s")
         r_d = vdbc.Renderer(dense, cam, med, prm, vdbc.MODE_PT, background=0.0)
         d_step, d_maj, d_pt = time_frames(torch, r_d, args.steps, args.warmup)
         d_samples = r_d.sample_count()
+        del r_d
         dense_mrays = rays / (d_step * 1e-3) / 1e6
-        log(f"[bench] dense PT: {d_step:.2f} ms/frame, {dense_mrays:.1f} Mrays/s")
-        # random-position trilinear microbenchmark
+        log(f"[bench] dense PT: {d_step:.2f} ms/frame (majorant {d_maj:.2f} ms, PT {d_pt:.2f} ms), "
+            f"{dense_mrays:.1f} Mrays/s")
+        # random-position trilinear microbenchmark: positions uniform inside
+        # bricks that hold a non-background voxel
+        occ = occupied_bricks(vol, 0.0, threads)
         ns = 1 << 26
         g = torch.Generator(device="cuda").manual_seed(7)
-        pos = (torch.rand((ns, 3), device="cuda", generator=g) * (n + 1.0) - 1.0).contiguous()
+        ob = torch.from_numpy(occ).cuda()
+        pick = torch.randint(0, ob.shape[0], (ns,), device="cuda", generator=g)
+        off = torch.rand((ns, 3), device="cuda", generator=g) * BRICK - 0.5
+        hi = torch.tensor([nx - 0.5, ny - 0.5, nz - 0.5], device="cuda")
+        pos = torch.minimum(ob[pick].to(torch.float32) * BRICK + off, hi).contiguous()
+        del pick, off, ob
         out = torch.empty(ns, dtype=torch.float32, device="cuda")
         sv_ms = time_sampler(torch, lambda: vdbc.sample(grid, pos, 1, out), args.steps, 2)
         sd_ms = time_sampler(torch, lambda: vdbc.sample_dense(dense, 0.0, pos, 1, out),
@@ -228,12 +407,16 @@ def main():
             "dense_mrays_per_s": round(dense_mrays, 3),
             "vdb_over_dense_mrays": round(vdb_mrays / dense_mrays, 4),
             "dense_ms_per_step": round(d_step, 4),
+            "dense_majorant_ms": round(d_maj, 4),
             "samples_per_s": {
                 "vdb_render": round(samples / (pt_ms * 1e-3), 1),
                 "dense_render": round(d_samples / (d_pt * 1e-3), 1),
                 "vdb_sample_random_2^26": round(ns / (sv_ms * 1e-3), 1),
                 "dense_sample_random_2^26": round(ns / (sd_ms * 1e-3), 1),
             },
+            "random_sample_positions": f"2^26 uniform inside the {len(occ)} of "
+                                       f"{math.prod(-(-d // BRICK) for d in dims)} bricks that hold "
+                                       "a non-background voxel",
             "random_sample_gbs": {
                 "vdb": round(ns * BYTES_PER_RANDOM_SAMPLE / (sv_ms * 1e-3) / 1e9, 2),
                 "dense": round(ns * BYTES_PER_RANDOM_SAMPLE / (sd_ms * 1e-3) / 1e9, 2),
@@ -241,7 +424,8 @@ def main():
         }
         log(f"[bench] random samples/s: VDB {ns / (sv_ms * 1e-3) / 1e9:.2f} G, "
             f"dense {ns / (sd_ms * 1e-3) / 1e9:.2f} G")
-        del pos, out
+        del pos, out, dense
+        torch.cuda.empty_cache()
         # the HBM bandwidth a plain streaming copy reaches on this GPU (1 GiB
         # read + 1 GiB written per launch), next to the 8 TB/s datasheet figure
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -250,55 +434,23 @@ def main():
         extras["hbm_copy_gbs"] = round(2 * x.numel() * 4 / (copy_ms * 1e-3) / 1e9, 1)
         log(f"[bench] streaming copy: {extras['hbm_copy_gbs']:.0f} GB/s")
         del x, y
+    del vol
 
-    cpu = None
+    cpu_line = None
     rel = None
     if not args.no_cpu_baseline:
         import oracle
-        log(f"[bench] CPU oracle on {args.cpu_pixels} of {W * H} pixels")
-        rng = np.random.default_rng(52)
-        pix = np.sort(rng.choice(W * H, args.cpu_pixels, replace=False)).astype(np.uint32)
-        fld = oracle.VdbField(buf)
-        t = time.time()
-        oracle.majorant(fld, med, C)
-        t_maj = time.time() - t
-        t = time.time()
-        ref = oracle.render_pt(fld, cam, med, dict(spp=spp, max_bounces=bounces,
-                                                   seed=M["seed"], macrocell=C), pixels=pix)
-        t_all = time.time() - t
-        t_paths = max(t_all - t_maj, 1e-9)
-        frame_s = t_maj + t_paths * (W * H / len(pix))
-        rel = relmse(img[pix], ref)
-        cpu = {"value": round(rays / frame_s / 1e6, 6), "unit": "Mrays/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{len(pix)} random pixels x {spp} spp of the same frame "
-                         f"({t_all:.1f}s incl. a {t_maj:.1f}s majorant build); frame time "
-                         f"extrapolated as majorant + paths x {W * H}/{len(pix)}"}
-        log(f"[bench] oracle {cpu['value']:.4f} Mrays/s; relMSE GPU vs oracle {rel:.3e}")
-        if args.cpu_threads > 1:
-            # the same oracle on every host core: disjoint pixel sets rendered
-            # by concurrent calls (ctypes releases the GIL during each call)
-            from concurrent.futures import ThreadPoolExecutor
-            nt = args.cpu_threads
-            pix_all = np.sort(rng.choice(W * H, args.cpu_pixels * nt, replace=False)).astype(np.uint32)
-            parts = np.array_split(pix_all, nt)
-            prm_o = dict(spp=spp, max_bounces=bounces, seed=M["seed"], macrocell=C)
-            t = time.time()
-            with ThreadPoolExecutor(max_workers=nt) as ex:
-                list(ex.map(lambda pp: oracle.render_pt(fld, cam, med, prm_o, pixels=pp), parts))
-            t_par = time.time() - t
-            # each call also builds its own majorant (t_maj of work per thread)
-            paths_s = max(t_par - t_maj, 1e-9)
-            frame_par = t_maj + paths_s * (W * H / len(pix_all))
-            cpu["all_cores"] = {
-                "value": round(rays / frame_par / 1e6, 6), "unit": "Mrays/s", "cores": nt,
-                "sample": f"{len(pix_all)} random pixels x {spp} spp in {nt} concurrent oracle calls "
-                          f"({t_par:.1f}s); frame time extrapolated as majorant + paths x "
-                          f"{W * H}/{len(pix_all)}"}
-            log(f"[bench] oracle on {nt} threads: {cpu['all_cores']['value']:.3f} Mrays/s")
+        log(f"[bench] CPU oracle on {cpu_pixels} (+{cpu_pixels * threads} on {threads} threads) "
+            f"of {W * H} pixels")
+        oprm = dict(spp=spp, max_bounces=bounces, seed=S["seed"], macrocell=C)
+        cpu_line, rel = oracle_baseline(oracle.VdbField(buf), cam, med, oprm, img, W, H, spp,
+                                        cpu_pixels, threads, cpu)
+        log(f"[bench] relMSE GPU vs oracle {rel:.3e} on {cpu_line['relmse_pixels']} pixels")
 
     pt_s = pt_ms * 1e-3
-    prof = profile_values() if (args.rate == 0.10 and n == 512 and C == 16) else {}
+    prof_path = PROFILES[args.workload]
+    standard = (args.rate == 0.10 and C == 16 and (args.workload == "paper" or nx == 512))
+    prof = profile_values(prof_path) if standard else {}
     achieved = samples * BYTES_PER_RENDER_SAMPLE / pt_s / 1e9
     line = {
         "metric": METRIC,
@@ -314,11 +466,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"fbm-cloud-{n}^3-vdb-1:{round(1 / args.rate)}-pt-{W}x{H}x{spp}spp-"
+            "workload": f"{name}-vdb-1:{round(1 / args.rate)}-pt-{W}x{H}x{spp}spp-"
                         f"{bounces}bounces",
-            "dims": [n, n, n], "rate": args.rate, "width": W, "height": H, "spp": spp,
+            "dims": list(dims), "rate": args.rate, "width": W, "height": H, "spp": spp,
             "max_bounces": bounces, "macrocell": C,
-            "vdb_bytes": int(buf.size), "dense_bytes": int(vol.nbytes),
+            "vdb_bytes": int(buf.size), "dense_bytes": vol_bytes,
             "achieved_rate": round(st["achieved_rate"], 5),
         },
         "roofline": {
@@ -335,12 +487,12 @@ def main():
             "limiter": ({"kind": "VALU issue of divergent lanes (counters of the same kernel build)",
                          "valu_lane_utilisation": prof["valu_lane_utilisation"],
                          "l2_hit_rate": prof["l2_hit_rate"],
-                         "source": os.path.relpath(PROFILE, ROOT)} if prof else None),
+                         "source": os.path.relpath(prof_path, ROOT)} if prof else None),
             "per_launch": {"samples": int(samples), "bytes_per_sample": BYTES_PER_RENDER_SAMPLE,
                            "algorithmic_bytes": int(samples * BYTES_PER_RENDER_SAMPLE),
                            "avg_ms": round(pt_ms, 4)},
         },
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu_line,
         "relmse_vs_oracle": rel,
         "encode_s": round(encode_s, 3),
         "upload_s": round(upload_s, 4),

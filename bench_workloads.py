@@ -26,7 +26,7 @@ def _median_ms(torch, fn, reps, warmup=1):
     return float(np.median(ts))
 
 
-def paper(args, torch, vdbc, synth, scenes, log):
+def sweep(args, torch, vdbc, synth, scenes, log):
     """1987x1351x2449 billowed cloud (26.3 GB): encode at 1:20..1:4, path
     trace 1920x1080 at 64 spp with <= 16 bounces from every VDB and from the
     dense array on the same GPU."""
@@ -235,11 +235,40 @@ def quality(args, torch, vdbc, synth, scenes, log):
             del g
     lossless = {names[m]: min([r["rate"] for r in rows if r["metric"] == names[m] and r["differing_voxels"] == 0],
                               default=None) for m in (1, 2, 3)}
+    # partial-brick activation (Section 3.2.1 future work) at the same voxel
+    # budget: bricks below the similarity of the brick ranked K/2 (or every
+    # brick) keep a fraction p of their most dissimilar voxels
+    partial_rows = []
+    lo, hi = [], []
+    for q in (0.05, 0.1, 0.2, 0.3):
+        buf0, st0 = vdbc.encode(vol, q)
+        plain = vdbc.compare_dense(vdbc.Grid(buf0), dense)
+        K = int(st0["k_bricks"])
+        # similarity (Eq. 2) of the brick ranked K/2, from the brick ranges
+        nz_, ny_, nx_ = vol.shape
+        if not lo:
+            for bz in range(0, nz_, 32):
+                for by in range(0, ny_, 32):
+                    for bx in range(0, nx_, 32):
+                        blk = vol[bz:bz + 32, by:by + 32, bx:bx + 32]
+                        lo.append(float(blk.min()))
+                        hi.append(float(blk.max()))
+        B = float(st0["background"])
+        f = np.sort(np.maximum(np.abs(np.array(lo) - B), np.abs(np.array(hi) - B)))[::-1]
+        for p, tau_name, tau in ((0.5, "all", 1e30), (0.25, "all", 1e30),
+                                 (0.5, "rank K/2", float(f[K // 2]) if K else 1e30)):
+            buf, st = vdbc.encode(vol, q, partial=(p, tau))
+            c = vdbc.compare_dense(vdbc.Grid(buf), dense)
+            rec = {"rate": q, "fraction": p, "partial_from": tau_name, "mse": c["mse"],
+                   "psnr": c["psnr"], "plain_psnr": plain["psnr"], "vdb_bytes": int(buf.size),
+                   "plain_bytes": int(buf0.size), "achieved_rate": round(st["achieved_rate"], 5)}
+            log(f"[quality] partial {rec}")
+            partial_rows.append(rec)
     return {"metric": "MSE / PSNR of the compressed cloud vs the dense original", "unit": "dB",
             "value": [r for r in rows if r["metric"] == "farthest" and r["rate"] == 0.1][0]["psnr"],
             "config": {"workload": f"fbm-cloud-{n}^3-rates-0.1..1.0-metrics-f1f2f3",
                        "psnr_peak": "max - min of the dense volume"},
-            "lowest_lossless_rate": lossless, "rows": rows}
+            "lowest_lossless_rate": lossless, "rows": rows, "partial_rows": partial_rows}
 
 
 def worstcase(args, torch, vdbc, synth, scenes, log):

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define VDBC_ABI_VERSION 1u
+#define VDBC_ABI_VERSION 2u
 
 typedef enum {
     VDBC_OK = 0,
@@ -68,7 +68,8 @@ typedef struct {
 enum {
     VDBC_BG_EXPLICIT = 1u, /* use params.background instead of the histogram mode */
     VDBC_NO_CORNERS = 2u,  /* do not force-activate the two extreme corner voxels */
-    VDBC_NO_PRUNE = 4u     /* keep uniform leaves/lower nodes instead of tiles */
+    VDBC_NO_PRUNE = 4u,    /* keep uniform leaves/lower nodes instead of tiles */
+    VDBC_PARTIAL = 8u      /* partial-brick activation, see vdbc_encode_params */
 };
 
 enum { VDBC_METRIC_CLOSEST = 1u, VDBC_METRIC_FARTHEST = 2u, VDBC_METRIC_MEDIAN = 3u };
@@ -80,6 +81,25 @@ typedef struct {
     uint32_t flags;     /* VDBC_BG_EXPLICIT | VDBC_NO_CORNERS | VDBC_NO_PRUNE */
     float background;   /* used iff VDBC_BG_EXPLICIT */
     uint32_t threads;   /* host worker threads; 0 = all hardware threads */
+    /* VDBC_PARTIAL only: the partial-brick activation that Section 3.2.1
+     * names as future work (past a similarity threshold, a share of each
+     * brick's voxels in proportionally more bricks; the paper gives no rule
+     * for which voxels, this is the library's).  The
+     * bricks are ranked as in Alg. 1 and K computed from `rate` as above.
+     * The first F = #{ranks r < K : f_r >= partial_threshold} bricks are
+     * activated whole.  The voxels plain Alg. 1 would activate in the bricks
+     * ranked F..K-1 (their in-volume count R) are spent instead along the
+     * bricks ranked F, F+1, ..., N-1: first ceil(partial_fraction * v_r)
+     * voxels of each (v_r its in-volume voxel count; product in double),
+     * then, once every such brick had that share, the rest of each brick in
+     * rank order, until R voxels are active.  Inside a brick the voxels go by
+     * |value - B| descending (double), ties by linear voxel index ascending.
+     * So the active voxel count equals plain Alg. 1's, 1:1 stays lossless,
+     * partial_fraction = 1 or a threshold below every similarity gives Alg. 1
+     * itself, and the selection at a lower rate is a subset of the one at a
+     * higher rate.  The header records both values (bytes 160 and 164). */
+    float partial_fraction;   /* in (0, 1] */
+    float partial_threshold;  /* similarity (Eq. 1-3 units), not NaN */
 } vdbc_encode_params;
 
 typedef struct {

@@ -76,6 +76,7 @@ def build(verbose: bool = False) -> str:
 def built_hash(path: str = LIB) -> str:
     """Source hash recorded in a built library (vdbc_source_hash)."""
     import ctypes
+    import torch  # noqa: F401  (torch's HIP runtime first: see vdbc._torch_hip_first)
     L = ctypes.CDLL(path)
     L.vdbc_source_hash.restype = ctypes.c_char_p
     return L.vdbc_source_hash().decode()

@@ -46,6 +46,8 @@ vdbc_status parse_header(const void* header, uint64_t bytes, Header* out)
     h.metric = get<uint32_t>(p, hdr::metric);
     h.flags = get<uint32_t>(p, hdr::flags);
     h.layout = get<uint32_t>(p, hdr::layout);
+    h.partial_fraction = get<float>(p, hdr::partial_fraction);
+    h.partial_threshold = get<float>(p, hdr::partial_threshold);
     h.n_bricks = get<uint64_t>(p, hdr::n_bricks);
     h.k_bricks = get<uint64_t>(p, hdr::k_bricks);
     h.active_voxels = get<uint64_t>(p, hdr::active_voxels);

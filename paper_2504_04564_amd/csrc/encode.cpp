@@ -13,7 +13,10 @@
 //   3. similarity f (Eq. 1-3) in double, bricks sorted by f descending (most
 //      dissimilar from B first), ties by brick index;
 //   4. activation of all voxels of the first K = min(N, floor(q*N + 0.5))
-//      bricks plus the two extreme corner voxels (Section 3.2.1), then
+//      bricks plus the two extreme corner voxels (Section 3.2.1) — or, with
+//      VDBC_PARTIAL, the partial-brick variant Section 3.2.1 leaves as future
+//      work: bricks ranked below the similarity threshold share the same
+//      voxel budget as a fraction of each brick (rule in vdbc.h), then
 //      pruning at tolerance 0 (Section 3.2.1 tree.prune()): full uniform
 //      leaves become lower-node tiles, lower nodes made of one uniform tile
 //      value become upper-node tiles;
@@ -60,6 +63,18 @@ struct LeafRec {
     uint32_t tile_bits; // valid if is_tile
     uint8_t in_brick;   // inside a selected brick (all in-volume voxels active)
     uint8_t is_tile;
+    uint32_t part;      // index of its partially active brick, or kNoChild
+};
+
+// A partially active brick: its active voxels are those that come first in
+// the order (|value - B| descending, linear index ascending), up to and
+// including the last one taken, (d_last, i_last).
+struct PartialBrick {
+    uint32_t brick;
+    uint64_t count;     // active voxels
+    double d_last;
+    uint64_t i_last;
+    uint64_t leaf_any;  // bit l: leaf l (x-fastest 4^3 of the brick) holds an active voxel
 };
 
 struct LowerRec {
@@ -80,6 +95,8 @@ struct vdbc_encoder {
     uint64_t N = 0, K = 0;
     uint32_t nbx = 0, nby = 0, nbz = 0;
     std::vector<uint8_t> brick_sel;
+    std::vector<PartialBrick> partial;
+    std::vector<uint32_t> brick_part;  // brick -> index in `partial` or kNoChild
     std::vector<LeafRec> leaves;      // sorted by key
     std::vector<LowerRec> lowers;     // sorted by key
     std::vector<uint64_t> upper_root; // root index of each upper, ascending
@@ -255,6 +272,95 @@ bool is_corner(const vdbc_encoder& e, uint64_t x, uint64_t y, uint64_t z)
     return (x == 0 && y == 0 && z == 0) || (x == e.nx - 1u && y == e.ny - 1u && z == e.nz - 1u);
 }
 
+uint64_t brick_voxels(const vdbc_encoder& e, uint32_t b)
+{
+    uint32_t bx = b % e.nbx, by = (b / e.nbx) % e.nby, bz = b / (e.nbx * e.nby);
+    return (uint64_t)std::min(kBrick, e.nx - bx * kBrick) * std::min(kBrick, e.ny - by * kBrick) *
+           std::min(kBrick, e.nz - bz * kBrick);
+}
+
+// Voxel (x, y, z) of partially active brick P is active.
+inline bool partial_active(const vdbc_encoder& e, const PartialBrick& P, uint64_t x, uint64_t y,
+                           uint64_t z)
+{
+    const uint64_t i = voxel_index(e, x, y, z);
+    const double d = std::fabs((double)e.dense[i] - (double)e.B);
+    return d > P.d_last || (d == P.d_last && i <= P.i_last);
+}
+
+// The voxel active in brick-selection terms (full brick, partial brick or
+// corner), for a leaf record.
+inline bool leaf_voxel_active(const vdbc_encoder& e, const LeafRec& L, uint64_t x, uint64_t y,
+                              uint64_t z)
+{
+    if (L.in_brick || is_corner(e, x, y, z)) return true;
+    return L.part != kNoChild && partial_active(e, e.partial[L.part], x, y, z);
+}
+
+// Partial-brick activation: the counts per brick from the budget walk, the
+// last voxel taken in each partially active brick and its leaf occupancy.
+// Bricks that end up with all their voxels join `selected`.
+vdbc_status plan_partial(vdbc_encoder& e, const std::vector<uint32_t>& order, uint64_t F,
+                         std::vector<uint32_t>& selected)
+{
+    uint64_t R = 0;
+    for (uint64_t r = F; r < e.K; ++r) R += brick_voxels(e, order[r]);
+    const double frac = (double)e.p.partial_fraction;
+    std::vector<uint64_t> cnt(e.N - F, 0);
+    for (int sweep = 0; sweep < 2 && R > 0; ++sweep)
+        for (uint64_t r = F; r < e.N && R > 0; ++r) {
+            const uint64_t v = brick_voxels(e, order[r]);
+            const uint64_t share = std::min<uint64_t>(v, (uint64_t)std::ceil(frac * (double)v));
+            const uint64_t want = sweep == 0 ? share : v - share;
+            const uint64_t take = std::min(want, R);
+            cnt[r - F] += take;
+            R -= take;
+        }
+    e.partial.clear();
+    e.brick_part.assign(e.N, kNoChild);
+    for (uint64_t r = F; r < e.N; ++r) {
+        const uint64_t c = cnt[r - F];
+        if (c == 0) continue;
+        if (c == brick_voxels(e, order[r])) {
+            selected.push_back(order[r]);
+            continue;
+        }
+        e.brick_part[order[r]] = (uint32_t)e.partial.size();
+        e.partial.push_back(PartialBrick{order[r], c, 0.0, 0, 0});
+    }
+    struct Key {
+        double d;
+        uint64_t i;
+    };
+    std::vector<std::vector<Key>> scratch(e.threads);
+    parallel_for(e.partial.size(), e.threads, [&](uint64_t pi, unsigned t) {
+        PartialBrick& P = e.partial[pi];
+        const uint32_t bx = P.brick % e.nbx, by = (P.brick / e.nbx) % e.nby, bz = P.brick / (e.nbx * e.nby);
+        std::vector<Key>& k = scratch[t];
+        k.clear();
+        for (uint32_t z = bz * kBrick; z < e.nz && z < (bz + 1) * kBrick; ++z)
+            for (uint32_t y = by * kBrick; y < e.ny && y < (by + 1) * kBrick; ++y)
+                for (uint32_t x = bx * kBrick; x < e.nx && x < (bx + 1) * kBrick; ++x) {
+                    const uint64_t i = voxel_index(e, x, y, z);
+                    k.push_back(Key{std::fabs((double)e.dense[i] - (double)e.B), i});
+                }
+        auto before = [](const Key& a, const Key& b) { return a.d > b.d || (a.d == b.d && a.i < b.i); };
+        std::nth_element(k.begin(), k.begin() + (P.count - 1), k.end(), before);
+        P.d_last = k[P.count - 1].d;
+        P.i_last = k[P.count - 1].i;
+        uint64_t any = 0;
+        for (uint32_t z = bz * kBrick; z < e.nz && z < (bz + 1) * kBrick; ++z)
+            for (uint32_t y = by * kBrick; y < e.ny && y < (by + 1) * kBrick; ++y)
+                for (uint32_t x = bx * kBrick; x < e.nx && x < (bx + 1) * kBrick; ++x)
+                    if (partial_active(e, P, x, y, z)) {
+                        const uint32_t l = ((x >> 3) & 3) + 4 * (((y >> 3) & 3) + 4 * ((z >> 3) & 3));
+                        any |= uint64_t(1) << l;
+                    }
+        P.leaf_any = any;
+    });
+    return VDBC_OK;
+}
+
 vdbc_status build_tree(vdbc_encoder& e, const std::vector<uint32_t>& selected)
 {
     const bool prune = !(e.p.flags & VDBC_NO_PRUNE);
@@ -279,8 +385,18 @@ vdbc_status build_tree(vdbc_encoder& e, const std::vector<uint32_t>& selected)
                 for (uint32_t i = 0; i < 4; ++i) {
                     uint32_t lx = 4 * bx + i, ly = 4 * by + j, lz = 4 * bz + k;
                     if (lx >= lgx || ly >= lgy || lz >= lgz) continue;
-                    e.leaves.push_back(LeafRec{make_key(lx, ly, lz), lx, ly, lz, 0, 1, 0});
+                    e.leaves.push_back(LeafRec{make_key(lx, ly, lz), lx, ly, lz, 0, 1, 0, kNoChild});
                 }
+    }
+    // leaves of partially active bricks that hold an active voxel
+    for (uint32_t pi = 0; pi < e.partial.size(); ++pi) {
+        const PartialBrick& P = e.partial[pi];
+        uint32_t bx = P.brick % e.nbx, by = (P.brick / e.nbx) % e.nby, bz = P.brick / (e.nbx * e.nby);
+        for (uint32_t l = 0; l < 64; ++l)
+            if (P.leaf_any >> l & 1) {
+                uint32_t lx = 4 * bx + (l & 3), ly = 4 * by + ((l >> 2) & 3), lz = 4 * bz + (l >> 4);
+                e.leaves.push_back(LeafRec{make_key(lx, ly, lz), lx, ly, lz, 0, 0, 0, pi});
+            }
     }
     // corner leaves outside the selection
     if (!(e.p.flags & VDBC_NO_CORNERS)) {
@@ -289,8 +405,11 @@ vdbc_status build_tree(vdbc_encoder& e, const std::vector<uint32_t>& selected)
             uint32_t lx = cl[c][0], ly = cl[c][1], lz = cl[c][2];
             uint32_t b = (lx / 4) + e.nbx * ((ly / 4) + e.nby * (lz / 4));
             if (e.brick_sel[b]) continue;
+            const uint32_t pi = e.partial.empty() ? kNoChild : e.brick_part[b];
+            const uint32_t l = (lx & 3) + 4 * ((ly & 3) + 4 * (lz & 3));
+            if (pi != kNoChild && (e.partial[pi].leaf_any >> l & 1)) continue;  // leaf exists
             if (c == 1 && lx == 0 && ly == 0 && lz == 0) continue;  // same leaf
-            e.leaves.push_back(LeafRec{make_key(lx, ly, lz), lx, ly, lz, 0, 0, 0});
+            e.leaves.push_back(LeafRec{make_key(lx, ly, lz), lx, ly, lz, 0, 0, 0, pi});
         }
     }
     std::sort(e.leaves.begin(), e.leaves.end(),
@@ -299,7 +418,7 @@ vdbc_status build_tree(vdbc_encoder& e, const std::vector<uint32_t>& selected)
     if (prune) {
         parallel_for(e.leaves.size(), e.threads, [&](uint64_t li, unsigned) {
             LeafRec& L = e.leaves[li];
-            if (!L.in_brick) return;
+            if (!L.in_brick && L.part == kNoChild) return;
             if (leaf_extent(L.lx, e.nx) != 8 || leaf_extent(L.ly, e.ny) != 8 ||
                 leaf_extent(L.lz, e.nz) != 8)
                 return;
@@ -310,6 +429,13 @@ vdbc_status build_tree(vdbc_encoder& e, const std::vector<uint32_t>& selected)
                     for (uint32_t i = 0; i < 8; ++i)
                         if (fbits(r[i]) != first) return;
                 }
+            // a leaf of a partially active brick is a tile only if all 512 are active
+            if (!L.in_brick)
+                for (uint32_t k = 0; k < 8; ++k)
+                    for (uint32_t j = 0; j < 8; ++j)
+                        for (uint32_t i = 0; i < 8; ++i)
+                            if (!leaf_voxel_active(e, L, 8ull * L.lx + i, 8ull * L.ly + j, 8ull * L.lz + k))
+                                return;
             L.is_tile = 1;
             L.tile_bits = first;
         });
@@ -364,6 +490,8 @@ void fill_header(vdbc_encoder& e)
     h.rate = e.p.rate;
     h.metric = e.p.metric;
     h.flags = e.p.flags;
+    h.partial_fraction = (e.p.flags & VDBC_PARTIAL) ? e.p.partial_fraction : 0.0f;
+    h.partial_threshold = (e.p.flags & VDBC_PARTIAL) ? e.p.partial_threshold : 0.0f;
     h.layout = 0;
     h.n_bricks = e.N;
     h.k_bricks = e.K;
@@ -425,6 +553,10 @@ void write_header(const Header& h, uint8_t* o)
     put<uint64_t>(o, hdr::off_leaf_masks, h.off_leaf_masks);
     put<uint64_t>(o, hdr::off_leaf_values, h.off_leaf_values);
     put<uint64_t>(o, hdr::total_bytes, h.total_bytes);
+    if (h.flags & VDBC_PARTIAL) {
+        put<float>(o, hdr::partial_fraction, h.partial_fraction);
+        put<float>(o, hdr::partial_threshold, h.partial_threshold);
+    }
 }
 
 }  // namespace
@@ -447,6 +579,11 @@ extern "C" vdbc_status vdbc_encode_begin(const float* dense, vdbc_dims dims,
         return fail(VDBC_E_INVALID, "vdbc_encode: metric must be 1, 2 or 3");
     if ((p->flags & VDBC_BG_EXPLICIT) && !std::isfinite(p->background))
         return fail(VDBC_E_INVALID, "vdbc_encode: explicit background must be finite");
+    if (p->flags & ~(uint32_t)(VDBC_BG_EXPLICIT | VDBC_NO_CORNERS | VDBC_NO_PRUNE | VDBC_PARTIAL))
+        return fail(VDBC_E_INVALID, "vdbc_encode: unknown flag bits 0x%x", p->flags);
+    if ((p->flags & VDBC_PARTIAL) &&
+        (!(p->partial_fraction > 0.0f && p->partial_fraction <= 1.0f) || std::isnan(p->partial_threshold)))
+        return fail(VDBC_E_INVALID, "vdbc_encode: partial fraction must be in (0, 1] and the threshold not NaN");
     std::unique_ptr<vdbc_encoder> e(new (std::nothrow) vdbc_encoder());
     if (!e) return fail(VDBC_E_NOMEM, "vdbc_encode: no memory");
     e->dense = dense;
@@ -486,24 +623,39 @@ extern "C" vdbc_status vdbc_encode_begin(const float* dense, vdbc_dims dims,
         });
         uint64_t K = (uint64_t)std::floor((double)p->rate * (double)e->N + 0.5);
         e->K = K > e->N ? e->N : K;
-        // step 4: activation
+        // step 4: activation (whole bricks: the first K, or with VDBC_PARTIAL
+        // the first F that reach the threshold, plus any partial-region brick
+        // the budget covers completely)
+        uint64_t F = e->K;
+        if (p->flags & VDBC_PARTIAL) {
+            const double tau = (double)p->partial_threshold;
+            F = 0;
+            while (F < e->K && f[order[F]] >= tau) ++F;
+        }
         e->brick_sel.assign(e->N, 0);
-        std::vector<uint32_t> selected(order.begin(), order.begin() + e->K);
+        std::vector<uint32_t> selected(order.begin(), order.begin() + F);
+        e->partial.clear();
+        e->brick_part.clear();
+        if (F < e->K) {
+            s = plan_partial(*e, order, F, selected);
+            if (s) return s;
+        }
         std::sort(selected.begin(), selected.end());
         for (uint32_t b : selected) e->brick_sel[b] = 1;
         uint64_t active = 0;
-        for (uint32_t b : selected) {
-            uint32_t bx = b % e->nbx, by = (b / e->nbx) % e->nby, bz = b / (e->nbx * e->nby);
-            active += (uint64_t)std::min(kBrick, e->nx - bx * kBrick) *
-                      std::min(kBrick, e->ny - by * kBrick) * std::min(kBrick, e->nz - bz * kBrick);
-        }
+        for (uint32_t b : selected) active += brick_voxels(*e, b);
+        for (const PartialBrick& P : e->partial) active += P.count;
         if (!(p->flags & VDBC_NO_CORNERS)) {
-            uint32_t b0 = 0;
-            uint32_t b1 = ((e->nx - 1) / kBrick) + e->nbx * (((e->ny - 1) / kBrick) +
-                                                           e->nby * ((e->nz - 1) / kBrick));
-            if (!e->brick_sel[b0]) ++active;
-            bool same = (e->nx == 1 && e->ny == 1 && e->nz == 1);
-            if (!same && !e->brick_sel[b1]) ++active;
+            const uint64_t cx[2] = {0, e->nx - 1u}, cy[2] = {0, e->ny - 1u}, cz[2] = {0, e->nz - 1u};
+            const bool same = (e->nx == 1 && e->ny == 1 && e->nz == 1);
+            for (int c = 0; c < (same ? 1 : 2); ++c) {
+                const uint32_t b = (uint32_t)(cx[c] / kBrick) +
+                                   e->nbx * ((uint32_t)(cy[c] / kBrick) + e->nby * (uint32_t)(cz[c] / kBrick));
+                if (e->brick_sel[b]) continue;
+                const uint32_t pi = e->partial.empty() ? kNoChild : e->brick_part[b];
+                if (pi != kNoChild && partial_active(*e, e->partial[pi], cx[c], cy[c], cz[c])) continue;
+                ++active;
+            }
         }
         e->active = active;
         s = build_tree(*e, selected);
@@ -625,7 +777,7 @@ extern "C" vdbc_status vdbc_encode_finish(vdbc_encoder* hnd, void* out_v, uint64
                         uint32_t n3 = i3 + 8 * (j + 8 * k);
                         float val = B;
                         if (x < e->nx && y < e->ny && z < e->nz) {
-                            bool act = F.in_brick || is_corner(*e, x, y, z);
+                            bool act = leaf_voxel_active(*e, F, x, y, z);
                             if (act) {
                                 val = e->dense[voxel_index(*e, x, y, z)];
                                 m[n3 >> 6] |= uint64_t(1) << (n3 & 63);

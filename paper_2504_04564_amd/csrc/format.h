@@ -47,7 +47,8 @@ constexpr int magic = 0, version = 4, nx = 8, ny = 12, nz = 16, background = 20,
               n_upper_tiles = 76, n_lower_tiles = 80, root_nx = 84, root_ny = 88,
               root_nz = 92, off_root = 96, off_upper = 104, off_lower = 112,
               off_upper_tiles = 120, off_lower_tiles = 128, off_leaf_masks = 136,
-              off_leaf_values = 144, total_bytes = 152;
+              off_leaf_values = 144, total_bytes = 152, partial_fraction = 160,
+              partial_threshold = 164;
 }
 
 // Parsed header (host side).
@@ -56,6 +57,7 @@ struct Header {
     float background;
     float rate;
     uint32_t metric, flags, layout;
+    float partial_fraction, partial_threshold;   // VDBC_PARTIAL only, else 0
     uint64_t n_bricks, k_bricks, active_voxels;
     uint32_t n_upper, n_lower, n_leaf, n_upper_tiles, n_lower_tiles;
     uint32_t root_nx, root_ny, root_nz;

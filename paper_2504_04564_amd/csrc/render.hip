@@ -556,11 +556,10 @@ extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_d
     return VDBC_OK;
 }
 
-extern "C" vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
-                                   const vdbc_render_params* r, float* image, float* aov, void* ws,
-                                   uint64_t ws_bytes, void* stream)
+static vdbc_status render_vdb(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
+                              const vdbc_render_params* r, float* image, float* aov, void* ws,
+                              uint64_t ws_bytes, void* stream)
 {
-    clear_error();
     VdbView v;
     vdbc_status s = make_view(g, &v);
     if (s) return s;
@@ -575,6 +574,14 @@ extern "C" vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, con
         return render_impl<VdbAccT<kCacheLeaf>, VdbView, false>(v, c, m, r, image, aov, ws, ws_bytes, stream);
     }
     return render_impl<VdbAcc>(v, c, m, r, image, aov, ws, ws_bytes, stream);
+}
+
+extern "C" vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
+                                   const vdbc_render_params* r, float* image, float* aov, void* ws,
+                                   uint64_t ws_bytes, void* stream)
+{
+    clear_error();
+    return render_vdb(g, c, m, r, image, aov, ws, ws_bytes, stream);
 }
 
 extern "C" vdbc_status vdbc_render_dense(const float* dense, vdbc_dims d, float background,

@@ -14,9 +14,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvdbc.so")
+ABI_VERSION = 2        # VDBC_ABI_VERSION of include/vdbc.h
 
 OK, E_INVALID, E_NOMEM, E_BUFFER_TOO_SMALL, E_FORMAT, E_DEVICE, E_UNSUPPORTED = range(7)
-BG_EXPLICIT, NO_CORNERS, NO_PRUNE = 1, 2, 4
+BG_EXPLICIT, NO_CORNERS, NO_PRUNE, PARTIAL = 1, 2, 4, 8
 MODE_EA, MODE_PT, MODE_ISO = 0, 1, 2
 RENDER_HDDA, RENDER_COUNT, RENDER_KEEP_MAJORANT, RENDER_RR = 1, 2, 4, 8
 RENDER_CACHE_NONE, RENDER_CACHE_LEAF = 16, 32
@@ -39,7 +40,8 @@ class Dims(C.Structure):
 
 class EncodeParams(C.Structure):
     _fields_ = [("rate", C.c_float), ("metric", C.c_uint32), ("flags", C.c_uint32),
-                ("background", C.c_float), ("threads", C.c_uint32)]
+                ("background", C.c_float), ("threads", C.c_uint32),
+                ("partial_fraction", C.c_float), ("partial_threshold", C.c_float)]
 
 
 class EncodeStats(C.Structure):
@@ -87,6 +89,16 @@ SYMBOLS = [
 _lib = None
 
 
+def _torch_hip_first():
+    """Imports torch before libvdbc.so is loaded.  The torch wheel carries its
+    own HIP runtime under the same soname (libamdhip64.so.7) as the ROCm one
+    the library is linked against: loaded after torch, the library binds to
+    torch's runtime; loaded first, the process ends up with two HIP runtimes,
+    and torch's memory and streams are unknown to the library's kernels (the
+    first launch fails with "no ROCm-capable device")."""
+    import torch  # noqa: F401
+
+
 def load():
     """Loads libvdbc.so (raises if it has not been built)."""
     global _lib
@@ -95,6 +107,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2504_04564_amd._build`")
+    _torch_hip_first()
     L = C.CDLL(LIB_PATH)
     P, u32, u64, f32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_float
     st = C.c_int
@@ -103,6 +116,9 @@ def load():
     L.vdbc_last_error.argtypes = []
     L.vdbc_last_error.restype = C.c_char_p
     L.vdbc_abi_version.restype = u32
+    if L.vdbc_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI version {L.vdbc_abi_version()}, the binding "
+                          f"expects {ABI_VERSION}: rebuild it")
     L.vdbc_encode_begin.argtypes = [P, Dims, C.POINTER(EncodeParams), C.POINTER(P),
                                     C.POINTER(u64), C.POINTER(EncodeStats)]
     L.vdbc_encode_finish.argtypes = [P, P, u64]
@@ -156,14 +172,20 @@ def _aligned(nbytes: int) -> np.ndarray:
 
 
 def encode(dense: np.ndarray, rate: float, metric: int = 2, flags: int = 0,
-           background: float = 0.0, threads: int = 0, layout: int = LAYOUT_V1):
+           background: float = 0.0, threads: int = 0, layout: int = LAYOUT_V1,
+           partial=None):
     """Encode a host float32 volume (nz, ny, nx) -> (uint8 buffer, stats);
-    a non-zero node layout is produced from the layout-0 buffer by relayout()."""
+    a non-zero node layout is produced from the layout-0 buffer by relayout().
+    `partial` = (fraction, threshold) selects partial-brick activation
+    (sets PARTIAL)."""
     L = load()
     d = np.ascontiguousarray(dense, dtype=np.float32)
     if d.ndim != 3:
         raise ValueError("dense must be 3-D (nz, ny, nx)")
-    p = EncodeParams(rate, metric, flags, background, threads)
+    pf, pt = (0.0, 0.0) if partial is None else partial
+    if partial is not None:
+        flags |= PARTIAL
+    p = EncodeParams(rate, metric, flags, background, threads, pf, pt)
     h = C.c_void_p()
     nbytes = C.c_uint64(0)
     st = EncodeStats()

@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol(lib):
     assert len(names) >= 18
     for n in sorted(names):
         assert hasattr(lib, n), n
-    assert lib.vdbc_abi_version() == 1
+    assert lib.vdbc_abi_version() == vdbc.ABI_VERSION == 2
 
 
 def test_library_records_its_sources_and_stale_builds_are_refused(lib, monkeypatch):
@@ -39,6 +39,21 @@ def test_library_records_its_sources_and_stale_builds_are_refused(lib, monkeypat
     monkeypatch.setattr(_build, "source_hash", lambda: "0" * 16)
     with pytest.raises(_build.StaleLibrary):
         _build.ensure_built()
+
+
+def test_one_hip_runtime_whatever_the_import_order():
+    # torch's wheel carries its own libamdhip64.so.7; loading the library
+    # before torch must not leave a second HIP runtime in the process
+    import subprocess
+    import sys
+    code = ("from paper_2504_04564_amd import _build, vdbc\n"
+            "_build.ensure_built(); vdbc.load()\n"
+            "m = open('/proc/self/maps').read()\n"
+            "print(len({l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l}))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "1"
 
 
 def _rand(shape, seed, zero=0.6):
@@ -67,6 +82,49 @@ def test_encoder_bytes_equal_oracle(shape, q, metric, flags):
     assert np.array_equal(b1, b2)
     assert s1 == s2
     assert vdbc.validate(b1)["n_leaf"] == s2["n_leaf"]
+
+
+PARTIAL_CASES = [
+    ((64, 96, 128), 0.25, 2, 0, (0.5, 1e30)), ((37, 50, 70), 0.3, 1, 0, (0.3, 0.6)),
+    ((37, 50, 70), 0.3, 3, 4, (0.7, 0.4)), ((130, 20, 140), 0.5, 2, 2, (0.25, 1e30)),
+    ((45, 70, 90), 1.0, 2, 0, (0.1, 1e30)), ((8, 200, 9), 0.6, 2, 0, (0.01, 1e30)),
+    ((1, 1, 1), 1.0, 2, 0, (0.5, 1e30)), ((40, 40, 40), 0.2, 2, 1, (0.5, 1e30)),
+    ((129, 257, 33), 0.07, 2, 0, (0.5, 0.99)), ((64, 64, 64), 0.3, 2, 0, (1.0, 1e30)),
+]
+
+
+@pytest.mark.parametrize("shape,q,metric,flags,part", PARTIAL_CASES)
+def test_partial_encoder_bytes_equal_oracle(shape, q, metric, flags, part):
+    # partial-brick activation: the host encoder writes the oracle's bytes
+    v = _rand(shape, 33)
+    v[: shape[0] // 2, : shape[1] // 2, : shape[2] // 2] = np.float32(0.75)
+    v[v > 0.9] = np.float32(0.95)   # ties in |v - B| inside bricks
+    bg = 0.5 if flags & 1 else 0.0
+    b1, s1 = vdbc.encode(v, q, metric, flags, bg, partial=part)
+    b2, s2 = oracle.encode(v, q, metric, flags, bg, partial=part)
+    assert b1.size == b2.size
+    assert np.array_equal(b1, b2)
+    assert s1 == s2
+    assert vdbc.validate(b1)["active_voxels"] == s2["active_voxels"]
+
+
+def test_partial_encoder_clouds_and_threads():
+    v = synth.mid_volume(n=160)
+    order, K = oracle.brick_order(v, 0.1)
+    for part in ((0.5, 1e30), (0.25, 0.5)):
+        b2, _ = oracle.encode(v, 0.1, partial=part)
+        for threads in (1, 3, 0):
+            b1, _ = vdbc.encode(v, 0.1, threads=threads, partial=part)
+            assert np.array_equal(b1, b2), (part, threads)
+
+
+def test_partial_encoder_rejects_bad_parameters():
+    v = _rand((32, 32, 32), 1)
+    for part in ((0.0, 1.0), (1.5, 1.0), (float("nan"), 1.0), (0.5, float("nan"))):
+        with pytest.raises(vdbc.VdbcError):
+            vdbc.encode(v, 0.5, partial=part)
+    with pytest.raises(vdbc.VdbcError):
+        vdbc.encode(v, 0.5, flags=64)
 
 
 def test_encoder_bytes_equal_oracle_clouds():

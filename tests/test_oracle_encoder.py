@@ -42,7 +42,7 @@ def test_background_negative_zero_and_ties():
 
 
 def test_background_sparse_volume_is_empty_space():
-    # "the value associated with most of the voxels becomes background"
+    # Section 3.1: the background is the value most voxels hold (empty space)
     assert oracle.background(synth.tiny_volume()) == 0.0
 
 
@@ -102,7 +102,7 @@ def test_k_closed_form_float_rates():
 
 @pytest.mark.parametrize("shape", [(64, 64, 64), (37, 50, 70), (1, 1, 1), (8, 8, 200)])
 def test_rate_one_is_lossless(shape):
-    # "In the latter case [1:1] the algorithm is guaranteed to be lossless"
+    # Section 5.1: at 1:1 the encoding loses nothing
     v = _rand_cloud(shape, 11)
     R = oracle.reconstruct(v, 1.0)
     assert np.array_equal(R.view(np.uint32), v.view(np.uint32))
@@ -266,7 +266,7 @@ def test_dense_noise_overhead_within_ten_percent():
 
 
 def test_achieved_rate_matches_target():
-    # "1:1 relationship between activated voxels and final output size"
+    # Section 3.2.1: output size grows one to one with the activated voxels
     v = synth.mid_volume(n=128)   # 64 bricks, ~45 non-background
     n = v.size
     for q in (0.05, 0.1, 0.25, 0.5):

@@ -1,6 +1,7 @@
 """Pins for the oracle's partial-brick activation, the variant Section 3.2.1
-leaves as future work ("activate half the number of voxels but twice the
-number of bricks").  The paper gives no rule for which voxels to keep; the
+leaves as future work (past a similarity threshold, a share of each brick's
+voxels in proportionally more bricks, e.g. half of them in twice as many
+bricks).  The paper gives no rule for which voxels to keep; the
 oracle's rule (fraction p, similarity threshold tau, voxels by |value - B|
 inside a brick) is checked here by what must hold for it whatever its code:
 the paper's own half/twice example, the exact voxel budget of plain Alg. 1,

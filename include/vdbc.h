@@ -300,6 +300,30 @@ vdbc_status vdbc_render_dense(const float* dense, vdbc_dims d, float background,
                               const vdbc_render_params* r, float* image, float* aov,
                               void* ws, uint64_t ws_bytes, void* stream);
 
+/* Bytes of the fixed device scratch that vdbc_render_noalloc uses. */
+#define VDBC_NOALLOC_SCRATCH_BYTES (16ull << 20)
+
+/* vdbc_render of a VDB without a caller workspace and without any device
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * workspace of vdbc_render is replaced by a fixed library-owned scratch of
+ * VDBC_NOALLOC_SCRATCH_BYTES (16 MiB) per GPU, held until the process ends:
+ * a path-traced frame whose vdbc_render_workspace exceeds it (e.g. the
+ * majorant grid of a 1987x1351x2449 volume at macrocell 8, 52 MB) is
+ * rejected with VDBC_E_BUFFER_TOO_SMALL before anything is enqueued; use
+ * vdbc_render with a workspace or a larger macrocell then.  Arguments,
+ * outputs and results are those of vdbc_render (bit-identical images), except
+ * that VDBC_RENDER_KEEP_MAJORANT is rejected (VDBC_E_INVALID: the scratch
+ * holds no majorant of the caller's).  Every call on one GPU shares its
+ * scratch and each call re-initialises what it reads (counters, queue,
+ * majorant, occupancy bits) on `stream`; calls that overlap on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller.  The sample counter (VDBC_RENDER_COUNT) stays in the scratch and
+ * is not readable by the caller. */
+vdbc_status vdbc_render_noalloc(const vdbc_grid* g, const vdbc_camera* c, const vdbc_medium* m,
+                                const vdbc_render_params* r, float* image, float* aov,
+                                void* stream);
+
 /* Majorant grid alone (Section 4 macrocells): out = device float32
  * ceil(n/macrocell)^3, x-fastest; per cell the extinction maximum over the
  * value range of voxels [C*c-1, C*c+C] (one-voxel dilation). */

@@ -2,6 +2,8 @@
 // emission-absorption and iso-surface marching, and the delta-tracking path
 // tracer (Section 4), each for the compressed VDB and for the dense float32
 // baseline through the same templated code, plus batched rendering.
+#include <mutex>
+
 #include "kcommon.h"
 #include "pt.h"
 
@@ -582,6 +584,62 @@ extern "C" vdbc_status vdbc_render(const vdbc_grid* g, const vdbc_camera* c, con
 {
     clear_error();
     return render_vdb(g, c, m, r, image, aov, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------- render without allocation
+
+// Fixed scratch of vdbc_render_noalloc: the render workspace (counters, tile
+// queue, majorant grid, coarse occupancy bits) of one call.  Every GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the symbol itself to a kernel: it takes the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr uint64_t kScratchBytes = VDBC_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+// Device address of `scratch` on the current device, resolved once per
+// device (with that device current) on its first call.
+static vdbc_status scratch_address(void** out)
+{
+    static std::mutex mu;
+    static void* addr[64] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(VDBC_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return fail(VDBC_E_UNSUPPORTED, "device index %d beyond 63", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(VDBC_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return VDBC_OK;
+}
+
+extern "C" vdbc_status vdbc_render_noalloc(const vdbc_grid* g, const vdbc_camera* c,
+                                           const vdbc_medium* m, const vdbc_render_params* r,
+                                           float* image, float* aov, void* stream)
+{
+    clear_error();
+    if (!g || !r) return fail(VDBC_E_INVALID, "null grid or params");
+    if (r->flags & VDBC_RENDER_KEEP_MAJORANT)
+        return fail(VDBC_E_INVALID, "VDBC_RENDER_KEEP_MAJORANT: the scratch holds no majorant of the caller's");
+    VdbView v;
+    vdbc_status s = make_view(g, &v);
+    if (s) return s;
+    vdbc_dims d{(uint32_t)v.nx, (uint32_t)v.ny, (uint32_t)v.nz};
+    uint64_t need = 0;
+    if ((s = vdbc_render_workspace(r, d, &need))) return s;
+    if (need > kScratchBytes)
+        return fail(VDBC_E_BUFFER_TOO_SMALL, "this render needs %llu bytes of scratch; the fixed scratch holds %llu "
+                    "(use vdbc_render with a workspace, or a larger macrocell)",
+                    (unsigned long long)need, (unsigned long long)kScratchBytes);
+    void* ws = nullptr;
+    if ((s = scratch_address(&ws))) return s;
+    return render_vdb(g, c, m, r, image, aov, ws, kScratchBytes, stream);
 }
 
 extern "C" vdbc_status vdbc_render_dense(const float* dense, vdbc_dims d, float background,

@@ -139,13 +139,15 @@ def load():
                               C.POINTER(RenderParamsC), P, P, P, u64, P]
     L.vdbc_render_dense.argtypes = [P, Dims, f32, C.POINTER(CameraC), C.POINTER(MediumC),
                                     C.POINTER(RenderParamsC), P, P, P, u64, P]
+    L.vdbc_render_noalloc.argtypes = [C.POINTER(GridC), C.POINTER(CameraC), C.POINTER(MediumC),
+                                      C.POINTER(RenderParamsC), P, P, P]
     L.vdbc_majorant.argtypes = [C.POINTER(GridC), C.POINTER(MediumC), u32, P, P]
     L.vdbc_majorant_dense.argtypes = [P, Dims, f32, C.POINTER(MediumC), u32, P, P]
     L.vdbc_philox.argtypes = [P, P, u64, P, P]
     for name in ["vdbc_encode_begin", "vdbc_encode_finish", "vdbc_encode", "vdbc_validate", "vdbc_relayout",
                  "vdbc_grid_init", "vdbc_sample", "vdbc_sample_dense", "vdbc_lookup",
-                 "vdbc_render_workspace", "vdbc_render", "vdbc_render_dense", "vdbc_majorant",
-                 "vdbc_majorant_dense", "vdbc_philox"]:
+                 "vdbc_render_workspace", "vdbc_render", "vdbc_render_dense", "vdbc_render_noalloc",
+                 "vdbc_majorant", "vdbc_majorant_dense", "vdbc_philox"]:
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -442,6 +444,25 @@ def render(field, camera: dict, medium: dict, params: dict, mode: int,
     r = Renderer(field, camera, medium, params, mode, background, aov)
     img = r.launch()
     return (img, r.aov) if aov else img
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def render_noalloc(grid: Grid, camera: dict, medium: dict, params: dict, mode: int,
+                   image=None, aov=None, stream=None):
+    """vdbc_render_noalloc: the render of a VDB into caller-owned outputs
+    (allocated here only when not given) with the library's fixed scratch
+    instead of a workspace."""
+    torch = _torch()
+    h, w = camera["height"], camera["width"]
+    if image is None:
+        image = torch.empty((h, w, 4), dtype=torch.float32, device="cuda")
+    cam, med, prm = camera_c(camera), (medium_c(medium) if medium else MediumC()), params_c(params, mode)
+    s = stream if stream is not None else _stream()
+    _check(load().vdbc_render_noalloc(C.byref(grid.c), C.byref(cam), C.byref(med), C.byref(prm),
+                                      _dptr(image), _dptr(aov) if aov is not None else None, s))
+    return image
 
 
 def majorant(field, medium: dict, macrocell: int = 8, background: float | None = None):

@@ -1,0 +1,77 @@
+"""vdbc_render_noalloc, the render entry point that allocates nothing (its
+workspace is the library's fixed per-GPU scratch), against vdbc_render with a
+caller workspace: bit-identical images and AOVs on consecutive calls that
+share the scratch, the second with a smaller volume, image and majorant grid;
+and the host-side refusal of frames whose workspace exceeds the scratch."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2504_04564_amd import _build, vdbc
+from synth import scenes
+
+
+@pytest.fixture(scope="module")
+def lib():
+    _build.ensure_built()
+    return vdbc.load()
+
+
+def _case(n, w, h, q, macrocell, spp, seed):
+    v = synth.mid_volume(n=n)
+    g = vdbc.Grid(vdbc.encode(v, q)[0])
+    cam = scenes.orbit_camera((n, n, n), w, h)
+    med = scenes.pt_medium_tf5(64.0)
+    prm = dict(spp=spp, max_bounces=8, seed=seed, macrocell=macrocell)
+    return g, cam, med, prm
+
+
+@pytest.mark.gpu
+def test_noalloc_render_equals_workspace_render_on_consecutive_calls(lib):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    big = _case(96, 64, 48, 0.10, 8, 4, 11)     # 12^3 majorant cells
+    small = _case(40, 24, 20, 0.25, 16, 2, 12)  # 3^3 majorant cells, smaller image
+    want = [vdbc.render(g, cam, med, prm, vdbc.MODE_PT, aov=True) for g, cam, med, prm in (big, small)]
+    torch.cuda.synchronize()
+    for (g, cam, med, prm), (wi, wa) in zip((big, small), want):
+        aov = torch.full_like(wa, -7.0)
+        got = vdbc.render_noalloc(g, cam, med, prm, vdbc.MODE_PT, aov=aov)
+        torch.cuda.synchronize()
+        assert torch.equal(got, wi)
+        assert torch.equal(aov, wa)
+        assert float(wi[..., 3].max()) > 0.0        # the frame shows the medium
+    # the emission-absorption marcher through the same scratch (sample
+    # counter on), after the path tracer left its majorant there
+    g, cam, med, _ = small
+    ea = dict(step=0.5, flags=vdbc.RENDER_COUNT)
+    want_ea = vdbc.render(g, cam, scenes.ea_medium(8.0), ea, vdbc.MODE_EA)
+    got_ea = vdbc.render_noalloc(g, cam, scenes.ea_medium(8.0), ea, vdbc.MODE_EA)
+    torch.cuda.synchronize()
+    assert torch.equal(got_ea, want_ea)
+
+
+def test_noalloc_refuses_what_the_scratch_cannot_hold(lib):
+    # every check fails before any HIP call, so this runs without a GPU
+    nx, ny, nz = 4096, 4096, 17                  # 1024 x 1024 x 5 cells at macrocell 4
+    z = np.zeros((nz, ny, nx), np.float32)
+    buf, _ = vdbc.encode(z, 0.5)
+    g = vdbc.GridC()
+    assert lib.vdbc_grid_init(C.byref(g), 512, buf.size, buf.ctypes.data) == vdbc.OK
+    cam = vdbc.camera_c(dict(kind=0, width=4, height=4, dir=(0, 0, 1)))
+    med = vdbc.medium_c(scenes.pt_medium(8.0))
+    prm = vdbc.params_c(dict(spp=1, macrocell=4), vdbc.MODE_PT)
+    ws = C.c_uint64(0)
+    assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(nx, ny, nz), C.byref(ws)) == 0
+    assert ws.value > vdbc.NOALLOC_SCRATCH_BYTES
+    assert lib.vdbc_render_noalloc(C.byref(g), C.byref(cam), C.byref(med), C.byref(prm), 4096,
+                                   None, None) == vdbc.E_BUFFER_TOO_SMALL
+    assert b"fixed scratch" in lib.vdbc_last_error()
+    # the caller's majorant cannot be kept: the scratch holds none of it
+    keep = vdbc.params_c(dict(spp=1, macrocell=64, flags=vdbc.RENDER_KEEP_MAJORANT), vdbc.MODE_PT)
+    assert lib.vdbc_render_noalloc(C.byref(g), C.byref(cam), C.byref(med), C.byref(keep), 4096,
+                                   None, None) == vdbc.E_INVALID
+    assert lib.vdbc_render_noalloc(None, C.byref(cam), C.byref(med), C.byref(prm), 4096,
+                                   None, None) == vdbc.E_INVALID

@@ -147,28 +147,33 @@ def loss_grad(out, target):
     return 2.0 * (out - t) / (t * t + 0.01) / out.size
 
 
-def backward(params, x, target):
+def backward(params, x, target, bf16_grads: bool = False):
     """Loss and the gradient of every parameter (flat float64 vector) of the
     network whose forward pass uses the BF16-rounded weights and activations;
-    the gradient itself is exact (float64, no rounding)."""
+    the gradient itself is exact (float64, no rounding).  With bf16_grads the
+    gradient with respect to each convolution's output (after the ReLU
+    mask) is rounded to BF16 before it is propagated further, the precision
+    in which a BF16 training step stores these tensors; everything else stays
+    float64."""
     W, b = unpack(params)
     Wq = {k: bf16(v) for k, v in W.items()}
     out, a = forward(params, x)
     L = loss(out, target)
+    q = bf16 if bf16_grads else (lambda v: v)
     g = {}
-    d6 = loss_grad(out, target)
+    d6 = q(loss_grad(out, target))
     g["c6"] = conv_wgrad(a["c5"], d6)
-    d5 = conv_dgrad(d6, Wq["c6"], a["c5"].shape) * (a["c5"] > 0)
+    d5 = q(conv_dgrad(d6, Wq["c6"], a["c5"].shape) * (a["c5"] > 0))
     g["c5"] = conv_wgrad(a["cat"], d5)
     dcat = conv_dgrad(d5, Wq["c5"], a["cat"].shape)
     d1 = dcat[..., :32]
-    d4 = dcat[..., 32:] * (a["c4"] > 0)
+    d4 = q(dcat[..., 32:] * (a["c4"] > 0))
     g["c4"] = conv_wgrad(a["u3"], d4)
-    d3 = up2_backward(conv_dgrad(d4, Wq["c4"], a["u3"].shape)) * (a["c3"] > 0)
+    d3 = q(up2_backward(conv_dgrad(d4, Wq["c4"], a["u3"].shape)) * (a["c3"] > 0))
     g["c3"] = conv_wgrad(a["c2"], d3)
-    d2 = conv_dgrad(d3, Wq["c3"], a["c2"].shape) * (a["c2"] > 0)
+    d2 = q(conv_dgrad(d3, Wq["c3"], a["c2"].shape) * (a["c2"] > 0))
     g["c2"] = conv_wgrad(a["c1"], d2, 2)
-    d1 = (d1 + conv_dgrad(d2, Wq["c2"], a["c1"].shape, 2)) * (a["c1"] > 0)
+    d1 = q((d1 + conv_dgrad(d2, Wq["c2"], a["c1"].shape, 2)) * (a["c1"] > 0))
     g["c1"] = conv_wgrad(a["x"], d1)
     lay, total = param_layout()
     grad = np.zeros(total)

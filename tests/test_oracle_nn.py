@@ -112,3 +112,54 @@ def test_adam_first_step_is_signed_lr():
         opt.step()
     p2, m2, v2 = nn.adam_step(new, g * 0.5 + 0.1, m, v, 2, 0.01)
     np.testing.assert_allclose(p2, pt.detach().numpy(), rtol=1e-12)
+
+
+def _torch_bf16(t):
+    return t.to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_gradient_option_matches_autograd_with_rounding_hooks():
+    # the option that rounds every inter-layer gradient to BF16, against
+    # torch's autograd of the same float64 network: activations rounded to
+    # BF16 in the forward pass with an identity gradient, and a hook rounding
+    # the gradient of each convolution's output (pre-activation) to BF16
+    rng = np.random.default_rng(6)
+    params = nn.init_params(7).astype(np.float64)
+    params[nn.param_layout()[0]["c6"][0]:] *= 10
+    x = nn.bf16(rng.uniform(0, 1, size=(2, 8, 12, 8)))
+    x[..., 5:] = 0
+    t = rng.uniform(0, 1, size=(2, 8, 12, 3))
+    L, g = nn.backward(params, x, t, bf16_grads=True)
+    W, b = nn.unpack(params)
+    Wt = {k: _torch_bf16(_t(v).permute(0, 3, 1, 2)).requires_grad_(True) for k, v in W.items()}
+    bt = {k: _t(v).requires_grad_(True) for k, v in b.items()}
+
+    def conv(a, name, stride=1, relu=True):
+        y = torch.nn.functional.conv2d(a, Wt[name], bt[name], stride=stride, padding=1)
+        y.register_hook(_torch_bf16)
+        if not relu:
+            return y
+        r = torch.relu(y)
+        return r + (_torch_bf16(r) - r).detach()     # rounded value, identity gradient
+
+    xt = _t(x).permute(0, 3, 1, 2)
+    c1 = conv(xt, "c1")
+    c2 = conv(c1, "c2", 2)
+    c3 = conv(c2, "c3")
+    c4 = conv(torch.repeat_interleave(torch.repeat_interleave(c3, 2, 2), 2, 3), "c4")
+    c5 = conv(torch.cat([c1, c4], 1), "c5")
+    out = xt[:, :3] + conv(c5, "c6", relu=False)
+    tt = _t(t).permute(0, 3, 1, 2)
+    Lt = torch.mean((out - tt) ** 2 / (tt * tt + 0.01))
+    Lt.backward()
+    assert L == pytest.approx(Lt.item(), rel=1e-12)
+    lay, _ = nn.param_layout()
+    for name, (ow, ob, cin, cout) in lay.items():
+        gw = Wt[name].grad.permute(0, 2, 3, 1).numpy().ravel()
+        np.testing.assert_allclose(g[ow:ob], gw, rtol=1e-9, atol=1e-12 * np.abs(gw).max())
+        np.testing.assert_allclose(g[ob:ob + cout], bt[name].grad.numpy(), rtol=1e-9,
+                                   atol=1e-12 * np.abs(gw).max())
+    # and the rounding moves the gradient by no more than BF16 precision allows
+    _, g_exact = nn.backward(params, x, t)
+    assert np.linalg.norm(g - g_exact) <= 2e-2 * np.linalg.norm(g_exact)
+    assert not np.array_equal(g, g_exact)

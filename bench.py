@@ -33,6 +33,13 @@ BYTES_PER_RENDER_SAMPLE = 32      # 8 float32 corners of one trilinear sample
 BYTES_PER_RANDOM_SAMPLE = 48      # + 12 B position + 4 B result (vdbc_sample)
 BRICK = 32                        # brick edge of the encoder (Alg. 1)
 
+# majorant cell edge of each frame: the fastest candidate of the render
+# autotuner (--workload tune --tune-frame paper / mid) for both the VDB and
+# the dense array
+DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16}
+# wave tile width (pixels per wave row) of each frame, the same autotuner's
+# choice; the image does not depend on it
+DEFAULT_TILE_W = {"paper": 32, "mid": 8}
 # committed rocprofv3 counter summaries of pt_kernel<VdbAcc>, one per frame
 PROFILES = {"paper": os.path.join(ROOT, "profiles", "pt_kernel_vdb_paper_1to10.md"),
             "mid": os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")}
@@ -62,10 +69,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def profile_values(path: str | None = None):
+def profile_values(path: str | None = None, launch: str | None = None):
     """Figures of a committed rocprofv3 counter summary of the PT kernel (HBM
     bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the kernel
-    sources changed since the counters were taken."""
+    sources changed since the counters were taken or (with `launch`, e.g.
+    "macrocell=64 tile_w=32") the summary describes another launch."""
     path = path or PROFILE
     if not os.path.exists(path):
         return {}
@@ -75,6 +83,8 @@ def profile_values(path: str | None = None):
             k, _, v = line.partition(":")
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != kernel_source_hash():
+        return {}
+    if launch is not None and vals.get("launch") != launch:
         return {}
     try:
         return {"traffic": int(float(vals["traffic_bytes_per_launch"])),
@@ -198,7 +208,8 @@ def oracle_baseline(fld, cam, med, prm, img, W, H, spp, pixels, threads, cpu):
     maj_wall = time.time() - t
     log(f"[bench] oracle majorant: {maj_wall:.1f}s on {threads} threads ({maj_cpu:.1f} core-s)")
     rng = np.random.default_rng(52)
-    pix_all = np.sort(rng.choice(W * H, pixels * (threads + 1), replace=False)).astype(np.uint32)
+    n_all = min(pixels * (threads + 1), W * H)   # at most every pixel once
+    pix_all = np.sort(rng.choice(W * H, n_all, replace=False)).astype(np.uint32)
     pix1 = pix_all[::threads + 1]
     rest = np.setdiff1d(pix_all, pix1)
     t = time.time()
@@ -251,13 +262,20 @@ def main():
                          "(default: the cores this process may use)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the dense renderer and the random-sample microbenchmark")
-    ap.add_argument("--macrocell", type=int, default=16, help="majorant cell edge in voxels")
+    ap.add_argument("--macrocell", type=int, default=None,
+                    help="majorant cell edge in voxels (default: the render autotuner's choice for the "
+                         "workload's frame, 64 for the paper-scale frame, 16 for the 512^3 one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (scales the HBM byte counters)")
     ap.add_argument("--train-steps", type=int, default=1500, help="denoiser workload: Adam steps")
     ap.add_argument("--denoiser-full", action="store_true",
                     help="denoiser workload: 1,000 crops of 512^2 with 1024-spp targets from 256^3..512^3 "
                          "clouds (about 14 minutes) instead of 96 crops of 256^2 with 512-spp targets")
+    ap.add_argument("--denoiser-part", type=int, default=0, choices=(0, 1, 2),
+                    help="with --denoiser-full: 1 = crops of volumes 0..49, train, write the "
+                         "checkpoint; 2 = resume from it with the crops of volumes 50..99")
+    ap.add_argument("--denoiser-ckpt", default="denoiser_ckpt.npz",
+                    help="checkpoint file of --denoiser-part")
     ap.add_argument("--workload", default="paper",
                     choices=("paper", "mid", "sweep", "denoiser", "batch", "quality", "worstcase",
                              "iso", "ea", "tune"),
@@ -271,6 +289,8 @@ def main():
                     help="paper/mid frame: file holding the encoded buffer.  Written after "
                          "encoding; with --no-extras an existing file is read instead of "
                          "generating and encoding the volume (profiling passes)")
+    ap.add_argument("--tune-frame", default="mid", choices=("mid", "paper"),
+                    help="tune workload: the frame whose launch configuration is searched")
     ap.add_argument("--worst-max", type=int, default=1024,
                     help="worstcase workload: largest noise cube edge (2048 = the paper's 34 GB)")
     args = ap.parse_args()
@@ -302,6 +322,8 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
                           "launches": 3}))
         return
+    if args.macrocell is None:
+        args.macrocell = DEFAULT_MACROCELL.get(args.workload, 16)
     if args.workload not in ("paper", "mid"):
         import bench_workloads
         line = getattr(bench_workloads, args.workload)(args, torch, vdbc, synth, scenes, log)
@@ -363,6 +385,7 @@ def main():
     med = scenes.pt_medium(64.0)
     C = args.macrocell
     prm = dict(spp=spp, max_bounces=bounces, seed=S["seed"], macrocell=C,
+               tile_w=DEFAULT_TILE_W[args.workload],
                flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
     rays = W * H * spp
 
@@ -449,8 +472,9 @@ def main():
 
     pt_s = pt_ms * 1e-3
     prof_path = PROFILES[args.workload]
-    standard = (args.rate == 0.10 and C == 16 and (args.workload == "paper" or nx == 512))
-    prof = profile_values(prof_path) if standard else {}
+    standard = (args.rate == 0.10 and C == DEFAULT_MACROCELL[args.workload] and
+                (args.workload == "paper" or nx == 512))
+    prof = profile_values(prof_path, f"macrocell={C} tile_w={prm['tile_w']}") if standard else {}
     achieved = samples * BYTES_PER_RENDER_SAMPLE / pt_s / 1e9
     line = {
         "metric": METRIC,
@@ -469,7 +493,7 @@ def main():
             "workload": f"{name}-vdb-1:{round(1 / args.rate)}-pt-{W}x{H}x{spp}spp-"
                         f"{bounces}bounces",
             "dims": list(dims), "rate": args.rate, "width": W, "height": H, "spp": spp,
-            "max_bounces": bounces, "macrocell": C,
+            "max_bounces": bounces, "macrocell": C, "tile_w": prm["tile_w"],
             "vdb_bytes": int(buf.size), "dense_bytes": vol_bytes,
             "achieved_rate": round(st["achieved_rate"], 5),
         },

@@ -39,12 +39,12 @@ def sweep(args, torch, vdbc, synth, scenes, log):
     C = args.macrocell
     cam = scenes.orbit_camera((nx, ny, nz), W, H)
     med = scenes.pt_medium(64.0)
-    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C,
+    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C, tile_w=32,
                flags=vdbc.RENDER_COUNT)
     rays = W * H * spp
     out = {"metric": "paper-scale VDB vs dense path-traced Mrays/s", "unit": "Mrays/s",
            "config": {"workload": "fbm-cloud-1987x1351x2449-pt-1920x1080x64spp-16bounces",
-                      "dims": list(P["dims"]), "macrocell": C}, "rates": []}
+                      "dims": list(P["dims"]), "macrocell": C, "tile_w": 32}, "rates": []}
     for q in P["rates"]:
         t = time.time()
         buf, st = vdbc.encode(vol, q)
@@ -82,18 +82,29 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
     reference."""
     from paper_2504_04564_amd import denoiser as dz
     rng = np.random.default_rng(1000)
+    part = args.denoiser_part
+    vols = None
     if args.denoiser_full:
-        # the recipe's crops (512^2 from 256^3..512^3 clouds, 1024-spp targets),
-        # 1,000 of them: rendering the 2,000 of the recipe takes ~26 min of GPU
-        # time at 0.77 s per crop, beyond a 20-minute run
-        n_vol, views, size, spp_tgt, lo, hi = 50, 20, 512, 1024, 256, 512
+        # the recipe's crops (512^2 from 256^3..512^3 clouds, 1024-spp targets).
+        # Rendering its 2,000 crops takes ~26 min of GPU time at 0.77 s per
+        # crop, beyond one 20-minute run: --denoiser-part 1 renders the crops
+        # of volumes 0..49, trains and writes a checkpoint (parameters, Adam
+        # moments, step); --denoiser-part 2 resumes from it with the crops of
+        # volumes 50..99
+        n_vol, views, size, spp_tgt, lo, hi = 100 if part else 50, 20, 512, 1024, 256, 512
+        if part:
+            vols = range(0, 50) if part == 1 else range(50, 100)
     else:
         n_vol, views, size, spp_tgt, lo, hi = 16, 6, 256, 512, 128, 256
+    if vols is None:
+        vols = range(n_vol)
     spp_in = 4
     med = scenes.pt_medium(64.0)
     xs, ts = [], []
     t = time.time()
     sides = [int(rng.integers(lo, hi + 1)) for _ in range(n_vol)]
+    # camera draws per volume, so a part renders the same crops as a full run
+    cam_rng = {i: np.random.default_rng([1000, i]) for i in vols} if part else None
 
     def make(i):
         # host side of one training volume: generate and encode (overlaps the
@@ -103,18 +114,20 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
 
     from concurrent.futures import ThreadPoolExecutor
     pool = ThreadPoolExecutor(max_workers=2)
-    pending = [pool.submit(make, i) for i in range(min(2, n_vol))]
-    for i in range(n_vol):
-        if args.denoiser_full and i % 10 == 0:
-            log(f"[denoiser] volume {i}/{n_vol}, {len(xs)} crops, {time.time() - t:.0f}s")
+    order = list(vols)
+    pending = [pool.submit(make, i) for i in order[:2]]
+    for j, i in enumerate(order):
+        if args.denoiser_full and j % 10 == 0:
+            log(f"[denoiser] volume {i} ({j}/{len(order)}), {len(xs)} crops, {time.time() - t:.0f}s")
         buf = pending.pop(0).result()
-        if i + 2 < n_vol:
-            pending.append(pool.submit(make, i + 2))
+        if j + 2 < len(order):
+            pending.append(pool.submit(make, order[j + 2]))
         g = vdbc.Grid(buf)
+        r = cam_rng[i] if cam_rng else rng
         for k in range(views):
-            cam = scenes.orbit_camera(g.dims, size, size, azimuth_deg=float(rng.uniform(0, 360)),
-                                      elevation_deg=float(rng.uniform(-30, 45)),
-                                      distance=float(rng.uniform(1.2, 2.0)))
+            cam = scenes.orbit_camera(g.dims, size, size, azimuth_deg=float(r.uniform(0, 360)),
+                                      elevation_deg=float(r.uniform(-30, 45)),
+                                      distance=float(r.uniform(1.2, 2.0)))
             x, ref = dz.render_pair(g, cam, med, spp_in, spp_tgt, seed=7919 * i + k)
             xs.append(x)
             ts.append(ref)
@@ -124,12 +137,25 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
     X = torch.stack(xs)
     T = torch.stack(ts)
     log(f"[denoiser] {X.shape[0]} training crops of {size}^2 in {gen_s:.1f}s")
-    dn = vdbc.Denoiser(seed=5)
     steps, batch = args.train_steps, 8
+    if part == 2:
+        ck = np.load(args.denoiser_ckpt)
+        dn = vdbc.Denoiser(params=ck["params"])
+        dn.m.copy_(torch.from_numpy(ck["m"]))
+        dn.v.copy_(torch.from_numpy(ck["v"]))
+        dn.step = int(ck["step"])
+        log(f"[denoiser] resumed from {args.denoiser_ckpt} at step {dn.step}")
+    else:
+        dn = vdbc.Denoiser(seed=5)
     t = time.time()
-    losses = dz.train(dn, X, T, steps=steps, batch=batch, lr=1e-3, seed=1, log_every=200)
+    losses = dz.train(dn, X, T, steps=steps, batch=batch, lr=1e-3, seed=part or 1, log_every=200)
     torch.cuda.synchronize()
     train_s = time.time() - t
+    if part == 1:
+        np.savez(args.denoiser_ckpt, params=dn.params.cpu().numpy(), m=dn.m.cpu().numpy(),
+                 v=dn.v.cpu().numpy(), step=dn.step)
+        log(f"[denoiser] checkpoint at step {dn.step} written to {args.denoiser_ckpt}")
+    del X, T, xs, ts
     evals = []
     for j in range(3):
         side = 384
@@ -144,9 +170,11 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
     mean = {k: float(np.mean([e[k] for e in evals])) for k in keys}
     return {"metric": "denoised 4-spp relMSE vs plain 64-spp relMSE (1024-spp reference)",
             "value": mean["relmse_denoised"], "unit": "relMSE", "higher_is_better": False,
-            "config": {"workload": f"{n_vol}x{views} crops {size}^2 of {lo}^3..{hi}^3 clouds at 1:10,"
+            "config": {"workload": f"{len(order)}x{views} crops {size}^2 of {lo}^3..{hi}^3 clouds at 1:10,"
                                    f" targets {spp_tgt} spp, eval 3 clouds 384^3 at 512^2",
-                       "train_steps": steps, "batch": batch, "lr": 1e-3},
+                       "train_steps": steps, "batch": batch, "lr": 1e-3,
+                       "part": part, "volumes": [order[0], order[-1]],
+                       "total_steps": dn.step},
             "train_s": round(train_s, 2), "gen_s": round(gen_s, 2),
             "ms_per_train_step": round(train_s / steps * 1e3, 3),
             "loss_first": float(losses[0]), "loss_last": float(np.mean(losses[-20:])),
@@ -284,7 +312,15 @@ def worstcase(args, torch, vdbc, synth, scenes, log):
     while n <= args.worst_max:
         t = time.time()
         vol = synth.dense_noise(n, seed=n)
-        buf, st = vdbc.encode(vol, 1.0)
+        log(f"[worstcase] {n}^3 generated in {time.time() - t:.1f}s, encoding")
+        t = time.time()
+        if n >= 2048:
+            # white noise has no dominant value: the exact mode of 8.6e9
+            # values would need a 34 GB sort, and at 1:1 every voxel is kept
+            # whatever the background, so it is given (0) instead
+            buf, st = vdbc.encode(vol, 1.0, flags=vdbc.BG_EXPLICIT, background=0.0)
+        else:
+            buf, st = vdbc.encode(vol, 1.0)
         enc = time.time() - t
         g = vdbc.Grid(buf)
         dense = torch.from_numpy(vol).cuda()
@@ -297,6 +333,7 @@ def worstcase(args, torch, vdbc, synth, scenes, log):
         ms_d = _median_ms(torch, rd.launch, 3)
         same = bool(torch.equal(rv.image.view(torch.int32), rd.image.view(torch.int32)))
         rec = {"n": n, "dense_bytes": n ** 3 * 4, "vdb_bytes": int(buf.size),
+               "background": "explicit 0" if n >= 2048 else "exact mode",
                "overhead": round(buf.size / (n ** 3 * 4) - 1.0, 5), "encode_s": round(enc, 2),
                "vdb_fps": round(1e3 / ms_v, 2), "dense_fps": round(1e3 / ms_d, 2),
                "vdb_over_dense": round(ms_d / ms_v, 4), "images_bitwise_equal": same}
@@ -374,23 +411,34 @@ def ea(args, torch, vdbc, synth, scenes, log):
 
 
 def tune(args, torch, vdbc, synth, scenes, log):
-    """The render autotuner on the headline frame (512^3 cloud at 1:10,
-    1024^2 x 16 spp, <= 8 bounces): every (macrocell, wave tile, accessor
-    cache policy) candidate timed, the fastest kept."""
+    """The render autotuner on a headline frame: every (macrocell, wave tile,
+    accessor cache policy) candidate timed, the fastest kept.  --tune-frame
+    mid: the 512^3 cloud at 1:10, 1024^2 x 16 spp, <= 8 bounces; paper: the
+    1987x1351x2449 cloud at 1:10, 1920x1080 x 64 spp, <= 16 bounces."""
     from paper_2504_04564_amd import autotune
-    n = args.size
-    M = scenes.MID
-    vol = synth.mid_volume(n=n)
+    if args.tune_frame == "paper":
+        S = scenes.PAPER
+        dims = S["dims"]
+        vol = synth.paper_volume(dims=dims)
+        name = f"fbm-cloud-{dims[0]}x{dims[1]}x{dims[2]}-billowed"
+    else:
+        S = scenes.MID
+        n = args.size
+        dims = (n, n, n)
+        vol = synth.mid_volume(n=n)
+        name = f"fbm-cloud-{n}^3"
     buf, _ = vdbc.encode(vol, args.rate)
+    del vol
     g = vdbc.Grid(buf)
-    cam = scenes.orbit_camera((n, n, n), M["width"], M["height"])
+    cam = scenes.orbit_camera(dims, S["width"], S["height"])
     med = scenes.pt_medium(64.0)
-    prm = dict(spp=M["spp"], max_bounces=M["max_bounces"], seed=M["seed"])
+    prm = dict(spp=S["spp"], max_bounces=S["max_bounces"], seed=S["seed"])
     best, rows = autotune.tune_render(g, cam, med, prm, reps=5)
     for r in sorted(rows, key=lambda x: x["ms"]):
         log(f"[tune] {r}")
     return {"metric": "render autotuner: fastest PT launch configuration", "unit": "ms",
             "value": round(best["ms"], 3), "higher_is_better": False,
-            "config": {"workload": f"fbm-cloud-{n}^3-1to10-pt-1024x1024x16spp-8bounces",
+            "config": {"workload": f"{name}-1to{round(1 / args.rate)}-pt-{S['width']}x{S['height']}x"
+                                   f"{S['spp']}spp-{S['max_bounces']}bounces",
                        "space": {k: list(v) for k, v in autotune.RENDER_SPACE.items()}},
             "best": best, "candidates": rows}

@@ -475,17 +475,19 @@ def test_pt_mid_config_sampled_pixels():
     assert np.all(np.isfinite(img))
 
 
-def test_pt_paper_launch_configuration_sampled_pixels():
-    # the paper-scale launch (1920x1080, 64 spp, <= 16 bounces, macrocell 16,
-    # 1:10) on the same billowed recipe at 1/8 of the edge lengths; the oracle
-    # renders a sample of the pixels one by one
+@pytest.mark.parametrize("C,tw", [(16, 8), (64, 32)])
+def test_pt_paper_launch_configuration_sampled_pixels(C, tw):
+    # the paper-scale launch (1920x1080, 64 spp, <= 16 bounces, 1:10; the
+    # benchmark's macrocell 64 and 32-wide wave tiles, and macrocell 16) on
+    # the same billowed recipe at 1/8 of the edge lengths; the oracle renders
+    # a sample of the pixels one by one
     P = scenes.PAPER
     dims = tuple(d // 8 for d in P["dims"])
     v = synth.paper_volume(dims=dims)
     buf, _ = vdbc.encode(v, 0.10)
     cam = scenes.orbit_camera(dims, P["width"], P["height"])
     med = scenes.pt_medium(64.0)
-    prm = dict(spp=P["spp"], max_bounces=P["max_bounces"], seed=P["seed"], macrocell=16)
+    prm = dict(spp=P["spp"], max_bounces=P["max_bounces"], seed=P["seed"], macrocell=C, tile_w=tw)
     img = vdbc.render(vdbc.Grid(buf), cam, med, prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
     rng = np.random.default_rng(53)
     pix = np.sort(rng.choice(P["width"] * P["height"], 1024, replace=False)).astype(np.uint32)

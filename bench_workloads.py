@@ -117,7 +117,7 @@ def denoiser(args, torch, vdbc, synth, scenes, log):
     order = list(vols)
     pending = [pool.submit(make, i) for i in order[:2]]
     for j, i in enumerate(order):
-        if args.denoiser_full and j % 10 == 0:
+        if args.denoiser_full and j % 5 == 0:
             log(f"[denoiser] volume {i} ({j}/{len(order)}), {len(xs)} crops, {time.time() - t:.0f}s")
         buf = pending.pop(0).result()
         if j + 2 < len(order):

@@ -169,12 +169,29 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
 // an integer output position.  dz has channel stride coutp (multiple of 8),
 // Wt is the transposed weight [cin][9][coutp].  A wave computes MB tiles of
 // 16 input pixels x NT tiles of 16 channels, as the forward kernel.
+// Where the data gradient goes.  Channels [0, split) are written (or added,
+// with `accumulate`) as FP32 to dx with dx_stride channels per pixel.
+// Channels [split, cin) are the backward of the ReLU that produced the
+// layer's input: dz[q][c - split] = BF16((dx + add) * (y > 0)), with `add`
+// an optional FP32 gradient of the same activation from another branch;
+// this is the whole input of the next layer's backward, so no FP32 copy of
+// those channels is written.
+struct DgradOut {
+    float* dx;
+    int dx_stride, accumulate, split;
+    uint16_t* dz;
+    int dz_stride;
+    const uint16_t* y;
+    int y_stride;
+    const float* add;
+    int add_stride;
+};
+
 template <int NT, int MB>
 __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __restrict__ dz, int coutp,
                                                               int n_img, int ho, int wo,
                                                               const uint16_t* __restrict__ wt, int cin,
-                                                              int stride, int hv, int wv,
-                                                              float* __restrict__ dx, int accumulate)
+                                                              int stride, int hv, int wv, DgradOut o)
 {
     const int K = 9 * coutp;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
@@ -230,8 +247,16 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __
             for (int i = 0; i < 4; ++i) {
                 const int64_t qq = q0 + 16 * m + 4 * g + i;
                 if (qq >= Q) continue;
-                float* o = dx + qq * cin + c;
-                *o = accumulate ? *o + acc[m][t][i] : acc[m][t][i];
+                float v = acc[m][t][i];
+                if (c < o.split) {
+                    float* d = o.dx + qq * o.dx_stride + c;
+                    *d = o.accumulate ? *d + v : v;
+                } else {
+                    const int cc = c - o.split;
+                    if (o.add) v += o.add[qq * o.add_stride + cc];
+                    if (!(bf2f(o.y[qq * o.y_stride + cc]) > 0.0f)) v = 0.0f;
+                    o.dz[qq * o.dz_stride + cc] = f2bf(v);
+                }
             }
     }
 }
@@ -562,8 +587,17 @@ vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const floa
     return check("conv3x3 forward");
 }
 
+// Every channel as FP32 (stride `cin`).
+DgradOut fp32_out(float* dx, int cin) { return DgradOut{dx, cin, 0, cin, nullptr, 0, nullptr, 0, nullptr, 0}; }
+// Channels [split, cin) through the ReLU backward into BF16 dz (see DgradOut).
+DgradOut relu_out(float* dx, int split, uint16_t* dz, int dz_stride, const uint16_t* y, int y_stride,
+                  const float* add = nullptr, int add_stride = 0)
+{
+    return DgradOut{dx, split, 0, split, dz, dz_stride, y, y_stride, add, add_stride};
+}
+
 vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, int wo, const uint16_t* w,
-                       int cin, int stride, int hv, int wv, float* dx, int accumulate, uint16_t* wt,
+                       int cin, int stride, int hv, int wv, const DgradOut& out, uint16_t* wt,
                        hipStream_t st)
 {
     hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks((uint64_t)cin * 9 * coutp)), dim3(kThreads), 0, st,
@@ -572,13 +606,13 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
     const unsigned gb = blocks(Q, 64 * kConvTiles);
     if (cin <= 16)
         hipLaunchKernelGGL((conv_dgrad_kernel<1, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
-                           wo, wt, cin, stride, hv, wv, dx, accumulate);
+                           wo, wt, cin, stride, hv, wv, out);
     else if (cin <= 32)
         hipLaunchKernelGGL((conv_dgrad_kernel<2, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
-                           wo, wt, cin, stride, hv, wv, dx, accumulate);
+                           wo, wt, cin, stride, hv, wv, out);
     else   // four channel tiles: two pixel tiles per wave (fewer registers, more waves in flight)
         hipLaunchKernelGGL((conv_dgrad_kernel<4, 2>), dim3(blocks(Q, 128)), dim3(kThreads), 0, st, dz, coutp, n, ho,
-                           wo, wt, cin, stride, hv, wv, dx, accumulate);
+                           wo, wt, cin, stride, hv, wv, out);
     return check("conv3x3 data gradient");
 }
 
@@ -637,7 +671,7 @@ vdbc_status relu_back(const ReluBack& a, uint16_t* dz, hipStream_t st)
 
 // Workspace carving for the whole network at n x h x w.
 struct NetLayout {
-    uint64_t c1, c2, c3, c4, c5, out, dz6, dy5, dz5, dcat, dz4, du, dz3, dy2, dz2, dy1, dz1, wt, partial,
+    uint64_t c1, c2, c3, c4, c5, out, dz6, dz5, dcat, dz4, du, dz3, dz2, dz1, wt, partial,
         lpart, grad, total;
 };
 
@@ -678,15 +712,12 @@ NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
     if (training) {
         L.out = take(P * 3 * 4);
         L.dz6 = take(P * 8 * 2);
-        L.dy5 = take(P * 32 * 4);
         L.dz5 = take(P * 32 * 2);
-        L.dcat = take(P * 64 * 4);
+        L.dcat = take(P * 32 * 4);   // the c1 half of the concat's gradient
         L.dz4 = take(P * 32 * 2);
         L.du = take(P * 64 * 4);
         L.dz3 = take(Ph * 64 * 2);
-        L.dy2 = take(Ph * 64 * 4);
         L.dz2 = take(Ph * 64 * 2);
-        L.dy1 = take(P * 32 * 4);
         L.dz1 = take(P * 32 * 2);
         L.wt = take(64 * 9 * 64 * 2);
         L.partial = take(net_partial_floats(n, h, w) * 4);
@@ -836,32 +867,35 @@ extern "C" vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, f
     uint16_t* wt = U(L.wt);
     // c6: 32 -> 3 (dz6 padded to 8 channels)
     if ((s = conv_wgrad(ConvIn{c5, nullptr, 32, 0, 0, N, H, W}, 1, U(L.dz6), 8, 3, gW(5), gB(5), part, pf, st))) return s;
-    if ((s = conv_dgrad(U(L.dz6), 8, 3, N, H, W, Wl(5), 32, 1, H, W, F(L.dy5), 0, wt, st))) return s;
-    if ((s = relu_back(ReluBack{F(L.dy5), 32, 0, nullptr, 0, 0, c5, 32, 32, 0, N, H, W}, U(L.dz5), st))) return s;
+    if ((s = conv_dgrad(U(L.dz6), 8, 3, N, H, W, Wl(5), 32, 1, H, W, relu_out(nullptr, 0, U(L.dz5), 32, c5, 32),
+                        wt, st)))
+        return s;
     // c5: concat(c1, c4) 64 -> 32
     if ((s = conv_wgrad(ConvIn{c1, c4, 32, 32, 0, N, H, W}, 1, U(L.dz5), 32, 32, gW(4), gB(4), part, pf, st))) return s;
-    if ((s = conv_dgrad(U(L.dz5), 32, 32, N, H, W, Wl(4), 64, 1, H, W, F(L.dcat), 0, wt, st))) return s;
-    if ((s = relu_back(ReluBack{F(L.dcat), 64, 32, nullptr, 0, 0, c4, 32, 32, 0, N, H, W}, U(L.dz4), st))) return s;
+    // channels 0..31 of the concat belong to c1 (FP32, added to c2's data
+    // gradient below), channels 32..63 to c4 (ReLU backward into dz4)
+    if ((s = conv_dgrad(U(L.dz5), 32, 32, N, H, W, Wl(4), 64, 1, H, W, relu_out(F(L.dcat), 32, U(L.dz4), 32, c4, 32),
+                        wt, st)))
+        return s;
     // c4: up2(c3) 64 -> 32
     if ((s = conv_wgrad(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, U(L.dz4), 32, 32, gW(3), gB(3), part, pf,
                         st)))
         return s;
-    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, F(L.du), 0, wt, st))) return s;
+    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, fp32_out(F(L.du), 64), wt, st))) return s;
     if ((s = relu_back(ReluBack{F(L.du), 64, 0, nullptr, 0, 0, c3, 64, 64, 1, N, H / 2, W / 2}, U(L.dz3), st)))
         return s;
     // c3: 64 -> 64 at half resolution
     if ((s = conv_wgrad(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, U(L.dz3), 64, 64, gW(2), gB(2), part, pf,
                         st)))
         return s;
-    if ((s = conv_dgrad(U(L.dz3), 64, 64, N, H / 2, W / 2, Wl(2), 64, 1, H / 2, W / 2, F(L.dy2), 0, wt, st)))
-        return s;
-    if ((s = relu_back(ReluBack{F(L.dy2), 64, 0, nullptr, 0, 0, c2, 64, 64, 0, N, H / 2, W / 2}, U(L.dz2), st)))
+    if ((s = conv_dgrad(U(L.dz3), 64, 64, N, H / 2, W / 2, Wl(2), 64, 1, H / 2, W / 2,
+                        relu_out(nullptr, 0, U(L.dz2), 64, c2, 64), wt, st)))
         return s;
     // c2: 32 -> 64, stride 2
     if ((s = conv_wgrad(ConvIn{c1, nullptr, 32, 0, 0, N, H, W}, 2, U(L.dz2), 64, 64, gW(1), gB(1), part, pf, st)))
         return s;
-    if ((s = conv_dgrad(U(L.dz2), 64, 64, N, H / 2, W / 2, Wl(1), 32, 2, H, W, F(L.dy1), 0, wt, st))) return s;
-    if ((s = relu_back(ReluBack{F(L.dcat), 64, 0, F(L.dy1), 32, 0, c1, 32, 32, 0, N, H, W}, U(L.dz1), st)))
+    if ((s = conv_dgrad(U(L.dz2), 64, 64, N, H / 2, W / 2, Wl(1), 32, 2, H, W,
+                        relu_out(nullptr, 0, U(L.dz1), 32, c1, 32, F(L.dcat), 32), wt, st)))
         return s;
     // c1: 8 -> 32 (no data gradient needed)
     if ((s = conv_wgrad(ConvIn{x, nullptr, 8, 0, 0, N, H, W}, 1, U(L.dz1), 32, 32, gW(0), gB(0), part, pf, st)))
@@ -917,7 +951,8 @@ extern "C" vdbc_status vdbc_conv3x3_dgrad(const uint16_t* dz, uint32_t coutp, ui
     if (ws_bytes < 64ull * 9 * 64 * 2) return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace too small");
     if (!aligned16(dz) || !aligned16(w) || !aligned16(ws)) return fail(VDBC_E_INVALID, "operands must be 16-byte aligned");
     return conv_dgrad(dz, (int)coutp, (int)cout, (int)n, (int)ho, (int)wo, w, (int)cin, (int)stride, (int)hv,
-                      (int)wv, dx, 0, static_cast<uint16_t*>(ws), static_cast<hipStream_t>(stream));
+                      (int)wv, fp32_out(dx, (int)cin), static_cast<uint16_t*>(ws),
+                      static_cast<hipStream_t>(stream));
 }
 
 extern "C" vdbc_status vdbc_conv3x3_wgrad(const uint16_t* a, uint32_t ca, const uint16_t* b, uint32_t cb,

@@ -104,6 +104,7 @@ enum CachePolicy { kCacheNone = 0, kCacheLeaf = 1, kCacheLeafLower = 2 };
 // lower node and the last leaf, reused across consecutive samples of one thread.
 template <int CP>
 struct VdbAccT {
+    static constexpr bool kTree = true;   // regions resolvable leaf by leaf
     VdbView v;
     int clx, cly, clz;       // cached leaf coordinates (voxel >> 3)
     LeafH cleaf;
@@ -260,6 +261,7 @@ struct DenseView {
 // The "3D texture" baseline: a plain x-fastest float32 array read in
 // software, background outside the volume.
 struct DenseAcc {
+    static constexpr bool kTree = false;
     DenseView v;
     __device__ void reset() {}
     __device__ __forceinline__ float background() const { return v.background; }

@@ -17,9 +17,19 @@ __global__ void zero_u64(unsigned long long* p)
 
 // ---------------------------------------------------------------- majorant
 
-// One workgroup per macrocell: the 256 threads split the (C+2)^3 dilated
-// footprint into z-columns (thread -> (i, j), walking k, so consecutive
-// lookups stay in one leaf), then reduce min and max across the workgroup.
+// One workgroup per macrocell: min and max of the values of the (C+2)^3
+// dilated footprint, reduced across the workgroup.  A dense array is read
+// voxel by voxel (thread -> z-column).  A VDB is read leaf region by leaf
+// region (thread -> 8^3 block of the footprint): a tile or an empty region
+// gives its one value without touching its voxels, a stored leaf its values
+// inside the footprint, so the empty space that makes up most of a
+// compressed volume costs one lookup per 512 voxels.  Both give the min and
+// max of the same values (the reconstruction, B outside), so the grids are
+// identical.
+// Leaf blocks a macrocell footprint can touch: (C + 2) / 8 + 2 per axis at
+// the largest macrocell, 64.
+constexpr int kMajorantQueue = 11 * 11 * 11;
+
 template <class Acc, class View>
 __global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, int C, int gx,
                                                           int gy, int gz, float* __restrict__ out)
@@ -31,12 +41,59 @@ __global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, 
               cz = (int)(cell / ((uint32_t)gx * (uint32_t)gy));
     const int E = C + 2, x0 = C * cx - 1, y0 = C * cy - 1, z0 = C * cz - 1;
     float vmin = INFINITY, vmax = -INFINITY;
-    for (int col = threadIdx.x; col < E * E; col += kBlock) {
-        const int i = col % E, j = col / E;
-        for (int k = 0; k < E; ++k) {
-            const float v = acc.voxel(x0 + i, y0 + j, z0 + k);
-            vmin = fminf(vmin, v);
-            vmax = fmaxf(vmax, v);
+    if constexpr (Acc::kTree) {
+        // leaf blocks [bx0, bx0 + nbx) x ... covering the footprint (floor
+        // division; at most 11^3 for a macrocell of 64).  First every thread
+        // resolves its blocks: a constant region enters the min and max at
+        // once, a stored leaf is queued in LDS.  Then each wave reads the
+        // queued leaves whole, 8 voxels per lane, keeping those inside the
+        // footprint.
+        __shared__ const float* qleaf[kMajorantQueue];
+        __shared__ int qblock[kMajorantQueue];
+        __shared__ int qn;
+        if (threadIdx.x == 0) qn = 0;
+        __syncthreads();
+        const int bx0 = x0 >> 3, by0 = y0 >> 3, bz0 = z0 >> 3;
+        const int nbx = ((x0 + E - 1) >> 3) - bx0 + 1, nby = ((y0 + E - 1) >> 3) - by0 + 1,
+                  nbz = ((z0 + E - 1) >> 3) - bz0 + 1;
+        for (int b = threadIdx.x; b < nbx * nby * nbz; b += kBlock) {
+            const int lx = bx0 + b % nbx, ly = by0 + (b / nbx) % nby, lz = bz0 + b / (nbx * nby);
+            const LeafH h = acc.resolve(lx, ly, lz);
+            if (h.m == 0u) {
+                vmin = fminf(vmin, h.p[0]);
+                vmax = fmaxf(vmax, h.p[0]);
+            } else {
+                const int q = atomicAdd(&qn, 1);
+                qleaf[q] = h.p;
+                qblock[q] = b;
+            }
+        }
+        __syncthreads();
+        const int lane = threadIdx.x & 63, nq = qn;
+        for (int q = threadIdx.x >> 6; q < nq; q += kBlock / 64) {
+            const int b = qblock[q];
+            const int ox = 8 * (bx0 + b % nbx) - x0, oy = 8 * (by0 + (b / nbx) % nby) - y0,
+                      oz = 8 * (bz0 + b / (nbx * nby)) - z0;
+            const float* p = qleaf[q];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int n3 = lane + 64 * s;
+                const int i = ox + (n3 & 7), j = oy + ((n3 >> 3) & 7), k = oz + (n3 >> 6);
+                if ((unsigned)i < (unsigned)E && (unsigned)j < (unsigned)E && (unsigned)k < (unsigned)E) {
+                    const float v = p[n3];
+                    vmin = fminf(vmin, v);
+                    vmax = fmaxf(vmax, v);
+                }
+            }
+        }
+    } else {
+        for (int col = threadIdx.x; col < E * E; col += kBlock) {
+            const int i = col % E, j = col / E;
+            for (int k = 0; k < E; ++k) {
+                const float v = acc.voxel(x0 + i, y0 + j, z0 + k);
+                vmin = fminf(vmin, v);
+                vmax = fmaxf(vmax, v);
+            }
         }
     }
 #pragma unroll
@@ -371,6 +428,7 @@ static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, 
 {
     const int gx = (v.nx + C - 1) / C, gy = (v.ny + C - 1) / C, gz = (v.nz + C - 1) / C;
     const uint64_t cells = (uint64_t)gx * gy * gz;
+    if (C < 4 || C > 64) return fail(VDBC_E_INVALID, "macrocell must be in [4, 64]");   // sizes kMajorantQueue
     if (cells > 0x7FFFFFFFull) return fail(VDBC_E_INVALID, "too many macrocells (%llu)", (unsigned long long)cells);
     hipLaunchKernelGGL((majorant_kernel<Acc, View>), dim3((unsigned)cells), dim3(kBlock), 0, st, v, m,
                        (int)C, gx, gy, gz, out);

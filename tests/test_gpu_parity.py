@@ -254,7 +254,7 @@ TF5 = dict(tf=[(0.2, 0.3, 0.9, 0.0), (0.9, 0.1, 0.2, 0.8), (0.4, 0.4, 0.4, 0.3),
                (1.0, 1.0, 0.0, 1.0), (0.0, 1.0, 1.0, 0.5)], tf_range=(0.1, 0.9))
 
 
-@pytest.mark.parametrize("C", [4, 8, 16])
+@pytest.mark.parametrize("C", [4, 8, 16, 64])
 def test_majorant_vs_oracle(C):
     shape = (45, 37, 70)
     v = _rand(shape, 51, zero=0.5)
@@ -266,6 +266,25 @@ def test_majorant_vs_oracle(C):
     got_d = vdbc.majorant(_dense_t(v), med, C, background=st["background"]).cpu().numpy()
     want_d = oracle.majorant(oracle.DenseField(v, st["background"]), med, C)
     np.testing.assert_allclose(got_d, want_d, rtol=2e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("C", [4, 8, 16, 32, 64])
+def test_majorant_of_tree_equals_majorant_of_its_reconstruction(C):
+    # the VDB majorant reads leaf regions (one value for a tile or empty
+    # region), the dense one every voxel: on the reconstructed grid the two
+    # must agree bit for bit, with tiles, empty regions, ragged edge bricks
+    # and footprints reaching outside the volume; lossless and 1:5, plus the
+    # partial-brick encoding
+    shape = (70, 45, 133)
+    v = _rand(shape, 52, zero=0.7)
+    v[:40, :32, :64] = np.float32(0.5)      # uniform region: tiles after pruning
+    med = dict(sigma_scale=6.0, **TF5)
+    for q, part in ((1.0, None), (0.2, None), (0.2, (0.5, 1e30))):
+        buf, st = vdbc.encode(v, q, partial=part)
+        R = oracle.reconstruct(v, q, partial=part)
+        got = vdbc.majorant(vdbc.Grid(buf), med, C).cpu().numpy()
+        want = vdbc.majorant(_dense_t(R), med, C, background=st["background"]).cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (q, part)
 
 
 # ---------------------------------------------------------------- EA

@@ -163,6 +163,88 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
     }
 }
 
+// Stride-1 forward on a two-dimensional output tile: the workgroup stages
+// its input tile (kFwdTH + 2) x (kFwdTW + 2) pixels x cin channels once in
+// LDS (zero outside the image; through the upsample / concat of ConvIn), so
+// the nine taps read shifted views of it instead of gathering every input
+// pixel from memory once per tap.  Pixels are padded by one 16-byte group in
+// LDS so that the 16 lanes of an operand fetch, reading consecutive pixels,
+// spread over the banks.  Wave w computes output rows 2w and 2w + 1, each
+// as two 16-pixel tiles, times NT tiles of 16 channels.
+constexpr int kFwdTH = 8, kFwdTW = 32;
+
+template <int NT>
+__global__ __launch_bounds__(kThreads) void conv_fwd_tiled_kernel(ConvIn in, const uint16_t* __restrict__ w,
+                                                                  const float* __restrict__ bias, int cout,
+                                                                  int ho, int wo, int relu,
+                                                                  uint16_t* __restrict__ out_bf,
+                                                                  float* __restrict__ out_f,
+                                                                  const uint16_t* __restrict__ resid)
+{
+    extern __shared__ uint4 s_tile[];
+    const int cin = in.ca + in.cb, K = 9 * cin, cg = cin / 8, ps = cg + 1;
+    constexpr int IW = kFwdTW + 2, IH = kFwdTH + 2;
+    const int tx0 = blockIdx.x * kFwdTW, ty0 = blockIdx.y * kFwdTH, n = blockIdx.z;
+    for (int e = threadIdx.x; e < IH * IW * cg; e += kThreads) {
+        const int pix = e / cg, c8 = e - pix * cg;
+        const int iy = ty0 - 1 + pix / IW, ix = tx0 - 1 + pix % IW;
+        s_tile[pix * ps + c8] = __builtin_bit_cast(uint4, gather8(in, n, iy, ix, 8 * c8));
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+    f4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kb = 0; kb < K; kb += 32) {
+        const int k = kb + 8 * g;
+        const int tap = k / cin, c0 = k - tap * cin;
+        const bool valid = tap < 9;
+        const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+        bf16x8 B[NT], A[4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = t * 16 + r;
+            B[t] = (co < cout && valid) ? load8(w + (int64_t)co * K + k) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int row = 2 * wave + (m >> 1) + ky, col = (m & 1) * 16 + r + kx;
+            A[m] = valid ? __builtin_bit_cast(bf16x8, s_tile[(row * IW + col) * ps + c0 / 8]) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = t * 16 + r;
+        if (co >= cout) continue;
+        const float bb = bias[co];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int y = ty0 + 2 * wave + (m >> 1);
+            if (y >= ho) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = tx0 + (m & 1) * 16 + 4 * g + i;
+                if (x >= wo) continue;
+                const int64_t pp = ((int64_t)n * ho + y) * wo + x;
+                float v = acc[m][t][i] + bb;
+                if (relu) v = fmaxf(v, 0.0f);
+                if (out_f) {
+                    if (resid) v += bf2f(resid[pp * 8 + co]);
+                    out_f[pp * cout + co] = v;
+                } else {
+                    out_bf[pp * cout + co] = f2bf(v);
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- data gradient
 // dx[q][c] (+)= sum_{tap, co} dz[p(q, tap)][co] Wt[c][tap][co] over the input
 // pixels q of the (virtual) input; p = ((y+1-ky)/s, (x+1-kx)/s) when that is
@@ -258,6 +340,172 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __
                     o.dz[qq * o.dz_stride + cc] = f2bf(v);
                 }
             }
+    }
+}
+
+// Stride-1 data gradient on a two-dimensional tile of input pixels, the
+// forward tile scheme with the taps mirrored: the workgroup stages dz over
+// its (kFwdTH + 2) x (kFwdTW + 2) window (zero outside the output) once in
+// LDS, and tap (ky, kx) of input pixel (y, x) reads dz at (y + 1 - ky,
+// x + 1 - kx), a shifted view of the window.  Same contraction order,
+// operands and epilogue as conv_dgrad_kernel.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void conv_dgrad_tiled_kernel(const uint16_t* __restrict__ dz, int coutp,
+                                                                    int ho, int wo,
+                                                                    const uint16_t* __restrict__ wt, int cin,
+                                                                    DgradOut o)
+{
+    extern __shared__ uint4 s_tile[];
+    const int K = 9 * coutp, cg = coutp / 8, ps = cg + 1;
+    constexpr int IW = kFwdTW + 2, IH = kFwdTH + 2;
+    const int tx0 = blockIdx.x * kFwdTW, ty0 = blockIdx.y * kFwdTH, n = blockIdx.z;
+    for (int e = threadIdx.x; e < IH * IW * cg; e += kThreads) {
+        const int pix = e / cg, c8 = e - pix * cg;
+        const int y = ty0 - 1 + pix / IW, x = tx0 - 1 + pix % IW;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if ((unsigned)y < (unsigned)ho && (unsigned)x < (unsigned)wo)
+            v = *reinterpret_cast<const uint4*>(dz + (((int64_t)n * ho + y) * wo + x) * coutp + 8 * c8);
+        s_tile[pix * ps + c8] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+    f4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kb = 0; kb < K; kb += 32) {
+        const int k = kb + 8 * g;
+        const int tap = k / coutp, co0 = k - tap * coutp;
+        const bool valid = tap < 9;
+        const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+        bf16x8 B[NT], A[4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = t * 16 + r;
+            B[t] = (c < cin && valid) ? load8(wt + (int64_t)c * K + k) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int row = 2 * wave + (m >> 1) + 2 - ky, col = (m & 1) * 16 + r + 2 - kx;
+            A[m] = valid ? __builtin_bit_cast(bf16x8, s_tile[(row * IW + col) * ps + co0 / 8]) : zero8();
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = t * 16 + r;
+        if (c >= cin) continue;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int y = ty0 + 2 * wave + (m >> 1);
+            if (y >= ho) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = tx0 + (m & 1) * 16 + 4 * g + i;
+                if (x >= wo) continue;
+                const int64_t qq = ((int64_t)n * ho + y) * wo + x;
+                float v = acc[m][t][i];
+                if (c < o.split) {
+                    float* d = o.dx + qq * o.dx_stride + c;
+                    *d = o.accumulate ? *d + v : v;
+                } else {
+                    const int cc = c - o.split;
+                    if (o.add) v += o.add[qq * o.add_stride + cc];
+                    if (!(bf2f(o.y[qq * o.y_stride + cc]) > 0.0f)) v = 0.0f;
+                    o.dz[qq * o.dz_stride + cc] = f2bf(v);
+                }
+            }
+        }
+    }
+}
+
+// Stride-2 data gradient by parity class: input pixel (y, x) takes tap
+// (ky, kx) only where y + 1 - ky and x + 1 - kx are even, so rows of even y
+// take ky = 1 alone and rows of odd y take ky = 0 and 2 (columns likewise):
+// 9 of the 36 (class, tap) pairs of a 2 x 2 pixel block.  Wave w takes
+// input rows ty0 + 2w (even) and ty0 + 2w + 1 (odd), each as a 16-pixel
+// tile of even and one of odd columns, so every MFMA tile is one parity
+// class and runs over its own taps only; the dz window under the
+// kFwdTH x kFwdTW input tile, (kFwdTH / 2 + 1) x (kFwdTW / 2 + 1) output
+// pixels, is staged in LDS once.  Chunks of 32 k (one tap, 32 output
+// channels) are added in the order of conv_dgrad_kernel, which adds only
+// zeros between them.
+template <int NT>
+__global__ __launch_bounds__(kThreads) void conv_dgrad_s2_kernel(const uint16_t* __restrict__ dz, int coutp,
+                                                                 int ho, int wo,
+                                                                 const uint16_t* __restrict__ wt, int cin,
+                                                                 int hv, int wv, DgradOut o)
+{
+    extern __shared__ uint4 s_tile[];
+    const int K = 9 * coutp, cg = coutp / 8, ps = cg + 1;
+    constexpr int IW = kFwdTW / 2 + 1, IH = kFwdTH / 2 + 1;
+    const int tx0 = blockIdx.x * kFwdTW, ty0 = blockIdx.y * kFwdTH, n = blockIdx.z;
+    const int oy0 = ty0 / 2, ox0 = tx0 / 2;
+    for (int e = threadIdx.x; e < IH * IW * cg; e += kThreads) {
+        const int pix = e / cg, c8 = e - pix * cg;
+        const int y = oy0 + pix / IW, x = ox0 + pix % IW;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (y < ho && x < wo)
+            v = *reinterpret_cast<const uint4*>(dz + (((int64_t)n * ho + y) * wo + x) * coutp + 8 * c8);
+        s_tile[pix * ps + c8] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, r = lane & 15;
+    f4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int py = m >> 1, px = m & 1;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int ky = tap / 3, kx = tap % 3;
+            if (((py + 1 - ky) & 1) || ((px + 1 - kx) & 1)) continue;
+            const int row = (2 * wave + py + 1 - ky) / 2, col = (2 * r + px + 1 - kx) / 2;
+            for (int cc = 0; cc < coutp; cc += 32) {
+                const int co0 = cc + 8 * g;
+                const bool valid = co0 < coutp;
+                const bf16x8 A = valid ? __builtin_bit_cast(bf16x8, s_tile[(row * IW + col) * ps + co0 / 8]) : zero8();
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int c = t * 16 + r;
+                    const bf16x8 B = (c < cin && valid) ? load8(wt + (int64_t)c * K + tap * coutp + co0) : zero8();
+                    acc[m][t] = mfma(A, B, acc[m][t]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int c = t * 16 + r;
+        if (c >= cin) continue;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int y = ty0 + 2 * wave + (m >> 1);
+            if (y >= hv) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = tx0 + 2 * (4 * g + i) + (m & 1);
+                if (x >= wv) continue;
+                const int64_t qq = ((int64_t)n * hv + y) * wv + x;
+                float v = acc[m][t][i];
+                if (c < o.split) {
+                    float* d = o.dx + qq * o.dx_stride + c;
+                    *d = o.accumulate ? *d + v : v;
+                } else {
+                    const int cc = c - o.split;
+                    if (o.add) v += o.add[qq * o.add_stride + cc];
+                    if (!(bf2f(o.y[qq * o.y_stride + cc]) > 0.0f)) v = 0.0f;
+                    o.dz[qq * o.dz_stride + cc] = f2bf(v);
+                }
+            }
+        }
     }
 }
 
@@ -389,6 +637,144 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
             const int co = t * 16 + 4 * g + i;
             partial[((int64_t)blockIdx.x * (MT * 16) + co) * K + k] = acc[t][i];
         }
+}
+
+// Stride-1 weight gradient on two-dimensional output tiles, every tap at
+// once: a workgroup owns a chunk of kWgTW output columns by `rows` output
+// rows of one image and a block of CB input channels, and walks it kWgTH
+// rows at a time.  Each step stages the dz rows and the input rows it needs
+// (kWgTH + 2 rows with the halo) in LDS once, channel-major so that the
+// eight consecutive pixels an MFMA operand fragment takes are one 16-byte
+// read; the input is stored three times, shifted by one pixel each, so the
+// three horizontal taps read aligned vectors.  The contraction runs over the
+// 32 pixels of one output row per MFMA; M = co (MT tiles of 16), N = the
+// 9 * CB (tap, channel) columns of the block, spread over the four waves
+// column tile by column tile.  Partials and bias partials have the layout
+// of conv_wgrad_kernel (chunk-major rows of 9 * cin), so the same reduction
+// follows; the workgroups of channel block 0 sum the bias partials.
+constexpr int kWgTW = 32;
+
+template <int MT, int CB, int TH>
+__global__ __launch_bounds__(kThreads) void conv_wgrad_tiled_kernel(ConvIn in, int ho, int wo,
+                                                                    const uint16_t* __restrict__ dz, int coutp,
+                                                                    int rows, int bands,
+                                                                    float* __restrict__ partial,
+                                                                    float* __restrict__ bpart)
+{
+    constexpr int IH = TH + 2, Q = kWgTW / 8;                 // staged input rows; 8-pixel groups per row
+    constexpr int TCT = (9 * CB + 15) / 16, NCT = (TCT + 3) / 4;   // column tiles: all, per wave
+    // channel strides padded to an odd number of 16-byte units, so that the
+    // 16 channels an operand fetch reads start in different banks
+    constexpr int SI = IH * Q + 1, SD = TH * Q + 1;
+    __shared__ uint4 s_in[3 * CB * SI];                       // [kx][c][iy][q]: pixels x0 + 8q + kx - 1 + j
+    __shared__ uint4 s_dz[MT * 16 * SD];                      // [co][oy][q]
+    const int cin = in.ca + in.cb, K = 9 * cin;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
+    const int x0 = blockIdx.x * kWgTW, band = blockIdx.y % bands, n = blockIdx.y / bands;
+    const int cb0 = blockIdx.z * CB, y_end = min(ho, (band + 1) * rows);
+    const bool bias = blockIdx.z == 0;   // uniform per workgroup
+    for (int e = tid; e < MT * 16 * SD; e += kThreads)         // channels past coutp stay zero
+        if (e >= coutp * SD) s_dz[e] = make_uint4(0, 0, 0, 0);
+    // this lane's LDS offset (in 16-byte units, row 0) per column tile
+    int boff[NCT];
+    bool bval[NCT];
+#pragma unroll
+    for (int i = 0; i < NCT; ++i) {
+        const int ct = wave + 4 * i, kl = 16 * ct + r, tap = kl / CB, c = kl - tap * CB;
+        bval[i] = ct < TCT;
+        const int ky = tap < 9 ? tap / 3 : 0, kx = tap < 9 ? tap - 3 * (tap / 3) : 0;
+        boff[i] = (tap < 9 && cb0 + c < cin) ? (kx * CB + c) * SI + ky * Q + g : -1;
+    }
+    f4 acc[MT][NCT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int i = 0; i < NCT; ++i) acc[t][i] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    auto half = [](const uint4& v, int ch) -> uint32_t {
+        const uint32_t w = ch < 2 ? v.x : ch < 4 ? v.y : ch < 6 ? v.z : v.w;
+        return (ch & 1) ? w >> 16 : w & 0xFFFFu;
+    };
+    for (int y0 = band * rows; y0 < y_end; y0 += TH) {
+        // input rows y0 - 1 .. y0 + TH: item (q, iy, channel group), so that
+        // neighbouring threads write neighbouring 16-byte units
+        for (int e = tid; e < IH * Q * (CB / 8); e += kThreads) {
+            const int q = e % Q, iy = (e / Q) % IH, cg = e / (Q * IH);
+            const int c8 = cb0 + 8 * cg, y = y0 - 1 + iy, xb = x0 + 8 * q - 1;
+            uint4 px[10];
+#pragma unroll
+            for (int m = 0; m < 10; ++m)
+                px[m] = c8 < cin ? __builtin_bit_cast(uint4, gather8(in, n, y, xb + m, c8)) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx)
+#pragma unroll
+                for (int ch = 0; ch < 8; ++ch) {
+                    uint4 v;
+                    v.x = half(px[kx + 0], ch) | half(px[kx + 1], ch) << 16;
+                    v.y = half(px[kx + 2], ch) | half(px[kx + 3], ch) << 16;
+                    v.z = half(px[kx + 4], ch) | half(px[kx + 5], ch) << 16;
+                    v.w = half(px[kx + 6], ch) | half(px[kx + 7], ch) << 16;
+                    s_in[(kx * CB + 8 * cg + ch) * SI + iy * Q + q] = v;
+                }
+        }
+        // dz rows y0 .. y0 + TH - 1 (zero past the image): item (q, oy, channel group)
+        for (int e = tid; e < TH * Q * (coutp / 8); e += kThreads) {
+            const int q = e % Q, oy = (e / Q) % TH, cg = e / (Q * TH);
+            const int y = y0 + oy, xb = x0 + 8 * q;
+            uint4 px[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                px[m] = (y < y_end && xb + m < wo)
+                            ? *reinterpret_cast<const uint4*>(dz + (((int64_t)n * ho + y) * wo + xb + m) * coutp + 8 * cg)
+                            : make_uint4(0, 0, 0, 0);
+#pragma unroll
+            for (int ch = 0; ch < 8; ++ch) {
+                uint4 v;
+                v.x = half(px[0], ch) | half(px[1], ch) << 16;
+                v.y = half(px[2], ch) | half(px[3], ch) << 16;
+                v.z = half(px[4], ch) | half(px[5], ch) << 16;
+                v.w = half(px[6], ch) | half(px[7], ch) << 16;
+                s_dz[(8 * cg + ch) * SD + oy * Q + q] = v;
+            }
+        }
+        __syncthreads();
+        if (bias && tid < coutp) {
+#pragma unroll
+            for (int e = 0; e < TH * Q; ++e) {
+                const uint4 v = s_dz[tid * SD + e];
+                bsum += ((bf2f(v.x & 0xFFFFu) + bf2f(v.x >> 16)) + (bf2f(v.y & 0xFFFFu) + bf2f(v.y >> 16))) +
+                        ((bf2f(v.z & 0xFFFFu) + bf2f(v.z >> 16)) + (bf2f(v.w & 0xFFFFu) + bf2f(v.w >> 16)));
+            }
+        }
+#pragma unroll
+        for (int oy = 0; oy < TH; ++oy) {
+            bf16x8 A[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                A[t] = __builtin_bit_cast(bf16x8, s_dz[(t * 16 + r) * SD + oy * Q + g]);
+#pragma unroll
+            for (int i = 0; i < NCT; ++i) {
+                if (!bval[i]) continue;   // uniform per wave
+                const bf16x8 B = boff[i] >= 0 ? __builtin_bit_cast(bf16x8, s_in[boff[i] + oy * Q]) : zero8();
+#pragma unroll
+                for (int t = 0; t < MT; ++t) acc[t][i] = mfma(A[t], B, acc[t][i]);
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t chunk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (bias && tid < coutp) bpart[chunk * coutp + tid] = bsum;
+#pragma unroll
+    for (int i = 0; i < NCT; ++i) {
+        if (!bval[i]) continue;
+        const int kl = 16 * (wave + 4 * i) + r, tap = kl / CB, c = kl - tap * CB;
+        if (tap >= 9 || cb0 + c >= cin) continue;
+        const int k = tap * cin + cb0 + c;
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) partial[(chunk * (MT * 16) + t * 16 + 4 * g + j) * K + k] = acc[t][i][j];
+    }
 }
 
 // grad[co][k] = sum over chunks of partial[chunk][co][k]: a workgroup takes
@@ -574,6 +960,21 @@ vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const floa
     const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
     const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
     const uint64_t P = (uint64_t)in.n * ho * wo;
+    const unsigned tiles_y = (unsigned)((ho + kFwdTH - 1) / kFwdTH);
+    if (stride == 1 && tiles_y <= 65535u && in.n <= 65535) {   // grid y and z limits
+        const dim3 grid((wo + kFwdTW - 1) / kFwdTW, tiles_y, in.n);
+        const size_t lds = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * ((in.ca + in.cb) / 8 + 1) * 16;
+        if (cout <= 16)
+            hipLaunchKernelGGL((conv_fwd_tiled_kernel<1>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo,
+                               relu, out_bf, out_f, resid);
+        else if (cout <= 32)
+            hipLaunchKernelGGL((conv_fwd_tiled_kernel<2>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo,
+                               relu, out_bf, out_f, resid);
+        else
+            hipLaunchKernelGGL((conv_fwd_tiled_kernel<4>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo,
+                               relu, out_bf, out_f, resid);
+        return check("conv3x3 forward");
+    }
     const unsigned gb = blocks(P, 64 * kConvTiles);
     if (cout <= 16)   // one channel tile: one pixel tile per wave keeps more workgroups in flight
         hipLaunchKernelGGL((conv_fwd_kernel<1, 1>), dim3(blocks(P, 64)), dim3(kThreads), 0, st, in, w, bias, cout,
@@ -604,6 +1005,35 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
                        w, cin, cout, coutp, wt);
     const uint64_t Q = (uint64_t)n * hv * wv;
     const unsigned gb = blocks(Q, 64 * kConvTiles);
+    const unsigned tiles_y = (unsigned)((hv + kFwdTH - 1) / kFwdTH);
+    if (stride == 1 && hv == ho && wv == wo && tiles_y <= 65535u && n <= 65535) {   // grid y and z limits
+        const dim3 grid((wv + kFwdTW - 1) / kFwdTW, tiles_y, n);
+        const size_t lds = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * (coutp / 8 + 1) * 16;
+        if (cin <= 16)
+            hipLaunchKernelGGL((conv_dgrad_tiled_kernel<1>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt,
+                               cin, out);
+        else if (cin <= 32)
+            hipLaunchKernelGGL((conv_dgrad_tiled_kernel<2>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt,
+                               cin, out);
+        else
+            hipLaunchKernelGGL((conv_dgrad_tiled_kernel<4>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt,
+                               cin, out);
+        return check("conv3x3 data gradient");
+    }
+    if (stride == 2 && tiles_y <= 65535u && n <= 65535) {
+        const dim3 grid((wv + kFwdTW - 1) / kFwdTW, tiles_y, n);
+        const size_t lds = (size_t)(kFwdTH / 2 + 1) * (kFwdTW / 2 + 1) * (coutp / 8 + 1) * 16;
+        if (cin <= 16)
+            hipLaunchKernelGGL((conv_dgrad_s2_kernel<1>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt, cin,
+                               hv, wv, out);
+        else if (cin <= 32)
+            hipLaunchKernelGGL((conv_dgrad_s2_kernel<2>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt, cin,
+                               hv, wv, out);
+        else
+            hipLaunchKernelGGL((conv_dgrad_s2_kernel<4>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt, cin,
+                               hv, wv, out);
+        return check("conv3x3 data gradient");
+    }
     if (cin <= 16)
         hipLaunchKernelGGL((conv_dgrad_kernel<1, kConvTiles>), dim3(gb), dim3(kThreads), 0, st, dz, coutp, n, ho,
                            wo, wt, cin, stride, hv, wv, out);
@@ -621,15 +1051,79 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
 // its partial rows are 64 apart).
 int wgrad_mt(int cout) { return cout <= 16 ? 1 : cout <= 32 ? 2 : 4; }
 
+// Launch plan of the tiled stride-1 weight-gradient kernel: channel block
+// CB (64 only where at most two output tiles keep the accumulators in
+// registers), TH rows per step, and output rows per chunk halved from 64
+// (down to TH) while the launch would have fewer than kWgTiledGroups
+// workgroups.  `ok` is false for stride 2 and for launches past the grid's
+// y and z limits; those take conv_wgrad_kernel.
+constexpr uint64_t kWgTiledGroups = 512;
+
+struct WgradTiled {
+    int cb, th, rows, bands, cols, cblocks;
+    uint64_t chunks;
+    bool ok;
+};
+
+WgradTiled wgrad_tiled_plan(const ConvIn& in, int stride, int cout)
+{
+    WgradTiled p{};
+    const int cin = in.ca + in.cb;
+    const int ho = in.up ? 2 * in.hs : in.hs, wo = in.up ? 2 * in.ws : in.ws;
+    p.cb = cin <= 8 ? 8 : cin <= 16 ? 16 : cin <= 32 ? 32 : wgrad_mt(cout) <= 2 ? 64 : 32;
+    p.th = p.cb == 64 ? 2 : 4;
+    p.cols = (wo + kWgTW - 1) / kWgTW;
+    p.cblocks = (cin + p.cb - 1) / p.cb;
+    auto groups = [&](int rows) { return (uint64_t)in.n * ((ho + rows - 1) / rows) * p.cols * p.cblocks; };
+    p.rows = 64;
+    while (p.rows > p.th && groups(p.rows) < kWgTiledGroups) p.rows /= 2;
+    p.bands = (ho + p.rows - 1) / p.rows;
+    p.chunks = (uint64_t)in.n * p.bands * p.cols;
+    p.ok = stride == 1 && (uint64_t)in.n * p.bands <= 65535u && p.cblocks <= 65535;
+    return p;
+}
+
+// Weight-gradient chunks of a launch: the tiled kernel's or conv_wgrad_kernel's.
+uint64_t wgrad_chunks(const ConvIn& in, int stride, int cout)
+{
+    const WgradTiled tp = wgrad_tiled_plan(in, stride, cout);
+    if (tp.ok) return tp.chunks;
+    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
+    const uint64_t P = (uint64_t)in.n * ((hv - 1) / stride + 1) * ((wv - 1) / stride + 1);
+    const uint64_t c = wgrad_chunk(P, 9 * (in.ca + in.cb));
+    return (P + c - 1) / c;
+}
+
 // Floats of the weight-gradient partials followed by the bias partials
 // (chunks x coutp, coutp <= 64).
 uint64_t wgrad_partial_floats(const ConvIn& in, int stride, int cout)
 {
-    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
-    const uint64_t P = (uint64_t)in.n * ((hv - 1) / stride + 1) * ((wv - 1) / stride + 1);
-    const uint64_t c = wgrad_chunk(P, 9 * (in.ca + in.cb)), chunks = (P + c - 1) / c;
+    const uint64_t chunks = wgrad_chunks(in, stride, cout);
     const int mpad = wgrad_mt(cout) * 16;
     return chunks * mpad * 9ull * (in.ca + in.cb) + chunks * 64ull;
+}
+
+template <int MT, int CB>
+void launch_wgrad_tiled(const WgradTiled& p, const ConvIn& in, int ho, int wo, const uint16_t* dz, int coutp,
+                        float* partial, float* bpart, hipStream_t st)
+{
+    constexpr int TH = CB == 64 ? 2 : 4;
+    hipLaunchKernelGGL((conv_wgrad_tiled_kernel<MT, CB, TH>), dim3(p.cols, in.n * p.bands, p.cblocks),
+                       dim3(kThreads), 0, st, in, ho, wo, dz, coutp, p.rows, p.bands, partial, bpart);
+}
+
+template <int MT>
+void launch_wgrad_tiled_mt(const WgradTiled& p, const ConvIn& in, int ho, int wo, const uint16_t* dz, int coutp,
+                           float* partial, float* bpart, hipStream_t st)
+{
+    if (p.cb == 8)
+        launch_wgrad_tiled<MT, 8>(p, in, ho, wo, dz, coutp, partial, bpart, st);
+    else if (p.cb == 16)
+        launch_wgrad_tiled<MT, 16>(p, in, ho, wo, dz, coutp, partial, bpart, st);
+    else if (p.cb == 32 || MT == 4)
+        launch_wgrad_tiled<MT, 32>(p, in, ho, wo, dz, coutp, partial, bpart, st);
+    else
+        launch_wgrad_tiled<MT, (MT <= 2 ? 64 : 32)>(p, in, ho, wo, dz, coutp, partial, bpart, st);
 }
 
 vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int coutp, int cout, float* dw,
@@ -644,11 +1138,19 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
     const int64_t P = (int64_t)in.n * ho * wo;
     const int chunk = wgrad_chunk(P, K);
-    const unsigned chunks = (unsigned)((P + chunk - 1) / chunk);
     const int mt = wgrad_mt(cout);
+    const WgradTiled tp = wgrad_tiled_plan(in, stride, cout);
+    const unsigned chunks = (unsigned)wgrad_chunks(in, stride, cout);
     dim3 grid(chunks, (K + 63) / 64);
     float* bpart = partial + (uint64_t)chunks * (mt * 16) * K;
-    if (mt == 1)
+    if (tp.ok) {
+        if (mt == 1)
+            launch_wgrad_tiled_mt<1>(tp, in, ho, wo, dz, coutp, partial, bpart, st);
+        else if (mt == 2)
+            launch_wgrad_tiled_mt<2>(tp, in, ho, wo, dz, coutp, partial, bpart, st);
+        else
+            launch_wgrad_tiled_mt<4>(tp, in, ho, wo, dz, coutp, partial, bpart, st);
+    } else if (mt == 1)
         hipLaunchKernelGGL(conv_wgrad_kernel<1>, grid, dim3(kThreads), 0, st, in, stride, ho, wo, dz, coutp, chunk, partial,
                            bpart);
     else if (mt == 2)
@@ -934,7 +1436,14 @@ extern "C" vdbc_status vdbc_conv3x3_grad_workspace(uint32_t cin, uint32_t cout, 
     if (!bytes || cin == 0 || cin > 64 || cout == 0 || cout > 64) return fail(VDBC_E_INVALID, "bad argument");
     const uint64_t P = (uint64_t)n * ho * wo;
     const uint64_t c = wgrad_chunk(P, 9 * (int)cin), chunks = (P + c - 1) / c;
-    *bytes = al(64ull * 9 * 64 * 2) + al(chunks * (64ull * 9 * cin + 64) * 4);
+    // the tiled stride-1 kernel's chunks for the same output (any cout)
+    uint64_t tiled = 0;
+    for (int mt_cout : {16, 32, 64}) {
+        const WgradTiled tp = wgrad_tiled_plan(ConvIn{nullptr, nullptr, (int)cin, 0, 0, (int)n, (int)ho, (int)wo},
+                                               1, mt_cout);
+        tiled = tp.chunks > tiled ? tp.chunks : tiled;
+    }
+    *bytes = al(64ull * 9 * 64 * 2) + al((chunks > tiled ? chunks : tiled) * (64ull * 9 * cin + 64) * 4);
     return VDBC_OK;
 }
 

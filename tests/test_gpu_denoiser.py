@@ -42,6 +42,8 @@ CONV_CASES = [  # (ca, cb, up, stride, cout, n, hs, ws)
     (32, 32, 0, 1, 32, 2, 14, 10),
     (32, 0, 0, 1, 3, 1, 17, 19),
     (32, 0, 0, 1, 40, 1, 12, 15),   # 33..48 output channels take the four-tile kernel
+    (16, 8, 0, 1, 20, 1, 9, 70),    # 24 input channels in a 32-channel block, three 32-column tiles
+    (40, 8, 1, 1, 16, 1, 5, 9),     # 48 input channels in a 64-channel block, upsampled
 ]
 
 

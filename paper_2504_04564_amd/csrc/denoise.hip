@@ -267,6 +267,11 @@ struct DgradOut {
     int y_stride;
     const float* add;
     int add_stride;
+    // The layer's input was upsampled x2 from the activation y: each 2 x 2
+    // block of the data gradient is summed (the upsample's backward) before
+    // the ReLU backward, and dz is written at half resolution (split 0,
+    // stride-1 tiled kernel only).
+    int pool;
 };
 
 template <int NT, int MB>
@@ -394,6 +399,30 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_tiled_kernel(const uint16
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+    }
+    if (o.pool) {
+        // rows 2w and 2w + 1 of the tile are tiles m and m + 2; columns
+        // 4g + i pair as (0, 1) and (2, 3) in one lane; ho and wo are even
+        const int y2 = ty0 / 2 + wave, h2 = ho / 2, w2 = wo / 2;
+        if (y2 >= h2) return;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int c = t * 16 + r;
+            if (c >= cin) continue;
+#pragma unroll
+            for (int mc = 0; mc < 2; ++mc)
+#pragma unroll
+                for (int ip = 0; ip < 2; ++ip) {
+                    const int x2 = (tx0 + mc * 16 + 4 * g) / 2 + ip;
+                    if (x2 >= w2) continue;
+                    const int64_t qh = ((int64_t)n * h2 + y2) * w2 + x2;
+                    float v = ((acc[mc][t][2 * ip] + acc[mc][t][2 * ip + 1]) + acc[mc + 2][t][2 * ip]) +
+                              acc[mc + 2][t][2 * ip + 1];
+                    if (!(bf2f(o.y[qh * o.y_stride + c]) > 0.0f)) v = 0.0f;
+                    o.dz[qh * o.dz_stride + c] = f2bf(v);
+                }
+        }
+        return;
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -813,47 +842,6 @@ __global__ __launch_bounds__(kThreads) void wgrad_reduce_kernel(const float* __r
 
 // ---------------------------------------------------------------- elementwise
 
-// dz[p][c] = (src1 + src2)[p][c] * (y[p][c] > 0) as BF16, zero-padded to
-// coutp channels.  With `pool`, src1 is read at full resolution (2h x 2w)
-// and summed over the 2x2 block of destination pixel (n, y, x): the backward
-// of the nearest x2 upsample.
-struct ReluBack {
-    const float* s1;
-    int s1_stride, s1_off;
-    const float* s2;
-    int s2_stride, s2_off;
-    const uint16_t* y;
-    int C, coutp, pool, n, h, w;
-};
-
-__global__ void relu_back_kernel(ReluBack a, uint16_t* __restrict__ dz)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t P = (int64_t)a.n * a.h * a.w;
-    if (i >= P * a.coutp) return;
-    const int c = (int)(i % a.coutp);
-    const int64_t p = i / a.coutp;
-    float v = 0.0f;
-    if (c < a.C) {
-        if (a.pool) {
-            const int x = (int)(p % a.w);
-            const int64_t t = p / a.w;
-            const int y = (int)(t % a.h), n = (int)(t / a.h);
-            const int W2 = 2 * a.w;
-            for (int dy = 0; dy < 2; ++dy)
-                for (int dxx = 0; dxx < 2; ++dxx) {
-                    const int64_t q = ((int64_t)n * 2 * a.h + 2 * y + dy) * W2 + 2 * x + dxx;
-                    v += a.s1[q * a.s1_stride + a.s1_off + c];
-                }
-        } else {
-            v = a.s1[p * a.s1_stride + a.s1_off + c];
-            if (a.s2) v += a.s2[p * a.s2_stride + a.s2_off + c];
-        }
-        if (a.y && !(bf2f(a.y[p * a.C + c]) > 0.0f)) v = 0.0f;
-    }
-    dz[i] = f2bf(v);
-}
-
 // Relative-MSE loss over RGB: per-block partial sums of (o-t)^2/(t^2+0.01)
 // and the gradient 2(o-t)/(t^2+0.01)/(3P) written as BF16 with 8 channels.
 __global__ __launch_bounds__(kThreads) void loss_kernel(const float* __restrict__ out,
@@ -988,6 +976,11 @@ vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const floa
     return check("conv3x3 forward");
 }
 
+// 2 x 2 sums through the ReLU backward into BF16 dz at half resolution.
+DgradOut pool_out(uint16_t* dz, int dz_stride, const uint16_t* y, int y_stride)
+{
+    return DgradOut{nullptr, 0, 0, 0, dz, dz_stride, y, y_stride, nullptr, 0, 1};
+}
 // Every channel as FP32 (stride `cin`).
 DgradOut fp32_out(float* dx, int cin) { return DgradOut{dx, cin, 0, cin, nullptr, 0, nullptr, 0, nullptr, 0}; }
 // Channels [split, cin) through the ReLU backward into BF16 dz (see DgradOut).
@@ -1006,7 +999,10 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
     const uint64_t Q = (uint64_t)n * hv * wv;
     const unsigned gb = blocks(Q, 64 * kConvTiles);
     const unsigned tiles_y = (unsigned)((hv + kFwdTH - 1) / kFwdTH);
-    if (stride == 1 && hv == ho && wv == wo && tiles_y <= 65535u && n <= 65535) {   // grid y and z limits
+    const bool tiled = stride == 1 && hv == ho && wv == wo && tiles_y <= 65535u && n <= 65535;   // grid y, z limits
+    if (out.pool && !(tiled && hv % 2 == 0 && wv % 2 == 0 && out.split == 0))
+        return fail(VDBC_E_INVALID, "pooled data gradient needs stride 1, even sizes and the tiled kernel");
+    if (tiled) {
         const dim3 grid((wv + kFwdTW - 1) / kFwdTW, tiles_y, n);
         const size_t lds = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * (coutp / 8 + 1) * 16;
         if (cin <= 16)
@@ -1164,16 +1160,9 @@ vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int cou
     return check("conv3x3 weight gradient");
 }
 
-vdbc_status relu_back(const ReluBack& a, uint16_t* dz, hipStream_t st)
-{
-    hipLaunchKernelGGL(relu_back_kernel, dim3(blocks((uint64_t)a.n * a.h * a.w * a.coutp)), dim3(kThreads), 0,
-                       st, a, dz);
-    return check("relu backward");
-}
-
 // Workspace carving for the whole network at n x h x w.
 struct NetLayout {
-    uint64_t c1, c2, c3, c4, c5, out, dz6, dz5, dcat, dz4, du, dz3, dz2, dz1, wt, partial,
+    uint64_t c1, c2, c3, c4, c5, out, dz6, dz5, dcat, dz4, dz3, dz2, dz1, wt, partial,
         lpart, grad, total;
 };
 
@@ -1217,7 +1206,6 @@ NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
         L.dz5 = take(P * 32 * 2);
         L.dcat = take(P * 32 * 4);   // the c1 half of the concat's gradient
         L.dz4 = take(P * 32 * 2);
-        L.du = take(P * 64 * 4);
         L.dz3 = take(Ph * 64 * 2);
         L.dz2 = take(Ph * 64 * 2);
         L.dz1 = take(P * 32 * 2);
@@ -1383,8 +1371,8 @@ extern "C" vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, f
     if ((s = conv_wgrad(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, U(L.dz4), 32, 32, gW(3), gB(3), part, pf,
                         st)))
         return s;
-    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, fp32_out(F(L.du), 64), wt, st))) return s;
-    if ((s = relu_back(ReluBack{F(L.du), 64, 0, nullptr, 0, 0, c3, 64, 64, 1, N, H / 2, W / 2}, U(L.dz3), st)))
+    // the upsample's backward (2 x 2 sums) and c3's ReLU backward in the epilogue
+    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, pool_out(U(L.dz3), 64, c3, 64), wt, st)))
         return s;
     // c3: 64 -> 64 at half resolution
     if ((s = conv_wgrad(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, U(L.dz3), 64, 64, gW(2), gB(2), part, pf,

@@ -7,6 +7,7 @@ passed in by the caller.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -58,7 +59,7 @@ def train(dn: "vdbc.Denoiser", xs, ts, steps: int, batch: int, lr: float, seed: 
                              ts.index_select(0, idx).contiguous(), lr)
         losses[s] = loss[0]
         if log_every and (s + 1) % log_every == 0:
-            print(f"[denoiser] step {s + 1}/{steps} loss {loss.item():.5f}", flush=True)
+            print(f"[denoiser] step {s + 1}/{steps} loss {loss.item():.5f}", file=sys.stderr, flush=True)
     return losses.cpu().numpy()
 
 
@@ -120,5 +121,5 @@ def timed_section(label: str):
             return self
 
         def __exit__(self, *a):
-            print(f"[denoiser] {label}: {time.time() - self.t:.1f}s", flush=True)
+            print(f"[denoiser] {label}: {time.time() - self.t:.1f}s", file=sys.stderr, flush=True)
     return _T()

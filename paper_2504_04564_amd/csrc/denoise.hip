@@ -272,6 +272,9 @@ struct DgradOut {
     // the ReLU backward, and dz is written at half resolution (split 0,
     // stride-1 tiled kernel only).
     int pool;
+    // Set by the launcher: every pointer above aligned for 16-byte (FP32)
+    // and 8-byte (BF16) accesses of four channels, strides multiples of 4.
+    int vec;
 };
 
 template <int NT, int MB>
@@ -348,13 +351,116 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __
     }
 }
 
+// Epilogue of a data-gradient kernel through LDS.  The accumulators of the
+// workgroup's kFwdTH x kFwdTW pixel tile go to LDS channel-major, FP32
+// [channel][pixel] with a channel stride of 256 + 4 floats, 32 channels per
+// pass: a lane holds
+// one channel of several pixels, and the caller passes them as 16-byte runs
+// of consecutive pixels (runs[n] holds pixels run_pix[n] .. + 3 of channel
+// t * 16 + r for run n of channel tile t).  Then each thread takes four
+// channels of one pixel at a time, so that neighbouring threads read and
+// write neighbouring 16-byte (FP32) and 8-byte (BF16) pieces of memory.  Per
+// element the arithmetic is that of the direct epilogue.
+constexpr int kEpiStride = kFwdTH * kFwdTW + 4;
+
+// Channels [c_lo, c_hi) of the tile, staged channel-major from channel c_lo.
+__device__ __forceinline__ void dgrad_store_pass(const float* s_out, int c_lo, int c_hi, int ty0, int tx0, int n,
+                                                 int hv, int wv, const DgradOut& o)
+{
+    const int groups = (c_hi - c_lo) / 4;
+    for (int e = threadIdx.x; e < kFwdTH * kFwdTW * groups; e += kThreads) {
+        const int p = e / groups, c = c_lo + (e - p * groups) * 4;
+        const int y = ty0 + p / kFwdTW, x = tx0 + p % kFwdTW;
+        if (y >= hv || x >= wv) continue;
+        const int64_t qq = ((int64_t)n * hv + y) * wv + x;
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = s_out[(c - c_lo + j) * kEpiStride + p];
+        if (c < o.split) {
+            float* d = o.dx + qq * o.dx_stride + c;
+            if (o.vec) {
+                float4* d4 = reinterpret_cast<float4*>(d);
+                if (o.accumulate) {
+                    const float4 b = *d4;
+                    v[0] = b.x + v[0];
+                    v[1] = b.y + v[1];
+                    v[2] = b.z + v[2];
+                    v[3] = b.w + v[3];
+                }
+                *d4 = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) d[j] = o.accumulate ? d[j] + v[j] : v[j];
+            }
+        } else {
+            const int cc = c - o.split;
+            const uint16_t* yp = o.y + qq * o.y_stride + cc;
+            uint16_t* zp = o.dz + qq * o.dz_stride + cc;
+            uint16_t yv[4], out[4];
+            if (o.vec) {
+                if (o.add) {
+                    const float4 b = *reinterpret_cast<const float4*>(o.add + qq * o.add_stride + cc);
+                    v[0] += b.x;
+                    v[1] += b.y;
+                    v[2] += b.z;
+                    v[3] += b.w;
+                }
+                const uint2 yy = *reinterpret_cast<const uint2*>(yp);
+                yv[0] = (uint16_t)(yy.x & 0xFFFFu);
+                yv[1] = (uint16_t)(yy.x >> 16);
+                yv[2] = (uint16_t)(yy.y & 0xFFFFu);
+                yv[3] = (uint16_t)(yy.y >> 16);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (o.add) v[j] += o.add[qq * o.add_stride + cc + j];
+                    yv[j] = yp[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[j] = f2bf(bf2f(yv[j]) > 0.0f ? v[j] : 0.0f);
+            if (o.vec) {
+                *reinterpret_cast<uint2*>(zp) =
+                    make_uint2((uint32_t)out[0] | (uint32_t)out[1] << 16, (uint32_t)out[2] | (uint32_t)out[3] << 16);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) zp[j] = out[j];
+            }
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void dgrad_store_staged(float* s_out, const float4 (&runs)[4][NT], const int (&run_pix)[4],
+                                                   int cin, int ty0, int tx0, int n, int hv, int wv,
+                                                   const DgradOut& o)
+{
+    // at most two channel tiles (32 channels) per pass, so that the buffer
+    // stays at 33 KB and more workgroups fit on a CU
+    constexpr int PT = NT < 2 ? NT : 2;
+    const int r = threadIdx.x & 15;
+#pragma unroll
+    for (int pass = 0; pass < NT / PT; ++pass) {
+        __syncthreads();   // the staged window, or the previous pass, is done with
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int tt = 0; tt < PT; ++tt)
+                *reinterpret_cast<float4*>(s_out + (tt * 16 + r) * kEpiStride + run_pix[k]) = runs[k][pass * PT + tt];
+        __syncthreads();
+        const int c_lo = pass * PT * 16, c_hi = min(cin, c_lo + PT * 16);
+        if (c_lo < c_hi) dgrad_store_pass(s_out, c_lo, c_hi, ty0, tx0, n, hv, wv, o);
+    }
+}
+
+
 // Stride-1 data gradient on a two-dimensional tile of input pixels, the
 // forward tile scheme with the taps mirrored: the workgroup stages dz over
 // its (kFwdTH + 2) x (kFwdTW + 2) window (zero outside the output) once in
 // LDS, and tap (ky, kx) of input pixel (y, x) reads dz at (y + 1 - ky,
 // x + 1 - kx), a shifted view of the window.  Same contraction order,
 // operands and epilogue as conv_dgrad_kernel.
-template <int NT>
+template <int NT, bool STAGED>
 __global__ __launch_bounds__(kThreads) void conv_dgrad_tiled_kernel(const uint16_t* __restrict__ dz, int coutp,
                                                                     int ho, int wo,
                                                                     const uint16_t* __restrict__ wt, int cin,
@@ -399,6 +505,19 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_tiled_kernel(const uint16
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+    }
+    if constexpr (STAGED) {
+        // tile m holds pixels (m & 1) * 16 + 4g .. + 3 of row 2w + (m >> 1)
+        int run_pix[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) run_pix[m] = (2 * wave + (m >> 1)) * kFwdTW + (m & 1) * 16 + 4 * g;
+        float4 runs[4][NT];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) runs[m][t] = make_float4(acc[m][t][0], acc[m][t][1], acc[m][t][2], acc[m][t][3]);
+        dgrad_store_staged<NT>(reinterpret_cast<float*>(s_tile), runs, run_pix, cin, ty0, tx0, n, ho, wo, o);
+        return;
     }
     if (o.pool) {
         // rows 2w and 2w + 1 of the tile are tiles m and m + 2; columns
@@ -509,6 +628,25 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_s2_kernel(const uint16_t*
                 }
             }
         }
+    }
+    if constexpr (NT <= 2) {
+        // row 2w + h holds pixels 8g .. 8g + 7 of this lane's channel as
+        // tiles m = 2h (even columns) and 2h + 1 (odd columns), interleaved
+        float4 runs[4][NT];
+        int run_pix[4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            run_pix[2 * h] = (2 * wave + h) * kFwdTW + 8 * g;
+            run_pix[2 * h + 1] = run_pix[2 * h] + 4;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const f4 e = acc[2 * h][t], d = acc[2 * h + 1][t];
+                runs[2 * h][t] = make_float4(e[0], d[0], e[1], d[1]);
+                runs[2 * h + 1][t] = make_float4(e[2], d[2], e[3], d[3]);
+            }
+        }
+        dgrad_store_staged<NT>(reinterpret_cast<float*>(s_tile), runs, run_pix, cin, ty0, tx0, n, hv, wv, o);
+        return;
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -942,6 +1080,17 @@ vdbc_status check(const char* what)
 
 bool aligned16(const void* p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Dynamic LDS past 64 KiB needs the kernel's limit raised first; false
+// (and the error cleared) where the device refuses, so that the caller can
+// take a variant that needs less.
+bool allow_lds(const void* kernel, size_t bytes)
+{
+    if (bytes <= 65536) return true;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    return false;
+}
+
 vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const float* bias, int cout,
                      int relu, uint16_t* out_bf, float* out_f, const uint16_t* resid, hipStream_t st)
 {
@@ -991,9 +1140,17 @@ DgradOut relu_out(float* dx, int split, uint16_t* dz, int dz_stride, const uint1
 }
 
 vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, int wo, const uint16_t* w,
-                       int cin, int stride, int hv, int wv, const DgradOut& out, uint16_t* wt,
+                       int cin, int stride, int hv, int wv, const DgradOut& out_in, uint16_t* wt,
                        hipStream_t st)
 {
+    if (out_in.split % 4) return fail(VDBC_E_INVALID, "data gradient: split must be a multiple of 4");
+    DgradOut out = out_in;
+    auto al8 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; };
+    const bool fp_ok = out.split == 0 || (aligned16(out.dx) && out.dx_stride % 4 == 0);
+    const bool bf_ok = out.split >= cin || ((!out.add || (aligned16(out.add) && out.add_stride % 4 == 0)) &&
+                                            al8(out.y) && al8(out.dz) && out.y_stride % 4 == 0 &&
+                                            out.dz_stride % 4 == 0);
+    out.vec = fp_ok && bf_ok;
     hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks((uint64_t)cin * 9 * coutp)), dim3(kThreads), 0, st,
                        w, cin, cout, coutp, wt);
     const uint64_t Q = (uint64_t)n * hv * wv;
@@ -1004,21 +1161,43 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
         return fail(VDBC_E_INVALID, "pooled data gradient needs stride 1, even sizes and the tiled kernel");
     if (tiled) {
         const dim3 grid((wv + kFwdTW - 1) / kFwdTW, tiles_y, n);
-        const size_t lds = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * (coutp / 8 + 1) * 16;
-        if (cin <= 16)
-            hipLaunchKernelGGL((conv_dgrad_tiled_kernel<1>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt,
-                               cin, out);
-        else if (cin <= 32)
-            hipLaunchKernelGGL((conv_dgrad_tiled_kernel<2>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt,
-                               cin, out);
-        else
-            hipLaunchKernelGGL((conv_dgrad_tiled_kernel<4>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt,
-                               cin, out);
+        const int nt = cin <= 16 ? 1 : cin <= 32 ? 2 : 4;
+        const size_t win = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * (coutp / 8 + 1) * 16;
+        const size_t epi = (size_t)(nt < 2 ? nt : 2) * 16 * kEpiStride * 4;   // two channel tiles per pass
+        const size_t lds = win > epi ? win : epi;
+        // the staged epilogue where the LDS allows it (the pooled one stays direct)
+        const void* kern = nt == 1   ? reinterpret_cast<const void*>(&conv_dgrad_tiled_kernel<1, true>)
+                           : nt == 2 ? reinterpret_cast<const void*>(&conv_dgrad_tiled_kernel<2, true>)
+                                     : reinterpret_cast<const void*>(&conv_dgrad_tiled_kernel<4, true>);
+        const bool staged = !out.pool && allow_lds(kern, lds);
+#define VDBC_DGRAD_TILED(NTV, S, L)                                                                              \
+    hipLaunchKernelGGL((conv_dgrad_tiled_kernel<NTV, S>), grid, dim3(kThreads), L, st, dz, coutp, ho, wo, wt, cin, \
+                       out)
+        if (staged) {
+            if (nt == 1)
+                VDBC_DGRAD_TILED(1, true, lds);
+            else if (nt == 2)
+                VDBC_DGRAD_TILED(2, true, lds);
+            else
+                VDBC_DGRAD_TILED(4, true, lds);
+        } else {
+            if (nt == 1)
+                VDBC_DGRAD_TILED(1, false, win);
+            else if (nt == 2)
+                VDBC_DGRAD_TILED(2, false, win);
+            else
+                VDBC_DGRAD_TILED(4, false, win);
+        }
+#undef VDBC_DGRAD_TILED
         return check("conv3x3 data gradient");
     }
     if (stride == 2 && tiles_y <= 65535u && n <= 65535) {
         const dim3 grid((wv + kFwdTW - 1) / kFwdTW, tiles_y, n);
-        const size_t lds = (size_t)(kFwdTH / 2 + 1) * (kFwdTW / 2 + 1) * (coutp / 8 + 1) * 16;
+        size_t lds = (size_t)(kFwdTH / 2 + 1) * (kFwdTW / 2 + 1) * (coutp / 8 + 1) * 16;
+        if (cin <= 32) {   // the staged epilogue of one or two channel tiles
+            const size_t epi = (size_t)(cin <= 16 ? 16 : 32) * kEpiStride * 4;
+            lds = lds > epi ? lds : epi;
+        }
         if (cin <= 16)
             hipLaunchKernelGGL((conv_dgrad_s2_kernel<1>), grid, dim3(kThreads), lds, st, dz, coutp, ho, wo, wt, cin,
                                hv, wv, out);

@@ -172,8 +172,53 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_kernel(ConvIn in, const uin
 // spread over the banks.  Wave w computes output rows 2w and 2w + 1, each
 // as two 16-pixel tiles, times NT tiles of 16 channels.
 constexpr int kFwdTH = 8, kFwdTW = 32;
+constexpr int kEpiStride = kFwdTH * kFwdTW + 4;   // channel stride of an epilogue staged through LDS
 
+// Forward epilogue through LDS (BF16 output, cout a multiple of 4): the
+// accumulators go to LDS channel-major as in the data gradient's staged
+// epilogue, 32 channels per pass; then each thread takes four channels of
+// one pixel, adds the bias, applies the ReLU and writes the four BF16 values
+// as one 8-byte store.  Per element the arithmetic is the direct epilogue's.
 template <int NT>
+__device__ __forceinline__ void fwd_store_staged(float* s_out, const f4 (&acc)[4][NT], const int (&run_pix)[4],
+                                                 const float* __restrict__ bias, int cout, int relu, int ty0,
+                                                 int tx0, int n, int ho, int wo, uint16_t* __restrict__ out_bf)
+{
+    constexpr int PT = NT < 2 ? NT : 2;
+    const int r = threadIdx.x & 15;
+#pragma unroll
+    for (int pass = 0; pass < NT / PT; ++pass) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int tt = 0; tt < PT; ++tt) {
+                const f4 a = acc[k][pass * PT + tt];
+                *reinterpret_cast<float4*>(s_out + (tt * 16 + r) * kEpiStride + run_pix[k]) =
+                    make_float4(a[0], a[1], a[2], a[3]);
+            }
+        __syncthreads();
+        const int c_lo = pass * PT * 16, c_hi = min(cout, c_lo + PT * 16);
+        const int groups = (c_hi - c_lo) / 4;
+        for (int e = threadIdx.x; e < kFwdTH * kFwdTW * groups; e += kThreads) {
+            const int p = e / groups, c = c_lo + (e - p * groups) * 4;
+            const int y = ty0 + p / kFwdTW, x = tx0 + p % kFwdTW;
+            if (y >= ho || x >= wo) continue;
+            const int64_t pp = ((int64_t)n * ho + y) * wo + x;
+            uint16_t out[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float v = s_out[(c - c_lo + j) * kEpiStride + p] + bias[c + j];
+                if (relu) v = fmaxf(v, 0.0f);
+                out[j] = f2bf(v);
+            }
+            *reinterpret_cast<uint2*>(out_bf + pp * cout + c) =
+                make_uint2((uint32_t)out[0] | (uint32_t)out[1] << 16, (uint32_t)out[2] | (uint32_t)out[3] << 16);
+        }
+    }
+}
+
+template <int NT, bool STAGED>
 __global__ __launch_bounds__(kThreads) void conv_fwd_tiled_kernel(ConvIn in, const uint16_t* __restrict__ w,
                                                                   const float* __restrict__ bias, int cout,
                                                                   int ho, int wo, int relu,
@@ -217,6 +262,15 @@ __global__ __launch_bounds__(kThreads) void conv_fwd_tiled_kernel(ConvIn in, con
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[m][t] = mfma(A[m], B[t], acc[m][t]);
+    }
+    if constexpr (STAGED) {
+        // tile m holds pixels (m & 1) * 16 + 4g .. + 3 of row 2w + (m >> 1)
+        int run_pix[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) run_pix[m] = (2 * wave + (m >> 1)) * kFwdTW + (m & 1) * 16 + 4 * g;
+        fwd_store_staged<NT>(reinterpret_cast<float*>(s_tile), acc, run_pix, bias, cout, relu, ty0, tx0, n, ho, wo,
+                             out_bf);
+        return;
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -361,8 +415,6 @@ __global__ __launch_bounds__(kThreads) void conv_dgrad_kernel(const uint16_t* __
 // channels of one pixel at a time, so that neighbouring threads read and
 // write neighbouring 16-byte (FP32) and 8-byte (BF16) pieces of memory.  Per
 // element the arithmetic is that of the direct epilogue.
-constexpr int kEpiStride = kFwdTH * kFwdTW + 4;
-
 // Channels [c_lo, c_hi) of the tile, staged channel-major from channel c_lo.
 __device__ __forceinline__ void dgrad_store_pass(const float* s_out, int c_lo, int c_hi, int ty0, int tx0, int n,
                                                  int hv, int wv, const DgradOut& o)
@@ -1100,16 +1152,31 @@ vdbc_status conv_fwd(const ConvIn& in, int stride, const uint16_t* w, const floa
     const unsigned tiles_y = (unsigned)((ho + kFwdTH - 1) / kFwdTH);
     if (stride == 1 && tiles_y <= 65535u && in.n <= 65535) {   // grid y and z limits
         const dim3 grid((wo + kFwdTW - 1) / kFwdTW, tiles_y, in.n);
-        const size_t lds = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * ((in.ca + in.cb) / 8 + 1) * 16;
-        if (cout <= 16)
-            hipLaunchKernelGGL((conv_fwd_tiled_kernel<1>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo,
-                               relu, out_bf, out_f, resid);
-        else if (cout <= 32)
-            hipLaunchKernelGGL((conv_fwd_tiled_kernel<2>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo,
-                               relu, out_bf, out_f, resid);
-        else
-            hipLaunchKernelGGL((conv_fwd_tiled_kernel<4>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo,
-                               relu, out_bf, out_f, resid);
+        const int nt = cout <= 16 ? 1 : cout <= 32 ? 2 : 4;
+        const size_t win = (size_t)(kFwdTH + 2) * (kFwdTW + 2) * ((in.ca + in.cb) / 8 + 1) * 16;
+        const size_t epi = (size_t)(nt < 2 ? nt : 2) * 16 * kEpiStride * 4;
+        // the staged epilogue for BF16 output in groups of four channels
+        const bool staged = out_bf && !out_f && cout % 4 == 0 && (reinterpret_cast<uintptr_t>(out_bf) & 7u) == 0;
+        const size_t lds = staged && epi > win ? epi : win;
+#define VDBC_FWD_TILED(NTV, S)                                                                                    \
+    hipLaunchKernelGGL((conv_fwd_tiled_kernel<NTV, S>), grid, dim3(kThreads), lds, st, in, w, bias, cout, ho, wo, \
+                       relu, out_bf, out_f, resid)
+        if (staged) {
+            if (nt == 1)
+                VDBC_FWD_TILED(1, true);
+            else if (nt == 2)
+                VDBC_FWD_TILED(2, true);
+            else
+                VDBC_FWD_TILED(4, true);
+        } else {
+            if (nt == 1)
+                VDBC_FWD_TILED(1, false);
+            else if (nt == 2)
+                VDBC_FWD_TILED(2, false);
+            else
+                VDBC_FWD_TILED(4, false);
+        }
+#undef VDBC_FWD_TILED
         return check("conv3x3 forward");
     }
     const unsigned gb = blocks(P, 64 * kConvTiles);

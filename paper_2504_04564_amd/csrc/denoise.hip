@@ -860,9 +860,9 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
 
 // Stride-1 weight gradient on two-dimensional output tiles, every tap at
 // once: a workgroup owns a chunk of kWgTW output columns by `rows` output
-// rows of one image and a block of CB input channels, and walks it kWgTH
+// rows of one image and a block of CB input channels, and walks it TH
 // rows at a time.  Each step stages the dz rows and the input rows it needs
-// (kWgTH + 2 rows with the halo) in LDS once, channel-major so that the
+// (TH + 2 rows with the halo) in LDS once, channel-major so that the
 // eight consecutive pixels an MFMA operand fragment takes are one 16-byte
 // read; the input is stored three times, shifted by one pixel each, so the
 // three horizontal taps read aligned vectors.  The contraction runs over the
@@ -1294,8 +1294,8 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
 int wgrad_mt(int cout) { return cout <= 16 ? 1 : cout <= 32 ? 2 : 4; }
 
 // Launch plan of the tiled stride-1 weight-gradient kernel: channel block
-// CB (64 only where at most two output tiles keep the accumulators in
-// registers), TH rows per step, and output rows per chunk halved from 64
+// CB (8, 16 or 32; blocks of 64 channels with two rows per step measured
+// 1 % slower), TH rows per step, and output rows per chunk halved from 64
 // (down to TH) while the launch would have fewer than kWgTiledGroups
 // workgroups.  `ok` is false for stride 2 and for launches past the grid's
 // y and z limits; those take conv_wgrad_kernel.
@@ -1312,8 +1312,8 @@ WgradTiled wgrad_tiled_plan(const ConvIn& in, int stride, int cout)
     WgradTiled p{};
     const int cin = in.ca + in.cb;
     const int ho = in.up ? 2 * in.hs : in.hs, wo = in.up ? 2 * in.ws : in.ws;
-    p.cb = cin <= 8 ? 8 : cin <= 16 ? 16 : cin <= 32 ? 32 : wgrad_mt(cout) <= 2 ? 64 : 32;
-    p.th = p.cb == 64 ? 2 : 4;
+    p.cb = cin <= 8 ? 8 : cin <= 16 ? 16 : 32;
+    p.th = 4;
     p.cols = (wo + kWgTW - 1) / kWgTW;
     p.cblocks = (cin + p.cb - 1) / p.cb;
     auto groups = [&](int rows) { return (uint64_t)in.n * ((ho + rows - 1) / rows) * p.cols * p.cblocks; };
@@ -1349,7 +1349,7 @@ template <int MT, int CB>
 void launch_wgrad_tiled(const WgradTiled& p, const ConvIn& in, int ho, int wo, const uint16_t* dz, int coutp,
                         float* partial, float* bpart, hipStream_t st)
 {
-    constexpr int TH = CB == 64 ? 2 : 4;
+    constexpr int TH = 4;
     hipLaunchKernelGGL((conv_wgrad_tiled_kernel<MT, CB, TH>), dim3(p.cols, in.n * p.bands, p.cblocks),
                        dim3(kThreads), 0, st, in, ho, wo, dz, coutp, p.rows, p.bands, partial, bpart);
 }
@@ -1362,10 +1362,8 @@ void launch_wgrad_tiled_mt(const WgradTiled& p, const ConvIn& in, int ho, int wo
         launch_wgrad_tiled<MT, 8>(p, in, ho, wo, dz, coutp, partial, bpart, st);
     else if (p.cb == 16)
         launch_wgrad_tiled<MT, 16>(p, in, ho, wo, dz, coutp, partial, bpart, st);
-    else if (p.cb == 32 || MT == 4)
-        launch_wgrad_tiled<MT, 32>(p, in, ho, wo, dz, coutp, partial, bpart, st);
     else
-        launch_wgrad_tiled<MT, (MT <= 2 ? 64 : 32)>(p, in, ho, wo, dz, coutp, partial, bpart, st);
+        launch_wgrad_tiled<MT, 32>(p, in, ho, wo, dz, coutp, partial, bpart, st);
 }
 
 vdbc_status conv_wgrad(const ConvIn& in, int stride, const uint16_t* dz, int coutp, int cout, float* dw,

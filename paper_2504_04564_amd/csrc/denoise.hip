@@ -1297,7 +1297,9 @@ int wgrad_mt(int cout) { return cout <= 16 ? 1 : cout <= 32 ? 2 : 4; }
 // CB (8, 16 or 32; blocks of 64 channels with two rows per step measured
 // 1 % slower), TH rows per step, and output rows per chunk halved from 64
 // (down to TH) while the launch would have fewer than kWgTiledGroups
-// workgroups.  `ok` is false for stride 2 and for launches past the grid's
+// workgroups (targets of 256 or 1024 were 5-7 % slower per training step:
+// fewer workgroups fill the chip less, more write more partials).  `ok` is
+// false for stride 2 and for launches past the grid's
 // y and z limits; those take conv_wgrad_kernel.
 constexpr uint64_t kWgTiledGroups = 512;
 

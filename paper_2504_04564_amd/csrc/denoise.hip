@@ -738,6 +738,24 @@ __global__ void transpose_weights_kernel(const uint16_t* __restrict__ w, int cin
     wt[i] = co < cout ? w[((int64_t)co * 9 + tap) * cin + c] : (uint16_t)0;
 }
 
+// The transposes of up to five layers in one launch (a training step's data
+// gradients): workgroup y takes layer y.
+struct WtJobs {
+    const uint16_t* w[5];
+    uint16_t* wt[5];
+    int cin[5], cout[5], coutp[5];
+};
+
+__global__ void transpose_weights_many_kernel(WtJobs j)
+{
+    const int l = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= j.cin[l] * 9 * j.coutp[l]) return;
+    const int coutp = j.coutp[l], cin = j.cin[l];
+    const int co = i % coutp, tap = (i / coutp) % 9, c = i / (9 * coutp);
+    j.wt[l][i] = co < j.cout[l] ? j.w[l][((int64_t)co * 9 + tap) * cin + c] : (uint16_t)0;
+}
+
 // ---------------------------------------------------------------- weight gradient
 // partial[chunk][co][k] = sum over the chunk's output pixels p of
 // dz[p][co] * A[p][k] with A the forward operand (k = tap * cin + ci).
@@ -1208,7 +1226,7 @@ DgradOut relu_out(float* dx, int split, uint16_t* dz, int dz_stride, const uint1
 
 vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, int wo, const uint16_t* w,
                        int cin, int stride, int hv, int wv, const DgradOut& out_in, uint16_t* wt,
-                       hipStream_t st)
+                       hipStream_t st, bool wt_ready = false)
 {
     if (out_in.split % 4) return fail(VDBC_E_INVALID, "data gradient: split must be a multiple of 4");
     DgradOut out = out_in;
@@ -1218,8 +1236,9 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
                                             al8(out.y) && al8(out.dz) && out.y_stride % 4 == 0 &&
                                             out.dz_stride % 4 == 0);
     out.vec = fp_ok && bf_ok;
-    hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks((uint64_t)cin * 9 * coutp)), dim3(kThreads), 0, st,
-                       w, cin, cout, coutp, wt);
+    if (!wt_ready)
+        hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks((uint64_t)cin * 9 * coutp)), dim3(kThreads), 0, st,
+                           w, cin, cout, coutp, wt);
     const uint64_t Q = (uint64_t)n * hv * wv;
     const unsigned gb = blocks(Q, 64 * kConvTiles);
     const unsigned tiles_y = (unsigned)((hv + kFwdTH - 1) / kFwdTH);
@@ -1455,7 +1474,7 @@ NetLayout net_layout(uint32_t n, uint32_t h, uint32_t w, bool training)
         L.dz3 = take(Ph * 64 * 2);
         L.dz2 = take(Ph * 64 * 2);
         L.dz1 = take(P * 32 * 2);
-        L.wt = take(64 * 9 * 64 * 2);
+        L.wt = take(5 * 64 * 9 * 64 * 2);   // transposed weights of the five data gradients
         L.partial = take(net_partial_floats(n, h, w) * 4);
         L.lpart = take((P + kThreads - 1) / kThreads * 4 + 16);
         L.grad = take(nn::param_count() * 4);
@@ -1600,38 +1619,55 @@ extern "C" vdbc_status vdbc_denoise_train_step(float* params, uint16_t* wbf16, f
     uint16_t *c1 = U(L.c1), *c2 = U(L.c2), *c3 = U(L.c3), *c4 = U(L.c4), *c5 = U(L.c5);
     float* part = F(L.partial);
     const uint64_t pf = net_partial_floats(N, H, W);
+    // the five layers' transposed weights in one launch
     uint16_t* wt = U(L.wt);
+    auto WT = [&](int l) { return wt + (size_t)l * 64 * 9 * 64; };
+    {
+        WtJobs j{};
+        const int lay[5] = {5, 4, 3, 2, 1}, cin_[5] = {32, 64, 64, 64, 32}, cout_[5] = {3, 32, 32, 64, 64},
+                  coutp_[5] = {8, 32, 32, 64, 64};
+        for (int i = 0; i < 5; ++i) {
+            j.w[i] = Wl(lay[i]);
+            j.wt[i] = WT(i);
+            j.cin[i] = cin_[i];
+            j.cout[i] = cout_[i];
+            j.coutp[i] = coutp_[i];
+        }
+        hipLaunchKernelGGL(transpose_weights_many_kernel, dim3(blocks(64 * 9 * 64), 5), dim3(kThreads), 0, st, j);
+        if ((s = check("weight transposes"))) return s;
+    }
     // c6: 32 -> 3 (dz6 padded to 8 channels)
     if ((s = conv_wgrad(ConvIn{c5, nullptr, 32, 0, 0, N, H, W}, 1, U(L.dz6), 8, 3, gW(5), gB(5), part, pf, st))) return s;
     if ((s = conv_dgrad(U(L.dz6), 8, 3, N, H, W, Wl(5), 32, 1, H, W, relu_out(nullptr, 0, U(L.dz5), 32, c5, 32),
-                        wt, st)))
+                        WT(0), st, true)))
         return s;
     // c5: concat(c1, c4) 64 -> 32
     if ((s = conv_wgrad(ConvIn{c1, c4, 32, 32, 0, N, H, W}, 1, U(L.dz5), 32, 32, gW(4), gB(4), part, pf, st))) return s;
     // channels 0..31 of the concat belong to c1 (FP32, added to c2's data
     // gradient below), channels 32..63 to c4 (ReLU backward into dz4)
     if ((s = conv_dgrad(U(L.dz5), 32, 32, N, H, W, Wl(4), 64, 1, H, W, relu_out(F(L.dcat), 32, U(L.dz4), 32, c4, 32),
-                        wt, st)))
+                        WT(1), st, true)))
         return s;
     // c4: up2(c3) 64 -> 32
     if ((s = conv_wgrad(ConvIn{c3, nullptr, 64, 0, 1, N, H / 2, W / 2}, 1, U(L.dz4), 32, 32, gW(3), gB(3), part, pf,
                         st)))
         return s;
     // the upsample's backward (2 x 2 sums) and c3's ReLU backward in the epilogue
-    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, pool_out(U(L.dz3), 64, c3, 64), wt, st)))
+    if ((s = conv_dgrad(U(L.dz4), 32, 32, N, H, W, Wl(3), 64, 1, H, W, pool_out(U(L.dz3), 64, c3, 64), WT(2), st,
+                        true)))
         return s;
     // c3: 64 -> 64 at half resolution
     if ((s = conv_wgrad(ConvIn{c2, nullptr, 64, 0, 0, N, H / 2, W / 2}, 1, U(L.dz3), 64, 64, gW(2), gB(2), part, pf,
                         st)))
         return s;
     if ((s = conv_dgrad(U(L.dz3), 64, 64, N, H / 2, W / 2, Wl(2), 64, 1, H / 2, W / 2,
-                        relu_out(nullptr, 0, U(L.dz2), 64, c2, 64), wt, st)))
+                        relu_out(nullptr, 0, U(L.dz2), 64, c2, 64), WT(3), st, true)))
         return s;
     // c2: 32 -> 64, stride 2
     if ((s = conv_wgrad(ConvIn{c1, nullptr, 32, 0, 0, N, H, W}, 2, U(L.dz2), 64, 64, gW(1), gB(1), part, pf, st)))
         return s;
     if ((s = conv_dgrad(U(L.dz2), 64, 64, N, H / 2, W / 2, Wl(1), 32, 2, H, W,
-                        relu_out(nullptr, 0, U(L.dz1), 32, c1, 32, F(L.dcat), 32), wt, st)))
+                        relu_out(nullptr, 0, U(L.dz1), 32, c1, 32, F(L.dcat), 32), WT(4), st, true)))
         return s;
     // c1: 8 -> 32 (no data gradient needed)
     if ((s = conv_wgrad(ConvIn{x, nullptr, 8, 0, 0, N, H, W}, 1, U(L.dz1), 32, 32, gW(0), gB(0), part, pf, st)))

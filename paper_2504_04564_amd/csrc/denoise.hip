@@ -876,14 +876,15 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
         }
 }
 
-// Stride-1 weight gradient on two-dimensional output tiles, every tap at
+// Weight gradient (stride S = 1 or 2) on two-dimensional output tiles, every tap at
 // once: a workgroup owns a chunk of kWgTW output columns by `rows` output
 // rows of one image and a block of CB input channels, and walks it TH
 // rows at a time.  Each step stages the dz rows and the input rows it needs
-// (TH + 2 rows with the halo) in LDS once, channel-major so that the
+// (S * TH + 3 - S rows with the halo) in LDS once, channel-major so that the
 // eight consecutive pixels an MFMA operand fragment takes are one 16-byte
-// read; the input is stored three times, shifted by one pixel each, so the
-// three horizontal taps read aligned vectors.  The contraction runs over the
+// read; the input is stored three times, one copy per horizontal tap kx
+// holding the input columns S * x + kx - 1 of output columns x, so that
+// every tap reads aligned vectors.  The contraction runs over the
 // 32 pixels of one output row per MFMA; M = co (MT tiles of 16), N = the
 // 9 * CB (tap, channel) columns of the block, spread over the four waves
 // column tile by column tile.  Partials and bias partials have the layout
@@ -891,19 +892,21 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_kernel(ConvIn in, int str
 // follows; the workgroups of channel block 0 sum the bias partials.
 constexpr int kWgTW = 32;
 
-template <int MT, int CB, int TH>
+template <int MT, int CB, int TH, int S>
 __global__ __launch_bounds__(kThreads) void conv_wgrad_tiled_kernel(ConvIn in, int ho, int wo,
                                                                     const uint16_t* __restrict__ dz, int coutp,
                                                                     int rows, int bands,
                                                                     float* __restrict__ partial,
                                                                     float* __restrict__ bpart)
 {
-    constexpr int IH = TH + 2, Q = kWgTW / 8;                 // staged input rows; 8-pixel groups per row
+    // staged input rows (S * TH + 3 - S for stride S); 8-pixel groups per row;
+    // input pixels an item of eight output columns reads
+    constexpr int IH = S * TH + 3 - S, Q = kWgTW / 8, NP = 7 * S + 3;
     constexpr int TCT = (9 * CB + 15) / 16, NCT = (TCT + 3) / 4;   // column tiles: all, per wave
     // channel strides padded to an odd number of 16-byte units, so that the
     // 16 channels an operand fetch reads start in different banks
     constexpr int SI = IH * Q + 1, SD = TH * Q + 1;
-    __shared__ uint4 s_in[3 * CB * SI];                       // [kx][c][iy][q]: pixels x0 + 8q + kx - 1 + j
+    __shared__ uint4 s_in[3 * CB * SI];   // [kx][c][iy][q]: input column S * (x0 + 8q + j) + kx - 1, j < 8
     __shared__ uint4 s_dz[MT * 16 * SD];                      // [co][oy][q]
     const int cin = in.ca + in.cb, K = 9 * cin;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, r = lane & 15;
@@ -933,24 +936,24 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_tiled_kernel(ConvIn in, i
         return (ch & 1) ? w >> 16 : w & 0xFFFFu;
     };
     for (int y0 = band * rows; y0 < y_end; y0 += TH) {
-        // input rows y0 - 1 .. y0 + TH: item (q, iy, channel group), so that
+        // input rows S * y0 - 1 .. : item (q, iy, channel group), so that
         // neighbouring threads write neighbouring 16-byte units
         for (int e = tid; e < IH * Q * (CB / 8); e += kThreads) {
             const int q = e % Q, iy = (e / Q) % IH, cg = e / (Q * IH);
-            const int c8 = cb0 + 8 * cg, y = y0 - 1 + iy, xb = x0 + 8 * q - 1;
-            uint4 px[10];
+            const int c8 = cb0 + 8 * cg, y = S * y0 - 1 + iy, xb = S * (x0 + 8 * q) - 1;
+            uint4 px[NP];
 #pragma unroll
-            for (int m = 0; m < 10; ++m)
+            for (int m = 0; m < NP; ++m)
                 px[m] = c8 < cin ? __builtin_bit_cast(uint4, gather8(in, n, y, xb + m, c8)) : make_uint4(0, 0, 0, 0);
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx)
 #pragma unroll
                 for (int ch = 0; ch < 8; ++ch) {
                     uint4 v;
-                    v.x = half(px[kx + 0], ch) | half(px[kx + 1], ch) << 16;
-                    v.y = half(px[kx + 2], ch) | half(px[kx + 3], ch) << 16;
-                    v.z = half(px[kx + 4], ch) | half(px[kx + 5], ch) << 16;
-                    v.w = half(px[kx + 6], ch) | half(px[kx + 7], ch) << 16;
+                    v.x = half(px[kx], ch) | half(px[S + kx], ch) << 16;
+                    v.y = half(px[2 * S + kx], ch) | half(px[3 * S + kx], ch) << 16;
+                    v.z = half(px[4 * S + kx], ch) | half(px[5 * S + kx], ch) << 16;
+                    v.w = half(px[6 * S + kx], ch) | half(px[7 * S + kx], ch) << 16;
                     s_in[(kx * CB + 8 * cg + ch) * SI + iy * Q + q] = v;
                 }
         }
@@ -992,7 +995,7 @@ __global__ __launch_bounds__(kThreads) void conv_wgrad_tiled_kernel(ConvIn in, i
 #pragma unroll
             for (int i = 0; i < NCT; ++i) {
                 if (!bval[i]) continue;   // uniform per wave
-                const bf16x8 B = boff[i] >= 0 ? __builtin_bit_cast(bf16x8, s_in[boff[i] + oy * Q]) : zero8();
+                const bf16x8 B = boff[i] >= 0 ? __builtin_bit_cast(bf16x8, s_in[boff[i] + S * oy * Q]) : zero8();
 #pragma unroll
                 for (int t = 0; t < MT; ++t) acc[t][i] = mfma(A[t], B, acc[t][i]);
             }
@@ -1312,13 +1315,13 @@ vdbc_status conv_dgrad(const uint16_t* dz, int coutp, int cout, int n, int ho, i
 // its partial rows are 64 apart).
 int wgrad_mt(int cout) { return cout <= 16 ? 1 : cout <= 32 ? 2 : 4; }
 
-// Launch plan of the tiled stride-1 weight-gradient kernel: channel block
+// Launch plan of the tiled weight-gradient kernel: channel block
 // CB (8, 16 or 32; blocks of 64 channels with two rows per step measured
 // 1 % slower), TH rows per step, and output rows per chunk halved from 64
 // (down to TH) while the launch would have fewer than kWgTiledGroups
 // workgroups (targets of 256 or 1024 were 5-7 % slower per training step:
-// fewer workgroups fill the chip less, more write more partials).  `ok` is
-// false for stride 2 and for launches past the grid's
+// fewer workgroups fill the chip less, more write more partials); stride 2
+// takes two output rows per step.  `ok` is false for launches past the grid's
 // y and z limits; those take conv_wgrad_kernel.
 constexpr uint64_t kWgTiledGroups = 512;
 
@@ -1332,9 +1335,10 @@ WgradTiled wgrad_tiled_plan(const ConvIn& in, int stride, int cout)
 {
     WgradTiled p{};
     const int cin = in.ca + in.cb;
-    const int ho = in.up ? 2 * in.hs : in.hs, wo = in.up ? 2 * in.ws : in.ws;
+    const int hv = in.up ? 2 * in.hs : in.hs, wv = in.up ? 2 * in.ws : in.ws;
+    const int ho = (hv - 1) / stride + 1, wo = (wv - 1) / stride + 1;
     p.cb = cin <= 8 ? 8 : cin <= 16 ? 16 : 32;
-    p.th = 4;
+    p.th = stride == 1 ? 4 : 2;
     p.cols = (wo + kWgTW - 1) / kWgTW;
     p.cblocks = (cin + p.cb - 1) / p.cb;
     auto groups = [&](int rows) { return (uint64_t)in.n * ((ho + rows - 1) / rows) * p.cols * p.cblocks; };
@@ -1342,7 +1346,7 @@ WgradTiled wgrad_tiled_plan(const ConvIn& in, int stride, int cout)
     while (p.rows > p.th && groups(p.rows) < kWgTiledGroups) p.rows /= 2;
     p.bands = (ho + p.rows - 1) / p.rows;
     p.chunks = (uint64_t)in.n * p.bands * p.cols;
-    p.ok = stride == 1 && (uint64_t)in.n * p.bands <= 65535u && p.cblocks <= 65535;
+    p.ok = (stride == 1 || stride == 2) && (uint64_t)in.n * p.bands <= 65535u && p.cblocks <= 65535;
     return p;
 }
 
@@ -1370,9 +1374,13 @@ template <int MT, int CB>
 void launch_wgrad_tiled(const WgradTiled& p, const ConvIn& in, int ho, int wo, const uint16_t* dz, int coutp,
                         float* partial, float* bpart, hipStream_t st)
 {
-    constexpr int TH = 4;
-    hipLaunchKernelGGL((conv_wgrad_tiled_kernel<MT, CB, TH>), dim3(p.cols, in.n * p.bands, p.cblocks),
-                       dim3(kThreads), 0, st, in, ho, wo, dz, coutp, p.rows, p.bands, partial, bpart);
+    const dim3 grid(p.cols, in.n * p.bands, p.cblocks);
+    if (p.th == 4)   // stride 1
+        hipLaunchKernelGGL((conv_wgrad_tiled_kernel<MT, CB, 4, 1>), grid, dim3(kThreads), 0, st, in, ho, wo, dz,
+                           coutp, p.rows, p.bands, partial, bpart);
+    else             // stride 2, two output rows per step
+        hipLaunchKernelGGL((conv_wgrad_tiled_kernel<MT, CB, 2, 2>), grid, dim3(kThreads), 0, st, in, ho, wo, dz,
+                           coutp, p.rows, p.bands, partial, bpart);
 }
 
 template <int MT>
@@ -1706,12 +1714,15 @@ extern "C" vdbc_status vdbc_conv3x3_grad_workspace(uint32_t cin, uint32_t cout, 
     if (!bytes || cin == 0 || cin > 64 || cout == 0 || cout > 64) return fail(VDBC_E_INVALID, "bad argument");
     const uint64_t P = (uint64_t)n * ho * wo;
     const uint64_t c = wgrad_chunk(P, 9 * (int)cin), chunks = (P + c - 1) / c;
-    // the tiled stride-1 kernel's chunks for the same output (any cout)
+    // the tiled kernel's chunks for the same output (any cout, stride 1 or 2)
     uint64_t tiled = 0;
     for (int mt_cout : {16, 32, 64}) {
-        const WgradTiled tp = wgrad_tiled_plan(ConvIn{nullptr, nullptr, (int)cin, 0, 0, (int)n, (int)ho, (int)wo},
+        const WgradTiled t1 = wgrad_tiled_plan(ConvIn{nullptr, nullptr, (int)cin, 0, 0, (int)n, (int)ho, (int)wo},
                                                1, mt_cout);
-        tiled = tp.chunks > tiled ? tp.chunks : tiled;
+        const WgradTiled t2 = wgrad_tiled_plan(
+            ConvIn{nullptr, nullptr, (int)cin, 0, 0, (int)n, 2 * (int)ho, 2 * (int)wo}, 2, mt_cout);
+        tiled = t1.chunks > tiled ? t1.chunks : tiled;
+        tiled = t2.chunks > tiled ? t2.chunks : tiled;
     }
     *bytes = al(64ull * 9 * 64 * 2) + al((chunks > tiled ? chunks : tiled) * (64ull * 9 * cin + 64) * 4);
     return VDBC_OK;

@@ -43,7 +43,8 @@ CONV_CASES = [  # (ca, cb, up, stride, cout, n, hs, ws)
     (32, 0, 0, 1, 3, 1, 17, 19),
     (32, 0, 0, 1, 40, 1, 12, 15),   # 33..48 output channels take the four-tile kernel
     (16, 8, 0, 1, 20, 1, 9, 70),    # 24 input channels in a 32-channel block, three 32-column tiles
-    (40, 8, 1, 1, 16, 1, 5, 9),     # 48 input channels in a 64-channel block, upsampled
+    (40, 8, 1, 1, 16, 1, 5, 9),     # 48 input channels in two 32-channel blocks, upsampled
+    (16, 8, 1, 2, 24, 2, 7, 9),     # stride 2 through an upsampled concat, odd sizes
 ]
 
 
@@ -90,18 +91,19 @@ def test_conv_gradients(ca, cb, up, stride, cout, n, hs, ws):
     assert rel(db.cpu().numpy(), rdb) <= 1e-5
 
 
-# Sizes at which a weight-gradient partial covers more than the smallest
-# pixel chunk: 64 input channels over 257 x 511 pixels (partials of 512
-# pixels, eight LDS stages each, the last partial ragged) and the first
-# layer's 8 input channels at batch 8 x 512^2 (partials of 2048 pixels).
-WGRAD_LARGE = [(64, 0, 0, 1, 64, 1, 257, 511), (8, 0, 0, 1, 32, 8, 512, 512)]
+# Sizes at which a weight-gradient chunk spans many rows of its band: 64
+# input channels over 257 x 511 pixels (two channel blocks, ragged last
+# band and column tile), the first layer's 8 input channels at batch
+# 8 x 512^2, and the stride-2 layer at batch 8 from 256 x 255 (odd width).
+WGRAD_LARGE = [(64, 0, 0, 1, 64, 1, 257, 511), (8, 0, 0, 1, 32, 8, 512, 512), (32, 0, 0, 2, 64, 8, 256, 255)]
 
 
 @pytest.mark.parametrize("ca,cb,up,stride,cout,n,hs,ws", WGRAD_LARGE)
 def test_conv_weight_gradient_large(ca, cb, up, stride, cout, n, hs, ws):
     rng = np.random.default_rng(ca + cout + hs)
     a, a64 = _bf(rng, (n, hs, ws, ca))
-    dz_np = rng.normal(size=(n, hs, ws, cout)).astype(np.float32)
+    ho, wo = (hs - 1) // stride + 1, (ws - 1) // stride + 1
+    dz_np = rng.normal(size=(n, ho, wo, cout)).astype(np.float32)
     dz = torch.from_numpy(dz_np).to(torch.bfloat16)
     dz64 = dz.to(torch.float64).numpy()
     dw, db = vdbc.conv3x3_wgrad(a, None, up, stride, dz.cuda(), cout)

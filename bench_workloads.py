@@ -208,8 +208,7 @@ def batch(args, torch, vdbc, synth, scenes, log):
         items.append(dict(grid=g, camera=scenes.orbit_camera(g.dims, 256, 256, azimuth_deg=7.0 * i),
                           medium=med, spp=spp, max_bounces=8, seed=0xB00 + i, frame=0))
     rays = sum(256 * 256 * it["spp"] for it in items)
-    best, allr = autotune.tune_batch(items, dict(macrocell=(8, 16), tile_w=(8, 16),
-                                                 blocks_per_cu=(2, 4, 8), persistent=(1,)), reps=3)
+    best, allr = autotune.tune_batch(items, autotune.BATCH_SPACE, reps=3)
     log(f"[batch] tuned: {best}")
     t_best = dict(best)
     t_best.pop("ms")

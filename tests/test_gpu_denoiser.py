@@ -253,3 +253,36 @@ def test_trained_denoiser_beats_the_plain_render():
     assert e["relmse_denoised"] < e["relmse_plain_lo"]
     assert e["relmse_denoised"] <= e["relmse_plain_hi"], e
     assert e["ms_denoised_pipeline"] < e["ms_plain_hi"], e
+
+
+def test_conv_outputs_at_unaligned_addresses():
+    # outputs that are not 16-byte (FP32) or 8-byte (BF16) aligned take the
+    # staged epilogues' element-by-element stores; results as at aligned ones
+    import ctypes as C
+    L = vdbc._nn()
+    rng = np.random.default_rng(91)
+    n, h, w, cin, cout = 1, 12, 40, 32, 32
+    a, a64 = _bf(rng, (n, h, w, cin))
+    wt, w64 = _bf(rng, (cout, 3, 3, cin), 0.2)
+    bias = torch.from_numpy(rng.normal(size=cout).astype(np.float32)).cuda()
+    want = vdbc.conv3x3(a, None, 0, 1, wt, bias, cout, relu=True)
+    raw = torch.zeros(n * h * w * cout + 8, dtype=torch.bfloat16, device="cuda")
+    ptr = raw.data_ptr() + 2   # 2-byte aligned only
+    assert L.vdbc_conv3x3(a.data_ptr(), cin, None, 0, 0, n, h, w, 1, wt.data_ptr(), bias.data_ptr(), cout, 1,
+                          C.c_void_p(ptr), None, vdbc._stream()) == 0
+    torch.cuda.synchronize()
+    got = raw[1:1 + n * h * w * cout].view(n, h, w, cout)
+    assert torch.equal(got.view(torch.int16), want.view(torch.int16))
+    # data gradient into an FP32 buffer offset by one float
+    dz_np = rng.normal(size=(n, h, w, cout)).astype(np.float32)
+    dz = torch.from_numpy(dz_np).to(torch.bfloat16).cuda()
+    ref = vdbc.conv3x3_dgrad(dz, cout, wt, cin, 1, h, w)
+    ws = C.c_uint64(0)
+    assert L.vdbc_conv3x3_grad_workspace(cin, cout, n, h, w, C.byref(ws)) == 0
+    buf, wptr = vdbc._aligned_empty(int(ws.value), dz.device)
+    dxr = torch.zeros(n * h * w * cin + 4, dtype=torch.float32, device="cuda")
+    assert L.vdbc_conv3x3_dgrad(dz.data_ptr(), cout, cout, n, h, w, wt.data_ptr(), cin, 1, h, w,
+                                C.c_void_p(dxr.data_ptr() + 4), wptr, int(ws.value), vdbc._stream()) == 0
+    torch.cuda.synchronize()
+    got_dx = dxr[1:1 + n * h * w * cin].view(n, h, w, cin)
+    assert torch.equal(got_dx, ref)

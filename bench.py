@@ -384,19 +384,31 @@ def main():
     cam = scenes.orbit_camera(dims, W, H)
     med = scenes.pt_medium(64.0)
     C = args.macrocell
+    # the timed frames run the kernels without counters; one more frame with
+    # them (the same paths: the image must be bit-identical) gives the
+    # trilinear samples and path segments per frame
     prm = dict(spp=spp, max_bounces=bounces, seed=S["seed"], macrocell=C,
-               tile_w=DEFAULT_TILE_W[args.workload],
-               flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
+               tile_w=DEFAULT_TILE_W[args.workload], flags=vdbc.RENDER_KEEP_MAJORANT)
+    prm_count = dict(prm, flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
     rays = W * H * spp
+
+    def counted(field, timed_image, **kw):
+        r = vdbc.Renderer(field, cam, med, prm_count, vdbc.MODE_PT, **kw)
+        r.build_majorant()
+        r.launch()
+        torch.cuda.synchronize()
+        if not torch.equal(r.image.view(torch.int32), timed_image.view(torch.int32)):
+            raise RuntimeError("the counting launch rendered another image")
+        return r.sample_count(), r.segment_count()
 
     r_vdb = vdbc.Renderer(grid, cam, med, prm, vdbc.MODE_PT)
     ms_step, maj_ms, pt_ms = time_frames(torch, r_vdb, args.steps, args.warmup)
-    samples = r_vdb.sample_count()
+    samples, segments = counted(grid, r_vdb.image)
     img = r_vdb.image.cpu().numpy().reshape(-1, 4)
     del r_vdb
     vdb_mrays = rays / (ms_step * 1e-3) / 1e6
     log(f"[bench] VDB PT: {ms_step:.2f} ms/frame (majorant {maj_ms:.2f} ms, PT {pt_ms:.2f} ms), "
-        f"{vdb_mrays:.1f} Mrays/s, {samples / 1e6:.1f} M samples/frame")
+        f"{vdb_mrays:.1f} Mrays/s, {samples / 1e6:.1f} M samples and {segments / 1e6:.1f} M segments/frame")
 
     extras = {}
     if not args.no_extras and vol is not None:
@@ -406,7 +418,7 @@ def main():
         log(f"[bench] dense array uploaded in {time.time() - t:.1f}s")
         r_d = vdbc.Renderer(dense, cam, med, prm, vdbc.MODE_PT, background=0.0)
         d_step, d_maj, d_pt = time_frames(torch, r_d, args.steps, args.warmup)
-        d_samples = r_d.sample_count()
+        d_samples, d_segments = counted(dense, r_d.image, background=0.0)
         del r_d
         dense_mrays = rays / (d_step * 1e-3) / 1e6
         log(f"[bench] dense PT: {d_step:.2f} ms/frame (majorant {d_maj:.2f} ms, PT {d_pt:.2f} ms), "
@@ -431,6 +443,10 @@ def main():
             "vdb_over_dense_mrays": round(vdb_mrays / dense_mrays, 4),
             "dense_ms_per_step": round(d_step, 4),
             "dense_majorant_ms": round(d_maj, 4),
+            "segments_per_s": {   # camera + shadow + scattered rays per second of frame
+                "vdb_render": round(segments / (ms_step * 1e-3), 1),
+                "dense_render": round(d_segments / (d_step * 1e-3), 1),
+            },
             "samples_per_s": {
                 "vdb_render": round(samples / (pt_ms * 1e-3), 1),
                 "dense_render": round(d_samples / (d_pt * 1e-3), 1),
@@ -512,7 +528,8 @@ def main():
                          "valu_lane_utilisation": prof["valu_lane_utilisation"],
                          "l2_hit_rate": prof["l2_hit_rate"],
                          "source": os.path.relpath(prof_path, ROOT)} if prof else None),
-            "per_launch": {"samples": int(samples), "bytes_per_sample": BYTES_PER_RENDER_SAMPLE,
+            "per_launch": {"samples": int(samples), "segments": int(segments),
+                           "bytes_per_sample": BYTES_PER_RENDER_SAMPLE,
                            "algorithmic_bytes": int(samples * BYTES_PER_RENDER_SAMPLE),
                            "avg_ms": round(pt_ms, 4)},
         },

@@ -277,6 +277,8 @@ typedef struct {
  *             the render call itself)
  *   [8, 16)   uint64 majorant cells visited by the path tracer's DDA (same flag)
  *   [16, 20)  uint32 path tracer tile queue (zeroed by the render call)
+ *   [24, 32)  uint64 path segments the path tracer began: camera, shadow and
+ *             scattered rays (VDBC_RENDER_COUNT)
  *   [256, ..) float32 majorant grid ceil(n/macrocell)^3, x-fastest */
 vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d, uint64_t* bytes);
 

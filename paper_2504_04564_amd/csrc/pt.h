@@ -243,7 +243,8 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                                         const float* __restrict__ maj, const uint32_t* cbits,
                                         int bx, int by, TileShared& ts, const float4* tf_lds,
                                         float* __restrict__ image,
-                                        float* __restrict__ aov, uint32_t& nsamp, uint32_t& ncell)
+                                        float* __restrict__ aov, uint32_t& nsamp, uint32_t& ncell,
+                                        uint32_t& nseg)
 {
     const int tid = threadIdx.x;
     const int tw = g.tw, th = 64 / g.tw;
@@ -287,6 +288,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
             L0 = L1 = L2 = 0.0f;
             b0 = b1 = b2 = 1.0f;
             flight_begin(f, g, nx, ny, nz, o, d, t0p);
+            ++nseg;   // camera ray
         }
         const int tentative = flight_advance(f, maj, cbits, g, rng, ncell);
         if (tentative == kFlightYield) continue;
@@ -318,6 +320,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                 rng.init(k0, g.seed_hi, smp, (uint32_t)b, 1u, g.frame);
                 float t0s;
                 flight_begin(f, g, nx, ny, nz, x, m.light, t0s);
+                ++nseg;   // shadow ray
                 shadow = true;
             } else {
                 float e0, e1, e2;
@@ -372,6 +375,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
             const float d[3] = {r * __cosf(phi), r * __sinf(phi), z};
             float t0n;
             flight_begin(f, g, nx, ny, nz, o, d, t0n);
+            ++nseg;   // scattered ray
         }
         if (path_done) {
             atomicAdd(reinterpret_cast<unsigned long long*>(&ts.rgb[q][0]), (unsigned long long)to_fixed(L0));
@@ -421,7 +425,7 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
     __syncthreads();
     Acc acc{view};
     acc.reset();
-    uint32_t nsamp = 0, ncell = 0;
+    uint32_t nsamp = 0, ncell = 0, nseg = 0;
     // persistent workgroups take tiles in raster order from a queue, so a
     // workgroup that drew cheap tiles goes on to the next one at once
     __shared__ uint32_t s_tile;
@@ -433,11 +437,12 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
         const uint32_t t = s_tile;   // pt_tile's barriers order this read before the next write
         if (t >= tiles) break;
         pt_tile<Acc, AOV, ENV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
-                          (int)(t / tiles_x), ts, tf_lds, image, aov, nsamp, ncell);
+                          (int)(t / tiles_x), ts, tf_lds, image, aov, nsamp, ncell, nseg);
     }
     if (COUNT) {
         block_count(nsamp, counter);
         block_count(ncell, counter + 1);
+        block_count(nseg, counter + 3);
     }
 }
 
@@ -486,10 +491,10 @@ __global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __
         __syncthreads();
         VdbAcc acc{D->view};
         acc.reset();
-        uint32_t ns = 0, nc = 0;
+        uint32_t ns = 0, nc = 0, nsg = 0;
         pt_tile<VdbAcc, false, true>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
                                (int)(tile % (uint32_t)D->tiles_x), (int)(tile / (uint32_t)D->tiles_x), ts,
-                               tf_lds, D->image, nullptr, ns, nc);
+                               tf_lds, D->image, nullptr, ns, nc, nsg);
     }
 }
 

@@ -9,10 +9,11 @@
 
 namespace vdbc {
 
-// Clears the workspace's counters: sample and cell counts, PT tile queue.
+// Clears the workspace's counters: sample and cell counts, PT tile queue,
+// path segment count.
 __global__ void zero_u64(unsigned long long* p)
 {
-    if (threadIdx.x < 3 && blockIdx.x == 0) p[threadIdx.x] = 0ull;
+    if (threadIdx.x < 4 && blockIdx.x == 0) p[threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------- majorant

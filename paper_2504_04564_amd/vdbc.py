@@ -431,6 +431,12 @@ class Renderer:
         torch = _torch()
         return int(self.ws[self.ws_off + 8:self.ws_off + 16].view(torch.int64).item())
 
+    def segment_count(self) -> int:
+        """Path segments (camera, shadow and scattered rays) of the last
+        path-traced launch with RENDER_COUNT."""
+        torch = _torch()
+        return int(self.ws[self.ws_off + 24:self.ws_off + 32].view(torch.int64).item())
+
     def majorant(self):
         torch = _torch()
         C_ = self.prm.macrocell

@@ -477,6 +477,33 @@ def test_pt_sample_count_and_ragged_image():
     assert r.sample_count() > 17 * 5 * 2
 
 
+def test_pt_segment_count():
+    # one bounce: every path has its camera segment and, where that segment
+    # ends in a real collision, one shadow ray; the image's alpha is the
+    # fraction of such paths (exact for 4 spp), so segments = paths + hits
+    v = synth.mid_volume(n=64)
+    buf, _ = vdbc.encode(v, 0.25)
+    g = vdbc.Grid(buf)
+    w, h, spp = 37, 29, 4
+    cam, med, prm = _pt_scene(64, w, h, spp, bounces=1)
+    prm["flags"] = vdbc.RENDER_COUNT
+    r = vdbc.Renderer(g, cam, med, prm, vdbc.MODE_PT)
+    img = r.launch().cpu().numpy().reshape(-1, 4)
+    hits = int(np.rint(img[:, 3] * spp).sum())
+    assert 0 < hits < w * h * spp
+    assert r.segment_count() == w * h * spp + hits
+    # more bounces: between one and 2 * bounces segments per path, the same
+    # count on a second launch
+    cam, med, prm = _pt_scene(64, w, h, spp, bounces=8)
+    prm["flags"] = vdbc.RENDER_COUNT
+    r = vdbc.Renderer(g, cam, med, prm, vdbc.MODE_PT)
+    r.launch()
+    n1 = r.segment_count()
+    r.launch()
+    assert r.segment_count() == n1
+    assert w * h * spp + hits <= n1 <= w * h * spp * 16
+
+
 def test_pt_mid_config_sampled_pixels():
     # the benchmark's launch: 512^3 cloud at 1:10, 1024x1024, 16 spp, 8 bounces;
     # the oracle renders a sample of the pixels one by one

@@ -39,7 +39,7 @@ BRICK = 32                        # brick edge of the encoder (Alg. 1)
 DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16}
 # wave tile width (pixels per wave row) of each frame, the same autotuner's
 # choice; the image does not depend on it
-DEFAULT_TILE_W = {"paper": 32, "mid": 8}
+DEFAULT_TILE_W = {"paper": 64, "mid": 64}
 # committed rocprofv3 counter summaries of pt_kernel<VdbAcc>, one per frame
 PROFILES = {"paper": os.path.join(ROOT, "profiles", "pt_kernel_vdb_paper_1to10.md"),
             "mid": os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")}
@@ -73,7 +73,7 @@ def profile_values(path: str | None = None, launch: str | None = None):
     """Figures of a committed rocprofv3 counter summary of the PT kernel (HBM
     bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the kernel
     sources changed since the counters were taken or (with `launch`, e.g.
-    "macrocell=64 tile_w=32") the summary describes another launch."""
+    "macrocell=64 tile_w=64") the summary describes another launch."""
     path = path or PROFILE
     if not os.path.exists(path):
         return {}

@@ -40,7 +40,7 @@ def sweep(args, torch, vdbc, synth, scenes, log):
     cam = scenes.orbit_camera((nx, ny, nz), W, H)
     med = scenes.pt_medium(64.0)
     # timed without the counters; samples from one more counting launch
-    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C, tile_w=32)
+    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C, tile_w=64)
     rays = W * H * spp
 
     def samples_of(field, **kw):
@@ -51,7 +51,7 @@ def sweep(args, torch, vdbc, synth, scenes, log):
 
     out = {"metric": "paper-scale VDB vs dense path-traced Mrays/s", "unit": "Mrays/s",
            "config": {"workload": "fbm-cloud-1987x1351x2449-pt-1920x1080x64spp-16bounces",
-                      "dims": list(P["dims"]), "macrocell": C, "tile_w": 32}, "rates": []}
+                      "dims": list(P["dims"]), "macrocell": C, "tile_w": 64}, "rates": []}
     for q in P["rates"]:
         t = time.time()
         buf, st = vdbc.encode(vol, q)

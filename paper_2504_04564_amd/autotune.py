@@ -19,7 +19,7 @@ import numpy as np
 
 from . import vdbc
 
-RENDER_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32), "cache": (0, 1, 2)}
+RENDER_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32, 64), "cache": (0, 1, 2)}
 BATCH_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32), "blocks_per_cu": (2, 4, 8),
                "persistent": (1,)}
 

@@ -1,7 +1,7 @@
 """GPU parity at the paper-scale size, in the benchmark's launch: the
 1987 x 1351 x 2449 billowed cloud (26.3 GB dense) at 1:10, the majorant grid
 of the whole volume at macrocell 64, the path tracer at 1920 x 1080 x 64 spp
-with at most 16 bounces and 32-wide wave tiles, and random trilinear samples
+with at most 16 bounces and 64-wide wave tiles, and random trilinear samples
 in the bricks that hold a non-background voxel.  The oracle computes the
 majorant grid (threaded over disjoint cell ranges), a sample of the image's
 pixels one by one and every sample.  Bars as in test_gpu_parity.py."""
@@ -19,7 +19,7 @@ from synth import scenes
 pytestmark = pytest.mark.gpu
 
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
-C, TW = 64, 32
+C, TW = 64, 64
 
 
 def relmse(x, y):

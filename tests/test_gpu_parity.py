@@ -521,10 +521,11 @@ def test_pt_mid_config_sampled_pixels():
     assert np.all(np.isfinite(img))
 
 
-@pytest.mark.parametrize("C,tw", [(16, 8), (64, 32)])
+@pytest.mark.parametrize("C,tw", [(16, 8), (64, 32), (64, 64)])
 def test_pt_paper_launch_configuration_sampled_pixels(C, tw):
     # the paper-scale launch (1920x1080, 64 spp, <= 16 bounces, 1:10; the
-    # benchmark's macrocell 64 and 32-wide wave tiles, and macrocell 16) on
+    # benchmark's macrocell 64 with 64-wide wave tiles, the same cells with
+    # 32-wide tiles, and macrocell 16) on
     # the same billowed recipe at 1/8 of the edge lengths; the oracle renders
     # a sample of the pixels one by one
     P = scenes.PAPER

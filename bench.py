@@ -39,7 +39,7 @@ BRICK = 32                        # brick edge of the encoder (Alg. 1)
 DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16}
 # wave tile width (pixels per wave row) of each frame, the same autotuner's
 # choice; the image does not depend on it
-DEFAULT_TILE_W = {"paper": 64, "mid": 64}
+DEFAULT_TILE_W = {"paper": 64, "mid": 8}
 # committed rocprofv3 counter summaries of pt_kernel<VdbAcc>, one per frame
 PROFILES = {"paper": os.path.join(ROOT, "profiles", "pt_kernel_vdb_paper_1to10.md"),
             "mid": os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")}

@@ -248,7 +248,10 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
 {
     const int tid = threadIdx.x;
     const int tw = g.tw, th = 64 / g.tw;
-    const int x0 = bx * 2 * tw, y0 = by * 2 * th;
+    // the four waves sit side by side in one band of th rows: wave w covers
+    // columns [x0 + w tw, x0 + (w + 1) tw), so the tile is 4 tw x th pixels
+    // (256 x 1 at tw = 64: neighbouring waves trace neighbouring rays)
+    const int x0 = bx * 4 * tw, y0 = by * th;
     ts.rgb[tid][0] = ts.rgb[tid][1] = ts.rgb[tid][2] = 0;
     ts.depth[tid] = 0;
     ts.hits[tid] = ts.escapes[tid] = 0;
@@ -271,8 +274,8 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
             q = (int)(u & (kBlock - 1));
             smp = u >> 8;
             const int w = q >> 6, l = q & 63;
-            px = x0 + (w & 1) * tw + (l % tw);
-            py = y0 + (w >> 1) * th + (l / tw);
+            px = x0 + w * tw + (l % tw);
+            py = y0 + (l / tw);
             if (px >= cam.width || py >= cam.height) {   // no pixel here
                 u = atomicAdd(&ts.next, 1u);
                 continue;
@@ -391,7 +394,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
     __syncthreads();
     {
         const int w = tid >> 6, l = tid & 63;
-        const int qx = x0 + (w & 1) * tw + (l % tw), qy = y0 + (w >> 1) * th + (l / tw);
+        const int qx = x0 + w * tw + (l % tw), qy = y0 + (l / tw);
         if (qx < cam.width && qy < cam.height) {
             const uint32_t pix = (uint32_t)qy * (uint32_t)cam.width + (uint32_t)qx;
             const double sc = 1.0 / (4294967296.0 * (double)g.spp);
@@ -429,8 +432,8 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
     // persistent workgroups take tiles in raster order from a queue, so a
     // workgroup that drew cheap tiles goes on to the next one at once
     __shared__ uint32_t s_tile;
-    const uint32_t tiles_x = (uint32_t)((cam.width + 2 * g.tw - 1) / (2 * g.tw));
-    const uint32_t tiles = tiles_x * (uint32_t)((cam.height + 128 / g.tw - 1) / (128 / g.tw));
+    const uint32_t tiles_x = (uint32_t)((cam.width + 4 * g.tw - 1) / (4 * g.tw));
+    const uint32_t tiles = tiles_x * (uint32_t)((cam.height + 64 / g.tw - 1) / (64 / g.tw));
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1u);
         __syncthreads();

@@ -575,8 +575,8 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     }
     const size_t lds = 4u * (size_t)g.cwords;
     {
-        const uint64_t tiles = (uint64_t)((cam.width + 2 * g.tw - 1) / (2 * g.tw)) *
-                               (uint64_t)((cam.height + 128 / g.tw - 1) / (128 / g.tw));
+        const uint64_t tiles = (uint64_t)((cam.width + 4 * g.tw - 1) / (4 * g.tw)) *
+                               (uint64_t)((cam.height + 64 / g.tw - 1) / (64 / g.tw));
         grid = dim3((unsigned)std::min<uint64_t>(tiles, (uint64_t)device_cus() * kPtBlocksPerCu));
     }
     uint32_t* queue = reinterpret_cast<uint32_t*>(counter + 2);
@@ -818,7 +818,7 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         g.seed_hi = (uint32_t)(it.seed >> 32);
         g.frame = it.frame;
         g.rr = 0;
-        const int tx = (cam.width + 2 * g.tw - 1) / (2 * g.tw), ty = (cam.height + 128 / g.tw - 1) / (128 / g.tw);
+        const int tx = (cam.width + 4 * g.tw - 1) / (4 * g.tw), ty = (cam.height + 64 / g.tw - 1) / (64 / g.tw);
         if ((uint64_t)tx * ty > 0xFFFFFu) return fail(VDBC_E_INVALID, "batch item %u: image too large", i);
         b->views.push_back(v);
         b->cams.push_back(cam);

@@ -39,7 +39,11 @@ BRICK = 32                        # brick edge of the encoder (Alg. 1)
 DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16}
 # wave tile width (pixels per wave row) of each frame, the same autotuner's
 # choice; the image does not depend on it
-DEFAULT_TILE_W = {"paper": 64, "mid": 8}
+DEFAULT_TILE_W = {"paper": 8, "sweep": 8, "mid": 8}
+# samples per work item (each 256-pixel tile split into spp / chunk items that
+# different workgroups run; 0 = one item per tile), the same autotuner's
+# choice; the image does not depend on it
+DEFAULT_CHUNK_SPP = {"paper": 8, "sweep": 8, "mid": 4}
 # committed rocprofv3 counter summaries of pt_kernel<VdbAcc>, one per frame
 PROFILES = {"paper": os.path.join(ROOT, "profiles", "pt_kernel_vdb_paper_1to10.md"),
             "mid": os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")}
@@ -73,7 +77,7 @@ def profile_values(path: str | None = None, launch: str | None = None):
     """Figures of a committed rocprofv3 counter summary of the PT kernel (HBM
     bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the kernel
     sources changed since the counters were taken or (with `launch`, e.g.
-    "macrocell=64 tile_w=64") the summary describes another launch."""
+    "macrocell=64 tile_w=8 chunk_spp=8") the summary describes another launch."""
     path = path or PROFILE
     if not os.path.exists(path):
         return {}
@@ -324,6 +328,8 @@ def main():
         return
     if args.macrocell is None:
         args.macrocell = DEFAULT_MACROCELL.get(args.workload, 16)
+    args.chunk_spp = DEFAULT_CHUNK_SPP.get(args.workload, 0)
+    args.tile_w = DEFAULT_TILE_W.get(args.workload, 8)
     if args.workload not in ("paper", "mid"):
         import bench_workloads
         line = getattr(bench_workloads, args.workload)(args, torch, vdbc, synth, scenes, log)
@@ -388,7 +394,8 @@ def main():
     # them (the same paths: the image must be bit-identical) gives the
     # trilinear samples and path segments per frame
     prm = dict(spp=spp, max_bounces=bounces, seed=S["seed"], macrocell=C,
-               tile_w=DEFAULT_TILE_W[args.workload], flags=vdbc.RENDER_KEEP_MAJORANT)
+               tile_w=args.tile_w, chunk_spp=args.chunk_spp,
+               flags=vdbc.RENDER_KEEP_MAJORANT)
     prm_count = dict(prm, flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
     rays = W * H * spp
 
@@ -490,7 +497,8 @@ def main():
     prof_path = PROFILES[args.workload]
     standard = (args.rate == 0.10 and C == DEFAULT_MACROCELL[args.workload] and
                 (args.workload == "paper" or nx == 512))
-    prof = profile_values(prof_path, f"macrocell={C} tile_w={prm['tile_w']}") if standard else {}
+    prof = profile_values(prof_path, f"macrocell={C} tile_w={prm['tile_w']} chunk_spp={prm['chunk_spp']}") \
+        if standard else {}
     achieved = samples * BYTES_PER_RENDER_SAMPLE / pt_s / 1e9
     line = {
         "metric": METRIC,
@@ -509,7 +517,7 @@ def main():
             "workload": f"{name}-vdb-1:{round(1 / args.rate)}-pt-{W}x{H}x{spp}spp-"
                         f"{bounces}bounces",
             "dims": list(dims), "rate": args.rate, "width": W, "height": H, "spp": spp,
-            "max_bounces": bounces, "macrocell": C, "tile_w": prm["tile_w"],
+            "max_bounces": bounces, "macrocell": C, "tile_w": prm["tile_w"], "chunk_spp": prm["chunk_spp"],
             "vdb_bytes": int(buf.size), "dense_bytes": vol_bytes,
             "achieved_rate": round(st["achieved_rate"], 5),
         },

@@ -40,7 +40,8 @@ def sweep(args, torch, vdbc, synth, scenes, log):
     cam = scenes.orbit_camera((nx, ny, nz), W, H)
     med = scenes.pt_medium(64.0)
     # timed without the counters; samples from one more counting launch
-    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C, tile_w=64)
+    prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C, tile_w=args.tile_w,
+               chunk_spp=args.chunk_spp)
     rays = W * H * spp
 
     def samples_of(field, **kw):
@@ -51,7 +52,8 @@ def sweep(args, torch, vdbc, synth, scenes, log):
 
     out = {"metric": "paper-scale VDB vs dense path-traced Mrays/s", "unit": "Mrays/s",
            "config": {"workload": "fbm-cloud-1987x1351x2449-pt-1920x1080x64spp-16bounces",
-                      "dims": list(P["dims"]), "macrocell": C, "tile_w": 64}, "rates": []}
+                      "dims": list(P["dims"]), "macrocell": C, "tile_w": args.tile_w,
+                      "chunk_spp": args.chunk_spp}, "rates": []}
     for q in P["rates"]:
         t = time.time()
         buf, st = vdbc.encode(vol, q)
@@ -418,7 +420,8 @@ def ea(args, torch, vdbc, synth, scenes, log):
 
 def tune(args, torch, vdbc, synth, scenes, log):
     """The render autotuner on a headline frame: every (macrocell, wave tile,
-    accessor cache policy) candidate timed, the fastest kept.  --tune-frame
+    accessor cache policy, samples per work item) candidate timed, the
+    fastest kept.  --tune-frame
     mid: the 512^3 cloud at 1:10, 1024^2 x 16 spp, <= 8 bounces; paper: the
     1987x1351x2449 cloud at 1:10, 1920x1080 x 64 spp, <= 16 bounces."""
     from paper_2504_04564_amd import autotune
@@ -439,7 +442,12 @@ def tune(args, torch, vdbc, synth, scenes, log):
     cam = scenes.orbit_camera(dims, S["width"], S["height"])
     med = scenes.pt_medium(64.0)
     prm = dict(spp=S["spp"], max_bounces=S["max_bounces"], seed=S["seed"])
-    best, rows = autotune.tune_render(g, cam, med, prm, reps=5)
+    rows = []
+    for C_ in autotune.RENDER_SPACE["macrocell"]:   # one cell size at a time, with progress
+        _, part = autotune.tune_render(g, cam, med, prm, space=dict(macrocell=(C_,)), reps=5)
+        rows += part
+        log(f"[tune] macrocell {C_}: best {min(part, key=lambda x: x['ms'])}")
+    best = min(rows, key=lambda x: x["ms"])
     for r in sorted(rows, key=lambda x: x["ms"]):
         log(f"[tune] {r}")
     return {"metric": "render autotuner: fastest PT launch configuration", "unit": "ms",

@@ -270,17 +270,31 @@ typedef struct {
                                depend on it */
     float iso;              /* ISO: iso value */
     uint32_t refine;        /* ISO: bisection steps on the crossing interval (<= 64) */
+    uint32_t chunk_spp;     /* PT work split: 0 or >= spp: one work item per 256-pixel
+                               tile (all its samples); otherwise each tile is split into
+                               ceil(spp / chunk_spp) work items of chunk_spp samples
+                               (the last one shorter) that different workgroups run,
+                               and the tiles' fixed-point sums meet in the workspace
+                               (see below).  The image does not depend on it (integer
+                               sums: bit-identical to the unsplit launch). */
 } vdbc_render_params;
 
 /* Workspace layout (caller-owned device memory, 256-B aligned):
  *   [0, 8)    uint64 trilinear-sample counter (VDBC_RENDER_COUNT; zeroed by
  *             the render call itself)
  *   [8, 16)   uint64 majorant cells visited by the path tracer's DDA (same flag)
- *   [16, 20)  uint32 path tracer tile queue (zeroed by the render call)
+ *   [16, 20)  uint32 path tracer work-item queue (zeroed by the render call)
  *   [24, 32)  uint64 path segments the path tracer began: camera, shadow and
  *             scattered rays (VDBC_RENDER_COUNT)
- *   [256, ..) float32 majorant grid ceil(n/macrocell)^3, x-fastest */
-vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d, uint64_t* bytes);
+ *   [256, ..) float32 majorant grid ceil(n/macrocell)^3, x-fastest, then the
+ *             coarse occupancy bits (256-B aligned)
+ *   then, for a path-traced launch with 0 < chunk_spp < spp only: 40 bytes
+ *             per pixel of fixed-point sums (cleared and read by the render
+ *             call itself).
+ * c: the camera; needed (else VDBC_E_INVALID) only when 0 < chunk_spp < spp
+ * in the path tracer, may be NULL otherwise. */
+vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d, const vdbc_camera* c,
+                                  uint64_t* bytes);
 
 /* image: device float32 [height][width][4] (RGB radiance + opacity).  aov:
  * NULL or device float32 [height][width][2] = (first-scatter depth fraction,
@@ -311,9 +325,10 @@ vdbc_status vdbc_render_dense(const float* dense, vdbc_dims d, float background,
  * workspace of vdbc_render is replaced by a fixed library-owned scratch of
  * VDBC_NOALLOC_SCRATCH_BYTES (16 MiB) per GPU, held until the process ends:
  * a path-traced frame whose vdbc_render_workspace exceeds it (e.g. the
- * majorant grid of a 1987x1351x2449 volume at macrocell 8, 52 MB) is
+ * majorant grid of a 1987x1351x2449 volume at macrocell 8, 52 MB, or the
+ * per-pixel sums of a split launch of more than about 400,000 pixels) is
  * rejected with VDBC_E_BUFFER_TOO_SMALL before anything is enqueued; use
- * vdbc_render with a workspace or a larger macrocell then.  Arguments,
+ * vdbc_render with a workspace, a larger macrocell or chunk_spp = 0 then.  Arguments,
  * outputs and results are those of vdbc_render (bit-identical images), except
  * that VDBC_RENDER_KEEP_MAJORANT is rejected (VDBC_E_INVALID: the scratch
  * holds no majorant of the caller's).  Every call on one GPU shares its

@@ -3,9 +3,10 @@
 Times every candidate of a small search space on the device (one warm-up,
 median of `reps` HIP-event timings) and keeps the fastest; choices are
 persisted to a JSON file keyed by workload class so later runs reuse them.
-Candidates only change launch geometry (wave tile shape, persistent grid
-size), the VDB accessor's per-thread cache policy (none, last leaf, last leaf
-and last lower node) or the majorant cell size; all but the cell size leave
+Candidates only change launch geometry (wave tile shape, samples per work
+item, persistent grid size), the VDB accessor's per-thread cache policy
+(none, last leaf, last leaf and last lower node) or the majorant cell size;
+all but the cell size leave
 every image bit-identical, the cell size changes the estimator's random
 stream but not its expectation.
 """
@@ -19,7 +20,8 @@ import numpy as np
 
 from . import vdbc
 
-RENDER_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32, 64), "cache": (0, 1, 2)}
+RENDER_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32, 64), "cache": (0, 1, 2),
+                "chunk_spp": (0, 4, 8, 16)}
 BATCH_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32), "blocks_per_cu": (2, 4, 8),
                "persistent": (1,)}
 
@@ -62,19 +64,25 @@ def save(path: str, table: dict):
 
 def tune_render(field, camera: dict, medium: dict, params: dict, background=None,
                 space: dict | None = None, reps: int = 5):
-    """Best (macrocell, tile_w, cache) for a path-traced frame; returns
-    (best, all).  The cache policy is searched for VDB grids only."""
+    """Best (macrocell, tile_w, cache, chunk_spp) for a path-traced frame;
+    returns (best, all).  The cache policy is searched for VDB grids only;
+    work-item sizes of spp samples or more are the same launch as 0 and are
+    skipped."""
     space = dict(RENDER_SPACE, **(space or {}))
     caches = space["cache"] if isinstance(field, vdbc.Grid) else (2,)
+    spp = params.get("spp", 1)
+    chunks = [c for c in space["chunk_spp"] if c == 0 or c < spp]
     results = []
     for C_ in space["macrocell"]:
         for tw in space["tile_w"]:
             for cp in caches:
-                p = dict(params, macrocell=C_, tile_w=tw,
-                         flags=params.get("flags", 0) | vdbc.CACHE_FLAGS[cp])
-                r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
-                ms = _median_ms(r.launch, reps)
-                results.append({"macrocell": C_, "tile_w": tw, "cache": cp, "ms": ms})
+                for ch in chunks:
+                    p = dict(params, macrocell=C_, tile_w=tw, chunk_spp=ch,
+                             flags=params.get("flags", 0) | vdbc.CACHE_FLAGS[cp])
+                    r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
+                    ms = _median_ms(r.launch, reps)
+                    del r
+                    results.append({"macrocell": C_, "tile_w": tw, "cache": cp, "chunk_spp": ch, "ms": ms})
     best = min(results, key=lambda x: x["ms"])
     return best, results
 

@@ -21,6 +21,7 @@ struct PtArgs {
     int lf, cgx, cgy, cgz, cwords;   // coarse blocks of 2^lf macrocells per axis, bit words
     uint32_t seed_lo, seed_hi, frame;
     int rr;                          // Russian roulette from bounce 2 on
+    uint32_t chunk, chunks;          // samples per work item, work items per tile
 };
 
 // Occupancy of the coarse blocks: bit set iff some macrocell of the block has
@@ -214,6 +215,15 @@ __device__ __forceinline__ int flight_advance(Flight& f, const float* __restrict
 
 // LDS state of one 256-pixel tile: next unit of work and per-pixel sums in
 // 2^-32 fixed point (integer sums do not depend on the order of the adds).
+// Per-pixel fixed-point sums of a launch whose tiles are split into several
+// work items: rgbn[4 pix + k] = red, green, blue (k < 3) and hits | escapes
+// << 32 (k = 3); depth[pix] for the AOV.  rgbn == nullptr: every tile is one
+// work item and writes its pixels itself.
+struct PtSums {
+    unsigned long long* rgbn;
+    unsigned long long* depth;
+};
+
 struct TileShared {
     long long rgb[kBlock][3];
     long long depth[kBlock];
@@ -223,11 +233,11 @@ struct TileShared {
 
 __device__ __forceinline__ long long to_fixed(float v) { return __float2ll_rn(v * 4294967296.0f); }
 
-// Delta-tracking path tracer (Section 4) over one tile of 256 pixels.  The
-// tile's 256 x spp paths (unit u = sample u / 256 of tile pixel u % 256) are
-// shared by the workgroup: every lane starts on one unit and takes the next
-// one from an LDS counter when its path ends, so lanes on empty pixels or on
-// short paths keep working.  Within a path the loop is flat: every iteration
+// Delta-tracking path tracer (Section 4) over samples [s0, s1) of one tile of
+// 256 pixels.  The work item's 256 (s1 - s0) paths (unit u = sample u / 256
+// of tile pixel u % 256) are shared by the workgroup: every lane starts on one
+// unit and takes the next one from an LDS counter when its path ends, so lanes
+// on empty pixels or on short paths keep working.  Within a path the loop is flat: every iteration
 // moves the lane to its next tentative collision and handles whatever event
 // it reached (collision, escape, end of a shadow ray, start of a new path).
 // The arithmetic and the random draws of each path are those of a recursive
@@ -244,7 +254,7 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
                                         int bx, int by, TileShared& ts, const float4* tf_lds,
                                         float* __restrict__ image,
                                         float* __restrict__ aov, uint32_t& nsamp, uint32_t& ncell,
-                                        uint32_t& nseg)
+                                        uint32_t& nseg, uint32_t s0, uint32_t s1, PtSums sums)
 {
     const int tid = threadIdx.x;
     const int tw = g.tw, th = 64 / g.tw;
@@ -255,11 +265,11 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
     ts.rgb[tid][0] = ts.rgb[tid][1] = ts.rgb[tid][2] = 0;
     ts.depth[tid] = 0;
     ts.hits[tid] = ts.escapes[tid] = 0;
-    if (tid == 0) ts.next = kBlock;
+    if (tid == 0) ts.next = (s0 + 1) * kBlock;
     __syncthreads();
-    const uint32_t total = (uint32_t)kBlock * (uint32_t)g.spp;
+    const uint32_t total = kBlock * s1;
     const float inv4pi = 0.0795774715459476679f;
-    uint32_t u = (uint32_t)tid;
+    uint32_t u = s0 * kBlock + (uint32_t)tid;
     int q = 0, px = 0, py = 0;
     uint32_t k0 = 0, smp = 0;
     float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f, b0 = 1.0f, b1 = 1.0f, b2 = 1.0f;
@@ -397,17 +407,55 @@ __device__ __forceinline__ void pt_tile(Acc& acc, int nx, int ny, int nz, const 
         const int qx = x0 + w * tw + (l % tw), qy = y0 + (l / tw);
         if (qx < cam.width && qy < cam.height) {
             const uint32_t pix = (uint32_t)qy * (uint32_t)cam.width + (uint32_t)qx;
-            const double sc = 1.0 / (4294967296.0 * (double)g.spp);
-            const float inv = 1.0f / (float)g.spp;
-            reinterpret_cast<float4*>(image)[pix] =
-                make_float4((float)((double)ts.rgb[tid][0] * sc), (float)((double)ts.rgb[tid][1] * sc),
-                            (float)((double)ts.rgb[tid][2] * sc), (float)ts.hits[tid] * inv);
-            if (AOV)
-                reinterpret_cast<float2*>(aov)[pix] =
-                    make_float2((float)((double)ts.depth[tid] * sc), (float)ts.escapes[tid] * inv);
+            if (sums.rgbn) {
+                // integer sums: the total does not depend on the order in
+                // which the tile's work items finish
+                unsigned long long* a = sums.rgbn + 4 * (size_t)pix;
+                atomicAdd(a + 0, (unsigned long long)ts.rgb[tid][0]);
+                atomicAdd(a + 1, (unsigned long long)ts.rgb[tid][1]);
+                atomicAdd(a + 2, (unsigned long long)ts.rgb[tid][2]);
+                atomicAdd(a + 3, (unsigned long long)ts.hits[tid] | ((unsigned long long)ts.escapes[tid] << 32));
+                if (AOV) atomicAdd(sums.depth + pix, (unsigned long long)ts.depth[tid]);
+            } else {
+                const double sc = 1.0 / (4294967296.0 * (double)g.spp);
+                const float inv = 1.0f / (float)g.spp;
+                reinterpret_cast<float4*>(image)[pix] =
+                    make_float4((float)((double)ts.rgb[tid][0] * sc), (float)((double)ts.rgb[tid][1] * sc),
+                                (float)((double)ts.rgb[tid][2] * sc), (float)ts.hits[tid] * inv);
+                if (AOV)
+                    reinterpret_cast<float2*>(aov)[pix] =
+                        make_float2((float)((double)ts.depth[tid] * sc), (float)ts.escapes[tid] * inv);
+            }
         }
     }
     __syncthreads();
+}
+
+// Clears the per-pixel sums of a split launch: n 16-byte words.
+__global__ void pt_sums_clear_kernel(uint4* __restrict__ p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// The image (and AOV) of a split launch from its per-pixel sums, with the
+// scaling of the tiles that write their pixels themselves.
+__global__ void pt_resolve_kernel(PtSums sums, float* __restrict__ image, float* __restrict__ aov, uint32_t npix,
+                                  int spp)
+{
+    const uint32_t pix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= npix) return;
+    const unsigned long long* a = sums.rgbn + 4 * (size_t)pix;
+    const ulonglong2 rg = *reinterpret_cast<const ulonglong2*>(a);
+    const ulonglong2 bn = *reinterpret_cast<const ulonglong2*>(a + 2);
+    const double sc = 1.0 / (4294967296.0 * (double)spp);
+    const float inv = 1.0f / (float)spp;
+    reinterpret_cast<float4*>(image)[pix] =
+        make_float4((float)((double)(long long)rg.x * sc), (float)((double)(long long)rg.y * sc),
+                    (float)((double)(long long)bn.x * sc), (float)(unsigned int)(bn.y & 0xFFFFFFFFull) * inv);
+    if (aov)
+        reinterpret_cast<float2*>(aov)[pix] =
+            make_float2((float)((double)(long long)sums.depth[pix] * sc), (float)(unsigned int)(bn.y >> 32) * inv);
 }
 
 template <class Acc, class View, bool COUNT, bool AOV, bool ENV>
@@ -417,7 +465,7 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
                                                     float* __restrict__ image,
                                                     float* __restrict__ aov,
                                                     unsigned long long* counter,
-                                                    uint32_t* queue)
+                                                    uint32_t* queue, PtSums sums)
 {
     extern __shared__ uint32_t cbits[];
     __shared__ TileShared ts;
@@ -429,18 +477,23 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
     Acc acc{view};
     acc.reset();
     uint32_t nsamp = 0, ncell = 0, nseg = 0;
-    // persistent workgroups take tiles in raster order from a queue, so a
-    // workgroup that drew cheap tiles goes on to the next one at once
-    __shared__ uint32_t s_tile;
+    // persistent workgroups take work items (tile, chunk of g.chunk samples)
+    // in raster order of the tiles from a queue, so a workgroup that drew
+    // cheap items goes on to the next one at once, and the paths of one
+    // expensive tile are spread over g.chunks workgroups
+    __shared__ uint32_t s_item;
     const uint32_t tiles_x = (uint32_t)((cam.width + 4 * g.tw - 1) / (4 * g.tw));
     const uint32_t tiles = tiles_x * (uint32_t)((cam.height + 64 / g.tw - 1) / (64 / g.tw));
+    const uint32_t items = tiles * g.chunks;
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1u);
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1u);
         __syncthreads();
-        const uint32_t t = s_tile;   // pt_tile's barriers order this read before the next write
-        if (t >= tiles) break;
+        const uint32_t it = s_item;   // pt_tile's barriers order this read before the next write
+        if (it >= items) break;
+        const uint32_t t = it / g.chunks, s0 = (it % g.chunks) * g.chunk;
         pt_tile<Acc, AOV, ENV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
-                          (int)(t / tiles_x), ts, tf_lds, image, aov, nsamp, ncell, nseg);
+                               (int)(t / tiles_x), ts, tf_lds, image, aov, nsamp, ncell, nseg, s0,
+                               min(s0 + g.chunk, (uint32_t)g.spp), sums);
     }
     if (COUNT) {
         block_count(nsamp, counter);
@@ -497,7 +550,7 @@ __global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __
         uint32_t ns = 0, nc = 0, nsg = 0;
         pt_tile<VdbAcc, false, true>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
                                (int)(tile % (uint32_t)D->tiles_x), (int)(tile / (uint32_t)D->tiles_x), ts,
-                               tf_lds, D->image, nullptr, ns, nc, nsg);
+                               tf_lds, D->image, nullptr, ns, nc, nsg, 0u, (uint32_t)g.spp, PtSums{});
     }
 }
 

@@ -422,6 +422,14 @@ static uint64_t pt_workspace(uint32_t C, int nx, int ny, int nz)
     return 256 + align256(majorant_bytes(C, nx, ny, nz)) + align256(4ull * g.cwords);
 }
 
+// A path-traced launch splits its tiles into several work items (and needs
+// the per-pixel sums after the occupancy bits) iff 0 < chunk_spp < spp.
+static bool pt_split(const vdbc_render_params* r) { return r->chunk_spp != 0 && r->chunk_spp < r->spp; }
+
+// Bytes of the per-pixel sums of a split launch: 32 (red, green, blue,
+// hits | escapes) + 8 (AOV depth) per pixel.
+static uint64_t pt_sums_bytes(uint64_t npix) { return align256(40ull * npix); }
+
 
 template <class Acc, class View>
 static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, float* out,
@@ -473,7 +481,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     unsigned long long* counter = reinterpret_cast<unsigned long long*>(ws);
     vdbc_dims d{(uint32_t)v.nx, (uint32_t)v.ny, (uint32_t)v.nz};
     uint64_t need = 0;
-    s = vdbc_render_workspace(r, d, &need);
+    s = vdbc_render_workspace(r, d, c, &need);
     if (s) return s;
     if (need && (!ws || ws_bytes < need))
         return fail(VDBC_E_BUFFER_TOO_SMALL, "workspace needs %llu bytes", (unsigned long long)need);
@@ -542,6 +550,15 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     if (r->tile_w != 0 && r->tile_w != 8 && r->tile_w != 16 && r->tile_w != 32 && r->tile_w != 64)
         return fail(VDBC_E_INVALID, "tile_w must be 0 (default 8), 8, 16, 32 or 64");
     {
+        // the work-item queue counts in 32 bits
+        const uint64_t tw = r->tile_w == 0 ? 8 : r->tile_w;
+        const uint64_t tiles = ((uint64_t)cam.width + 4 * tw - 1) / (4 * tw) *
+                               (((uint64_t)cam.height + 64 / tw - 1) / (64 / tw));
+        const uint64_t per_tile = pt_split(r) ? (r->spp + r->chunk_spp - 1) / r->chunk_spp : 1;
+        if (tiles * per_tile > 0xFFFFFFFFull)
+            return fail(VDBC_E_INVALID, "more than 2^32 work items: raise chunk_spp");
+    }
+    {
         const double l = std::sqrt((double)med->light_dir[0] * med->light_dir[0] +
                                    (double)med->light_dir[1] * med->light_dir[1] +
                                    (double)med->light_dir[2] * med->light_dir[2]);
@@ -565,8 +582,22 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     g.seed_hi = (uint32_t)(r->seed >> 32);
     g.frame = r->frame;
     g.rr = (r->flags & VDBC_RENDER_RR) ? 1 : 0;
+    const bool split = pt_split(r);
+    g.chunk = split ? r->chunk_spp : r->spp;
+    g.chunks = (r->spp + g.chunk - 1) / g.chunk;
     uint32_t* coarse = reinterpret_cast<uint32_t*>(
         static_cast<uint8_t*>(ws) + 256 + align256(majorant_bytes(r->macrocell, v.nx, v.ny, v.nz)));
+    const uint64_t npix = (uint64_t)cam.width * (uint64_t)cam.height;
+    PtSums sums{};
+    if (split) {
+        uint8_t* base = static_cast<uint8_t*>(ws) + pt_workspace(r->macrocell, v.nx, v.ny, v.nz);
+        sums.rgbn = reinterpret_cast<unsigned long long*>(base);
+        sums.depth = sums.rgbn + 4 * npix;
+        const uint64_t words = pt_sums_bytes(npix) / 16;
+        hipLaunchKernelGGL(pt_sums_clear_kernel, dim3((unsigned)std::min<uint64_t>((words + kBlock - 1) / kBlock, 4096)),
+                           dim3(kBlock), 0, st, reinterpret_cast<uint4*>(base), words);
+        if ((s = launch_check("clear pixel sums"))) return s;
+    }
     {
         const uint64_t ncoarse = (uint64_t)g.cgx * g.cgy * g.cgz;
         hipLaunchKernelGGL(coarse_bits_kernel, dim3((unsigned)((ncoarse + kBlock - 1) / kBlock)),
@@ -577,12 +608,12 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     {
         const uint64_t tiles = (uint64_t)((cam.width + 4 * g.tw - 1) / (4 * g.tw)) *
                                (uint64_t)((cam.height + 64 / g.tw - 1) / (64 / g.tw));
-        grid = dim3((unsigned)std::min<uint64_t>(tiles, (uint64_t)device_cus() * kPtBlocksPerCu));
+        grid = dim3((unsigned)std::min<uint64_t>(tiles * g.chunks, (uint64_t)device_cus() * kPtBlocksPerCu));
     }
     uint32_t* queue = reinterpret_cast<uint32_t*>(counter + 2);
 #define PT_LAUNCH(CNT, AO, EN)                                                                     \
     hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO, EN>), grid, dim3(kBlock), lds, st, v, cam, m, \
-                       g, maj, coarse, image, aov, counter, queue)
+                       g, maj, coarse, image, aov, counter, queue, sums)
 #define PT_LAUNCH_ENV(CNT, AO)           \
     if (m.env) PT_LAUNCH(CNT, AO, true); \
     else PT_LAUNCH(CNT, AO, false)
@@ -595,6 +626,12 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     }
 #undef PT_LAUNCH_ENV
 #undef PT_LAUNCH
+    if (split) {
+        if ((s = launch_check("pt render"))) return s;
+        hipLaunchKernelGGL(pt_resolve_kernel, dim3((unsigned)((npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, sums,
+                           image, aov, (uint32_t)npix, g.spp);
+        return launch_check("pixel sums to image");
+    }
     return launch_check("pt render");
 }
 
@@ -603,7 +640,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
 using namespace vdbc;
 
 extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_dims d,
-                                             uint64_t* bytes)
+                                             const vdbc_camera* c, uint64_t* bytes)
 {
     if (!r || !bytes) return fail(VDBC_E_INVALID, "null argument");
     if (d.nx == 0 || d.ny == 0 || d.nz == 0) return fail(VDBC_E_INVALID, "zero dims");
@@ -611,6 +648,10 @@ extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_d
         if (r->macrocell < 4 || r->macrocell > 64 || (r->macrocell & (r->macrocell - 1)))
             return fail(VDBC_E_INVALID, "macrocell must be 4, 8, 16, 32 or 64");
         *bytes = pt_workspace(r->macrocell, (int)d.nx, (int)d.ny, (int)d.nz);
+        if (pt_split(r)) {
+            if (!c) return fail(VDBC_E_INVALID, "0 < chunk_spp < spp: the workspace size needs the camera");
+            *bytes += pt_sums_bytes((uint64_t)c->width * (uint64_t)c->height);
+        }
     } else {
         *bytes = (r->flags & VDBC_RENDER_COUNT) ? 256 : 0;
     }
@@ -691,10 +732,10 @@ extern "C" vdbc_status vdbc_render_noalloc(const vdbc_grid* g, const vdbc_camera
     if (s) return s;
     vdbc_dims d{(uint32_t)v.nx, (uint32_t)v.ny, (uint32_t)v.nz};
     uint64_t need = 0;
-    if ((s = vdbc_render_workspace(r, d, &need))) return s;
+    if ((s = vdbc_render_workspace(r, d, c, &need))) return s;
     if (need > kScratchBytes)
         return fail(VDBC_E_BUFFER_TOO_SMALL, "this render needs %llu bytes of scratch; the fixed scratch holds %llu "
-                    "(use vdbc_render with a workspace, or a larger macrocell)",
+                    "(use vdbc_render with a workspace, a larger macrocell or chunk_spp 0)",
                     (unsigned long long)need, (unsigned long long)kScratchBytes);
     void* ws = nullptr;
     if ((s = scratch_address(&ws))) return s;
@@ -818,6 +859,8 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         g.seed_hi = (uint32_t)(it.seed >> 32);
         g.frame = it.frame;
         g.rr = 0;
+        g.chunk = g.spp;
+        g.chunks = 1;
         const int tx = (cam.width + 4 * g.tw - 1) / (4 * g.tw), ty = (cam.height + 64 / g.tw - 1) / (64 / g.tw);
         if ((uint64_t)tx * ty > 0xFFFFFu) return fail(VDBC_E_INVALID, "batch item %u: image too large", i);
         b->views.push_back(v);
@@ -874,11 +917,11 @@ static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
         if (b->meds[i].env)
             hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, true>), grid, dim3(kBlock),
                                4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter);
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{});
         else
             hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, false>), grid, dim3(kBlock),
                                4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter);
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{});
         if ((s = launch_check("per-volume render"))) return s;
     }
     return VDBC_OK;

@@ -75,7 +75,8 @@ class RenderParamsC(C.Structure):
     _fields_ = [("mode", C.c_uint32), ("spp", C.c_uint32), ("max_bounces", C.c_uint32),
                 ("macrocell", C.c_uint32), ("flags", C.c_uint32), ("step", C.c_float),
                 ("t_terminate", C.c_float), ("seed", C.c_uint64), ("frame", C.c_uint32),
-                ("tile_w", C.c_uint32), ("iso", C.c_float), ("refine", C.c_uint32)]
+                ("tile_w", C.c_uint32), ("iso", C.c_float), ("refine", C.c_uint32),
+                ("chunk_spp", C.c_uint32)]
 
 
 SYMBOLS = [
@@ -134,7 +135,7 @@ def load():
     L.vdbc_lookup.argtypes = [C.POINTER(GridC), P, u64, P, P]
     L.vdbc_compare_workspace.argtypes = [Dims, C.POINTER(u64)]
     L.vdbc_compare_dense.argtypes = [C.POINTER(GridC), P, P, P, u64, P]
-    L.vdbc_render_workspace.argtypes = [C.POINTER(RenderParamsC), Dims, C.POINTER(u64)]
+    L.vdbc_render_workspace.argtypes = [C.POINTER(RenderParamsC), Dims, C.POINTER(CameraC), C.POINTER(u64)]
     L.vdbc_render.argtypes = [C.POINTER(GridC), C.POINTER(CameraC), C.POINTER(MediumC),
                               C.POINTER(RenderParamsC), P, P, P, u64, P]
     L.vdbc_render_dense.argtypes = [P, Dims, f32, C.POINTER(CameraC), C.POINTER(MediumC),
@@ -361,6 +362,7 @@ def params_c(p: dict, mode: int) -> RenderParamsC:
     r.tile_w = p.get("tile_w", 8)
     r.iso = p.get("iso", 0.5)
     r.refine = p.get("refine", 12)
+    r.chunk_spp = p.get("chunk_spp", 0)
     return r
 
 
@@ -382,7 +384,7 @@ class Renderer:
         self.cam, self.med = camera_c(camera), (medium_c(medium) if medium else MediumC())
         self.prm = params_c(params, mode)
         ws = C.c_uint64(0)
-        _check(load().vdbc_render_workspace(C.byref(self.prm), self.dims, C.byref(ws)))
+        _check(load().vdbc_render_workspace(C.byref(self.prm), self.dims, C.byref(self.cam), C.byref(ws)))
         self.ws = torch.zeros(max(int(ws.value), 256) + 256, dtype=torch.uint8, device=device)
         self.ws_off = (-self.ws.data_ptr()) % 256
         self.ws_bytes = int(ws.value)

@@ -1,7 +1,8 @@
 """GPU parity at the paper-scale size, in the benchmark's launch: the
 1987 x 1351 x 2449 billowed cloud (26.3 GB dense) at 1:10, the majorant grid
 of the whole volume at macrocell 64, the path tracer at 1920 x 1080 x 64 spp
-with at most 16 bounces and 64-wide wave tiles, and random trilinear samples
+with at most 16 bounces, 8 x 8 wave tiles and work items of 8 samples, and
+random trilinear samples
 in the bricks that hold a non-background voxel.  The oracle computes the
 majorant grid (threaded over disjoint cell ranges), a sample of the image's
 pixels one by one and every sample.  Bars as in test_gpu_parity.py."""
@@ -19,7 +20,7 @@ from synth import scenes
 pytestmark = pytest.mark.gpu
 
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
-C, TW = 64, 64
+C, TW, CHUNK = 64, 8, 8
 
 
 def relmse(x, y):
@@ -65,7 +66,8 @@ def test_paper_scale_path_tracer_sampled_pixels(paper):
     P = paper["P"]
     dims = P["dims"]
     cam = scenes.orbit_camera(dims, P["width"], P["height"])
-    prm = dict(spp=P["spp"], max_bounces=P["max_bounces"], seed=P["seed"], macrocell=C, tile_w=TW)
+    prm = dict(spp=P["spp"], max_bounces=P["max_bounces"], seed=P["seed"], macrocell=C, tile_w=TW,
+               chunk_spp=CHUNK)
     img = vdbc.render(paper["grid"], cam, paper["med"], prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
     assert np.all(np.isfinite(img))
     rng = np.random.default_rng(62)

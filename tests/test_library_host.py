@@ -240,20 +240,31 @@ def test_device_calls_reject_bad_arguments_before_launch(lib):
                            None, 0, None) == vdbc.E_INVALID
     pt = vdbc.params_c(dict(spp=1), vdbc.MODE_PT)
     ws = C.c_uint64(0)
-    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == 0
     assert ws.value == 256 + 256 + 256   # counters | 2^3 majorants | coarse bits
     assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(pt), 4096, None,
                            8192, ws.value - 1, None) == vdbc.E_BUFFER_TOO_SMALL
     pt.macrocell = 3
-    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == \
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == \
         vdbc.E_INVALID
+    # split tiles (0 < chunk_spp < spp): 40 bytes of pixel sums per pixel after
+    # the occupancy bits, which needs the camera; unsplit launches need neither
+    pt.macrocell = 8
+    big = vdbc.camera_c(dict(kind=0, width=100, height=30, dir=(0, 0, 1)))
+    for spp, chunk, extra in ((8, 2, 120064), (8, 7, 120064), (8, 8, 0), (8, 9, 0), (8, 0, 0), (1, 1, 0)):
+        pt.spp, pt.chunk_spp = spp, chunk
+        assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(big), C.byref(ws)) == 0
+        assert ws.value == 768 + extra, (spp, chunk)          # align256(40 * 3000) = 120064
+        want = vdbc.OK if extra == 0 else vdbc.E_INVALID
+        assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == want
+    pt.spp, pt.chunk_spp = 1, 0
     assert lib.vdbc_status_string(3) == b"buffer too small"
     # degenerate scenes are refused before launch
     zero_dir = vdbc.camera_c(dict(kind=0, width=4, height=4))
     assert lib.vdbc_render(C.byref(g), C.byref(zero_dir), C.byref(med), C.byref(prm), 4096,
                            None, None, 0, None) == vdbc.E_INVALID
     pt.macrocell = 8
-    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == 0
     no_light = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)],
                                   light_dir=(0, 0, 0)))
     assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(no_light), C.byref(pt), 4096,
@@ -302,7 +313,7 @@ def test_iso_and_compare_reject_bad_arguments_before_launch(lib):
     # the iso mode needs no workspace unless counting
     ws = C.c_uint64(1)
     assert lib.vdbc_render_workspace(C.byref(vdbc.params_c(dict(), vdbc.MODE_ISO)),
-                                     vdbc.Dims(16, 16, 16), C.byref(ws)) == 0 and ws.value == 0
+                                     vdbc.Dims(16, 16, 16), None, C.byref(ws)) == 0 and ws.value == 0
     # compare: workspace = 5 doubles per workgroup, 64x8x8 voxels per workgroup
     for dims, blocks in (((16, 16, 16), 4), ((64, 8, 8), 1), ((65, 9, 9), 8),
                          ((2048, 2048, 2048), 4096)):
@@ -324,9 +335,16 @@ def test_path_tracer_limits_rejected_before_launch(lib):
     for bad in (dict(spp=0), dict(spp=65537), dict(max_bounces=0), dict(max_bounces=65536),
                 dict(tile_w=4), dict(tile_w=12), dict(tile_w=128)):
         prm = vdbc.params_c(dict(dict(spp=1), **bad), vdbc.MODE_PT)
-        assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(16, 16, 16), C.byref(ws)) == 0
+        assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == 0
         assert lib.vdbc_render(C.byref(g), C.byref(cam), C.byref(med), C.byref(prm), 4096, None,
                                8192, ws.value, None) == vdbc.E_INVALID, bad
+    # a split launch whose work items overflow the 32-bit queue: 2^23 tiles x
+    # 2^16 items of one sample each (the workspace pointer is never touched)
+    huge = vdbc.camera_c(dict(kind=0, width=65536, height=32768, dir=(0, 0, 1)))
+    prm = vdbc.params_c(dict(spp=65536, chunk_spp=1), vdbc.MODE_PT)
+    assert lib.vdbc_render(C.byref(g), C.byref(huge), C.byref(med), C.byref(prm), 4096, None,
+                           8192, 1 << 50, None) == vdbc.E_INVALID
+    assert b"work items" in lib.vdbc_last_error()
     env_bad = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)],
                                  light_dir=(0, 0, 1)))
     env_bad.env, env_bad.env_w, env_bad.env_h = 4096, 0, 4

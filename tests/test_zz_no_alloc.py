@@ -64,11 +64,16 @@ def test_noalloc_refuses_what_the_scratch_cannot_hold(lib):
     med = vdbc.medium_c(scenes.pt_medium(8.0))
     prm = vdbc.params_c(dict(spp=1, macrocell=4), vdbc.MODE_PT)
     ws = C.c_uint64(0)
-    assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(nx, ny, nz), C.byref(ws)) == 0
+    assert lib.vdbc_render_workspace(C.byref(prm), vdbc.Dims(nx, ny, nz), None, C.byref(ws)) == 0
     assert ws.value > vdbc.NOALLOC_SCRATCH_BYTES
     assert lib.vdbc_render_noalloc(C.byref(g), C.byref(cam), C.byref(med), C.byref(prm), 4096,
                                    None, None) == vdbc.E_BUFFER_TOO_SMALL
     assert b"fixed scratch" in lib.vdbc_last_error()
+    # nor the pixel sums of a split 1920 x 1080 launch (83 MB)
+    split = vdbc.params_c(dict(spp=8, chunk_spp=2, macrocell=64), vdbc.MODE_PT)
+    hd = vdbc.camera_c(dict(kind=0, width=1920, height=1080, dir=(0, 0, 1)))
+    assert lib.vdbc_render_noalloc(C.byref(g), C.byref(hd), C.byref(med), C.byref(split), 4096,
+                                   None, None) == vdbc.E_BUFFER_TOO_SMALL
     # the caller's majorant cannot be kept: the scratch holds none of it
     keep = vdbc.params_c(dict(spp=1, macrocell=64, flags=vdbc.RENDER_KEEP_MAJORANT), vdbc.MODE_PT)
     assert lib.vdbc_render_noalloc(C.byref(g), C.byref(cam), C.byref(med), C.byref(keep), 4096,

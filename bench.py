@@ -39,11 +39,14 @@ BRICK = 32                        # brick edge of the encoder (Alg. 1)
 DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16}
 # wave tile width (pixels per wave row) of each frame, the same autotuner's
 # choice; the image does not depend on it
-DEFAULT_TILE_W = {"paper": 8, "sweep": 8, "mid": 8}
+DEFAULT_TILE_W = {"paper": 16, "sweep": 16, "mid": 16}
 # samples per work item (each 256-pixel tile split into spp / chunk items that
 # different workgroups run; 0 = one item per tile), the same autotuner's
 # choice; the image does not depend on it
 DEFAULT_CHUNK_SPP = {"paper": 8, "sweep": 8, "mid": 4}
+# work queue in decreasing estimated tile cost (1) or in raster order (0), the
+# same autotuner's choice; the image does not depend on it
+DEFAULT_COST_ORDER = {"paper": 1, "sweep": 1, "mid": 1}
 # committed rocprofv3 counter summaries of pt_kernel<VdbAcc>, one per frame
 PROFILES = {"paper": os.path.join(ROOT, "profiles", "pt_kernel_vdb_paper_1to10.md"),
             "mid": os.path.join(ROOT, "profiles", "pt_kernel_vdb_mid512_1to10.md")}
@@ -77,7 +80,7 @@ def profile_values(path: str | None = None, launch: str | None = None):
     """Figures of a committed rocprofv3 counter summary of the PT kernel (HBM
     bytes per launch, VALU lane utilisation, L2 hit rate), or {} if the kernel
     sources changed since the counters were taken or (with `launch`, e.g.
-    "macrocell=64 tile_w=8 chunk_spp=8") the summary describes another launch."""
+    "macrocell=64 tile_w=16 chunk_spp=8 cost_order") the summary describes another launch."""
     path = path or PROFILE
     if not os.path.exists(path):
         return {}
@@ -330,6 +333,7 @@ def main():
         args.macrocell = DEFAULT_MACROCELL.get(args.workload, 16)
     args.chunk_spp = DEFAULT_CHUNK_SPP.get(args.workload, 0)
     args.tile_w = DEFAULT_TILE_W.get(args.workload, 8)
+    args.order_flag = vdbc.RENDER_COST_ORDER if DEFAULT_COST_ORDER.get(args.workload, 0) else 0
     if args.workload not in ("paper", "mid"):
         import bench_workloads
         line = getattr(bench_workloads, args.workload)(args, torch, vdbc, synth, scenes, log)
@@ -395,8 +399,8 @@ def main():
     # trilinear samples and path segments per frame
     prm = dict(spp=spp, max_bounces=bounces, seed=S["seed"], macrocell=C,
                tile_w=args.tile_w, chunk_spp=args.chunk_spp,
-               flags=vdbc.RENDER_KEEP_MAJORANT)
-    prm_count = dict(prm, flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT)
+               flags=vdbc.RENDER_KEEP_MAJORANT | args.order_flag)
+    prm_count = dict(prm, flags=vdbc.RENDER_COUNT | vdbc.RENDER_KEEP_MAJORANT | args.order_flag)
     rays = W * H * spp
 
     def counted(field, timed_image, **kw):
@@ -497,8 +501,9 @@ def main():
     prof_path = PROFILES[args.workload]
     standard = (args.rate == 0.10 and C == DEFAULT_MACROCELL[args.workload] and
                 (args.workload == "paper" or nx == 512))
-    prof = profile_values(prof_path, f"macrocell={C} tile_w={prm['tile_w']} chunk_spp={prm['chunk_spp']}") \
-        if standard else {}
+    launch = f"macrocell={C} tile_w={prm['tile_w']} chunk_spp={prm['chunk_spp']}" + \
+        (" cost_order" if args.order_flag else "")
+    prof = profile_values(prof_path, launch) if standard else {}
     achieved = samples * BYTES_PER_RENDER_SAMPLE / pt_s / 1e9
     line = {
         "metric": METRIC,
@@ -518,6 +523,7 @@ def main():
                         f"{bounces}bounces",
             "dims": list(dims), "rate": args.rate, "width": W, "height": H, "spp": spp,
             "max_bounces": bounces, "macrocell": C, "tile_w": prm["tile_w"], "chunk_spp": prm["chunk_spp"],
+            "cost_order": bool(args.order_flag),
             "vdb_bytes": int(buf.size), "dense_bytes": vol_bytes,
             "achieved_rate": round(st["achieved_rate"], 5),
         },

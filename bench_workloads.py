@@ -41,7 +41,7 @@ def sweep(args, torch, vdbc, synth, scenes, log):
     med = scenes.pt_medium(64.0)
     # timed without the counters; samples from one more counting launch
     prm = dict(spp=spp, max_bounces=bounces, seed=P["seed"], macrocell=C, tile_w=args.tile_w,
-               chunk_spp=args.chunk_spp)
+               chunk_spp=args.chunk_spp, flags=args.order_flag)
     rays = W * H * spp
 
     def samples_of(field, **kw):

@@ -250,9 +250,14 @@ enum {
                                       stream (bounce >= 1) */
     VDBC_RENDER_CACHE_NONE = 16u,  /* PT, VDB: no per-thread cache (every lookup descends
                                       from the root) */
-    VDBC_RENDER_CACHE_LEAF = 32u   /* PT, VDB: cache the last leaf only (default, neither
+    VDBC_RENDER_CACHE_LEAF = 32u,  /* PT, VDB: cache the last leaf only (default, neither
                                       flag: the last leaf and the last lower node).  The
                                       image does not depend on the cache policy. */
+    VDBC_RENDER_COST_ORDER = 64u   /* PT: hand the tiles to the workgroups in decreasing
+                                      order of an estimated cost (the majorant optical
+                                      depth of four camera rays per tile) instead of in
+                                      raster order; needs 8 bytes per tile + 512 of
+                                      workspace.  The image does not depend on it. */
 };
 
 typedef struct {

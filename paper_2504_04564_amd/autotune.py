@@ -4,7 +4,8 @@ Times every candidate of a small search space on the device (one warm-up,
 median of `reps` HIP-event timings) and keeps the fastest; choices are
 persisted to a JSON file keyed by workload class so later runs reuse them.
 Candidates only change launch geometry (wave tile shape, samples per work
-item, persistent grid size), the VDB accessor's per-thread cache policy
+item, order of the tiles in the work queue, persistent grid size), the VDB
+accessor's per-thread cache policy
 (none, last leaf, last leaf and last lower node) or the majorant cell size;
 all but the cell size leave
 every image bit-identical, the cell size changes the estimator's random
@@ -22,6 +23,9 @@ from . import vdbc
 
 RENDER_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32, 64), "cache": (0, 1, 2),
                 "chunk_spp": (0, 4, 8, 16)}
+# the cost order of the work queue is tried on this many of the fastest
+# raster-order candidates (a second stage instead of doubling the grid)
+ORDER_STAGE = 8
 BATCH_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32), "blocks_per_cu": (2, 4, 8),
                "persistent": (1,)}
 
@@ -64,10 +68,11 @@ def save(path: str, table: dict):
 
 def tune_render(field, camera: dict, medium: dict, params: dict, background=None,
                 space: dict | None = None, reps: int = 5):
-    """Best (macrocell, tile_w, cache, chunk_spp) for a path-traced frame;
-    returns (best, all).  The cache policy is searched for VDB grids only;
-    work-item sizes of spp samples or more are the same launch as 0 and are
-    skipped."""
+    """Best (macrocell, tile_w, cache, chunk_spp, order) for a path-traced
+    frame; returns (best, all).  The cache policy is searched for VDB grids
+    only; work-item sizes of spp samples or more are the same launch as 0 and
+    are skipped; the cost order (order 1) is timed on the ORDER_STAGE fastest
+    raster-order (order 0) candidates."""
     space = dict(RENDER_SPACE, **(space or {}))
     caches = space["cache"] if isinstance(field, vdbc.Grid) else (2,)
     spp = params.get("spp", 1)
@@ -82,7 +87,15 @@ def tune_render(field, camera: dict, medium: dict, params: dict, background=None
                     r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
                     ms = _median_ms(r.launch, reps)
                     del r
-                    results.append({"macrocell": C_, "tile_w": tw, "cache": cp, "chunk_spp": ch, "ms": ms})
+                    results.append({"macrocell": C_, "tile_w": tw, "cache": cp, "chunk_spp": ch, "order": 0,
+                                    "ms": ms})
+    for c in sorted(results, key=lambda x: x["ms"])[:ORDER_STAGE]:
+        p = dict(params, macrocell=c["macrocell"], tile_w=c["tile_w"], chunk_spp=c["chunk_spp"],
+                 flags=params.get("flags", 0) | vdbc.CACHE_FLAGS[c["cache"]] | vdbc.RENDER_COST_ORDER)
+        r = vdbc.Renderer(field, camera, medium, p, vdbc.MODE_PT, background=background)
+        ms = _median_ms(r.launch, reps)
+        del r
+        results.append(dict(c, order=1, ms=ms))
     best = min(results, key=lambda x: x["ms"])
     return best, results
 

@@ -458,6 +458,65 @@ __global__ void pt_resolve_kernel(PtSums sums, float* __restrict__ image, float*
             make_float2((float)((double)(long long)sums.depth[pix] * sc), (float)(unsigned int)(bn.y >> 32) * inv);
 }
 
+// ---------------------------------------------------------------- cost order
+// Optional order of the tiles in the work queue: most expensive first, so
+// that the longest work items do not start last.  The estimate of a tile is
+// the majorant optical depth of four camera rays through it (one through the
+// middle of each wave tile, 32 midpoint steps across the volume's box),
+// binned on a log scale (four bins per octave of 1 + depth, 64 bins); a
+// counting sort over the bins gives the order.  Ties within a bin are taken
+// in whatever order the atomics give: the image does not depend on the order.
+constexpr int kCostBins = 64;
+
+__global__ void pt_tile_cost_kernel(CameraK cam, PtArgs g, int nx, int ny, int nz, const float* __restrict__ maj,
+                                    uint32_t tiles_x, uint32_t tiles, uint32_t* __restrict__ key,
+                                    uint32_t* __restrict__ hist)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    const int tw = g.tw, th = 64 / g.tw;
+    const float x0 = (float)((t % tiles_x) * 4u * (uint32_t)tw), y0 = (float)((t / tiles_x) * (uint32_t)th);
+    float tau = 0.0f;
+    for (int w = 0; w < 4; ++w) {
+        float o[3], d[3], id[3], t0, t1;
+        camera_ray(cam, x0 + ((float)w + 0.5f) * (float)tw, y0 + 0.5f * (float)th, o, d);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) id[a] = 1.0f / d[a];
+        if (!box_clip(nx, ny, nz, o, d, id, t0, t1)) continue;
+        const float dt = (t1 - t0) * (1.0f / 32.0f);
+        for (int k = 0; k < 32; ++k) {
+            const float s = fmaf((float)k + 0.5f, dt, t0);
+            const int cx = min(max((int)floorf((fmaf(s, d[0], o[0]) + 0.5f) * g.invC), 0), g.gx - 1);
+            const int cy = min(max((int)floorf((fmaf(s, d[1], o[1]) + 0.5f) * g.invC), 0), g.gy - 1);
+            const int cz = min(max((int)floorf((fmaf(s, d[2], o[2]) + 0.5f) * g.invC), 0), g.gz - 1);
+            tau = fmaf(maj[cx + g.gx * (cy + g.gy * cz)], dt, tau);
+        }
+    }
+    // fminf / fmaxf also map an infinite or NaN depth into the bin range
+    const int k = (int)fmaxf(fminf(log2f(1.0f + fmaxf(tau, 0.0f)) * 4.0f, (float)(kCostBins - 1)), 0.0f);
+    key[t] = (uint32_t)k;
+    atomicAdd(&hist[k], 1u);
+}
+
+// First position of each bin in the queue, from the most expensive bin down.
+__global__ void pt_cost_offsets_kernel(const uint32_t* __restrict__ hist, uint32_t* __restrict__ off)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t s = 0;
+    for (int k = kCostBins - 1; k >= 0; --k) {
+        off[k] = s;
+        s += hist[k];
+    }
+}
+
+__global__ void pt_cost_scatter_kernel(const uint32_t* __restrict__ key, uint32_t* __restrict__ off,
+                                       uint32_t* __restrict__ order, uint32_t tiles)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles) return;
+    order[atomicAdd(&off[key[t]], 1u)] = t;
+}
+
 template <class Acc, class View, bool COUNT, bool AOV, bool ENV>
 __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, MediumK m, PtArgs g,
                                                     const float* __restrict__ maj,
@@ -465,7 +524,8 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
                                                     float* __restrict__ image,
                                                     float* __restrict__ aov,
                                                     unsigned long long* counter,
-                                                    uint32_t* queue, PtSums sums)
+                                                    uint32_t* queue, PtSums sums,
+                                                    const uint32_t* __restrict__ order)
 {
     extern __shared__ uint32_t cbits[];
     __shared__ TileShared ts;
@@ -478,9 +538,9 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
     acc.reset();
     uint32_t nsamp = 0, ncell = 0, nseg = 0;
     // persistent workgroups take work items (tile, chunk of g.chunk samples)
-    // in raster order of the tiles from a queue, so a workgroup that drew
-    // cheap items goes on to the next one at once, and the paths of one
-    // expensive tile are spread over g.chunks workgroups
+    // from a queue, the tiles in raster order or in the given order, so a
+    // workgroup that drew cheap items goes on to the next one at once, and
+    // the paths of one expensive tile are spread over g.chunks workgroups
     __shared__ uint32_t s_item;
     const uint32_t tiles_x = (uint32_t)((cam.width + 4 * g.tw - 1) / (4 * g.tw));
     const uint32_t tiles = tiles_x * (uint32_t)((cam.height + 64 / g.tw - 1) / (64 / g.tw));
@@ -490,7 +550,8 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
         __syncthreads();
         const uint32_t it = s_item;   // pt_tile's barriers order this read before the next write
         if (it >= items) break;
-        const uint32_t t = it / g.chunks, s0 = (it % g.chunks) * g.chunk;
+        const uint32_t rank = it / g.chunks, s0 = (it % g.chunks) * g.chunk;
+        const uint32_t t = order ? order[rank] : rank;
         pt_tile<Acc, AOV, ENV>(acc, view.nx, view.ny, view.nz, cam, m, g, maj, cbits, (int)(t % tiles_x),
                                (int)(t / tiles_x), ts, tf_lds, image, aov, nsamp, ncell, nseg, s0,
                                min(s0 + g.chunk, (uint32_t)g.spp), sums);

@@ -430,6 +430,18 @@ static bool pt_split(const vdbc_render_params* r) { return r->chunk_spp != 0 && 
 // hits | escapes) + 8 (AOV depth) per pixel.
 static uint64_t pt_sums_bytes(uint64_t npix) { return align256(40ull * npix); }
 
+// 256-pixel tiles of a path-traced image: 4 tw x 64 / tw pixels each.
+static uint64_t pt_tiles_x(uint64_t width, uint64_t tw) { return (width + 4 * tw - 1) / (4 * tw); }
+static uint64_t pt_tiles(uint64_t width, uint64_t height, uint64_t tw)
+{
+    return pt_tiles_x(width, tw) * ((height + 64 / tw - 1) / (64 / tw));
+}
+
+// Bytes of the cost order (VDBC_RENDER_COST_ORDER): bin histogram and bin
+// offsets (kCostBins u32 each), then per tile its bin and its place in the
+// order (u32 each).
+static uint64_t pt_order_bytes(uint64_t tiles) { return align256(8ull * kCostBins + 8ull * tiles); }
+
 
 template <class Acc, class View>
 static vdbc_status launch_majorant(const View& v, const MediumK& m, uint32_t C, float* out,
@@ -551,9 +563,7 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
         return fail(VDBC_E_INVALID, "tile_w must be 0 (default 8), 8, 16, 32 or 64");
     {
         // the work-item queue counts in 32 bits
-        const uint64_t tw = r->tile_w == 0 ? 8 : r->tile_w;
-        const uint64_t tiles = ((uint64_t)cam.width + 4 * tw - 1) / (4 * tw) *
-                               (((uint64_t)cam.height + 64 / tw - 1) / (64 / tw));
+        const uint64_t tiles = pt_tiles((uint64_t)cam.width, (uint64_t)cam.height, r->tile_w == 0 ? 8 : r->tile_w);
         const uint64_t per_tile = pt_split(r) ? (r->spp + r->chunk_spp - 1) / r->chunk_spp : 1;
         if (tiles * per_tile > 0xFFFFFFFFull)
             return fail(VDBC_E_INVALID, "more than 2^32 work items: raise chunk_spp");
@@ -588,9 +598,11 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
     uint32_t* coarse = reinterpret_cast<uint32_t*>(
         static_cast<uint8_t*>(ws) + 256 + align256(majorant_bytes(r->macrocell, v.nx, v.ny, v.nz)));
     const uint64_t npix = (uint64_t)cam.width * (uint64_t)cam.height;
+    const uint64_t tiles = pt_tiles((uint64_t)cam.width, (uint64_t)cam.height, (uint64_t)g.tw);
+    uint8_t* const tail = static_cast<uint8_t*>(ws) + pt_workspace(r->macrocell, v.nx, v.ny, v.nz);
     PtSums sums{};
     if (split) {
-        uint8_t* base = static_cast<uint8_t*>(ws) + pt_workspace(r->macrocell, v.nx, v.ny, v.nz);
+        uint8_t* base = tail;
         sums.rgbn = reinterpret_cast<unsigned long long*>(base);
         sums.depth = sums.rgbn + 4 * npix;
         const uint64_t words = pt_sums_bytes(npix) / 16;
@@ -604,16 +616,28 @@ static vdbc_status render_impl(const View& v, const vdbc_camera* c, const vdbc_m
                            dim3(kBlock), 0, st, maj, g, coarse);
         if ((s = launch_check("coarse occupancy"))) return s;
     }
-    const size_t lds = 4u * (size_t)g.cwords;
-    {
-        const uint64_t tiles = (uint64_t)((cam.width + 4 * g.tw - 1) / (4 * g.tw)) *
-                               (uint64_t)((cam.height + 64 / g.tw - 1) / (64 / g.tw));
-        grid = dim3((unsigned)std::min<uint64_t>(tiles * g.chunks, (uint64_t)device_cus() * kPtBlocksPerCu));
+    const uint32_t* order = nullptr;
+    if (r->flags & VDBC_RENDER_COST_ORDER) {
+        uint32_t* hist = reinterpret_cast<uint32_t*>(tail + (split ? pt_sums_bytes(npix) : 0));
+        uint32_t* off = hist + kCostBins;
+        uint32_t* key = off + kCostBins;
+        uint32_t* ord = key + tiles;
+        const unsigned tb = (unsigned)((tiles + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(pt_sums_clear_kernel, dim3(1), dim3(kBlock), 0, st, reinterpret_cast<uint4*>(hist),
+                           (uint64_t)(2 * kCostBins / 4));
+        hipLaunchKernelGGL(pt_tile_cost_kernel, dim3(tb), dim3(kBlock), 0, st, cam, g, v.nx, v.ny, v.nz, maj,
+                           (uint32_t)pt_tiles_x((uint64_t)cam.width, (uint64_t)g.tw), (uint32_t)tiles, key, hist);
+        hipLaunchKernelGGL(pt_cost_offsets_kernel, dim3(1), dim3(64), 0, st, hist, off);
+        hipLaunchKernelGGL(pt_cost_scatter_kernel, dim3(tb), dim3(kBlock), 0, st, key, off, ord, (uint32_t)tiles);
+        if ((s = launch_check("cost order"))) return s;
+        order = ord;
     }
+    const size_t lds = 4u * (size_t)g.cwords;
+    grid = dim3((unsigned)std::min<uint64_t>(tiles * g.chunks, (uint64_t)device_cus() * kPtBlocksPerCu));
     uint32_t* queue = reinterpret_cast<uint32_t*>(counter + 2);
 #define PT_LAUNCH(CNT, AO, EN)                                                                     \
     hipLaunchKernelGGL((pt_kernel<Acc, View, CNT, AO, EN>), grid, dim3(kBlock), lds, st, v, cam, m, \
-                       g, maj, coarse, image, aov, counter, queue, sums)
+                       g, maj, coarse, image, aov, counter, queue, sums, order)
 #define PT_LAUNCH_ENV(CNT, AO)           \
     if (m.env) PT_LAUNCH(CNT, AO, true); \
     else PT_LAUNCH(CNT, AO, false)
@@ -651,6 +675,12 @@ extern "C" vdbc_status vdbc_render_workspace(const vdbc_render_params* r, vdbc_d
         if (pt_split(r)) {
             if (!c) return fail(VDBC_E_INVALID, "0 < chunk_spp < spp: the workspace size needs the camera");
             *bytes += pt_sums_bytes((uint64_t)c->width * (uint64_t)c->height);
+        }
+        if (r->flags & VDBC_RENDER_COST_ORDER) {
+            if (!c) return fail(VDBC_E_INVALID, "VDBC_RENDER_COST_ORDER: the workspace size needs the camera");
+            if (r->tile_w != 0 && r->tile_w != 8 && r->tile_w != 16 && r->tile_w != 32 && r->tile_w != 64)
+                return fail(VDBC_E_INVALID, "tile_w must be 0 (default 8), 8, 16, 32 or 64");
+            *bytes += pt_order_bytes(pt_tiles(c->width, c->height, r->tile_w == 0 ? 8 : r->tile_w));
         }
     } else {
         *bytes = (r->flags & VDBC_RENDER_COUNT) ? 256 : 0;
@@ -861,7 +891,8 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         g.rr = 0;
         g.chunk = g.spp;
         g.chunks = 1;
-        const int tx = (cam.width + 4 * g.tw - 1) / (4 * g.tw), ty = (cam.height + 64 / g.tw - 1) / (64 / g.tw);
+        const int tx = (int)pt_tiles_x((uint64_t)cam.width, (uint64_t)g.tw),
+                  ty = (int)(pt_tiles((uint64_t)cam.width, (uint64_t)cam.height, (uint64_t)g.tw) / (uint64_t)tx);
         if ((uint64_t)tx * ty > 0xFFFFFu) return fail(VDBC_E_INVALID, "batch item %u: image too large", i);
         b->views.push_back(v);
         b->cams.push_back(cam);
@@ -917,11 +948,11 @@ static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
         if (b->meds[i].env)
             hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, true>), grid, dim3(kBlock),
                                4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{});
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{}, nullptr);
         else
             hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, false>), grid, dim3(kBlock),
                                4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{});
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{}, nullptr);
         if ((s = launch_check("per-volume render"))) return s;
     }
     return VDBC_OK;

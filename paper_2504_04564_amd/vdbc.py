@@ -20,7 +20,7 @@ OK, E_INVALID, E_NOMEM, E_BUFFER_TOO_SMALL, E_FORMAT, E_DEVICE, E_UNSUPPORTED = 
 BG_EXPLICIT, NO_CORNERS, NO_PRUNE, PARTIAL = 1, 2, 4, 8
 MODE_EA, MODE_PT, MODE_ISO = 0, 1, 2
 RENDER_HDDA, RENDER_COUNT, RENDER_KEEP_MAJORANT, RENDER_RR = 1, 2, 4, 8
-RENDER_CACHE_NONE, RENDER_CACHE_LEAF = 16, 32
+RENDER_CACHE_NONE, RENDER_CACHE_LEAF, RENDER_COST_ORDER = 16, 32, 64
 # accessor cache policy -> render flag (2 = last leaf and last lower node, the default)
 CACHE_FLAGS = {0: RENDER_CACHE_NONE, 1: RENDER_CACHE_LEAF, 2: 0}
 # node layouts (bits): Morton child-slot order, SoA node words

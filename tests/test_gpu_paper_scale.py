@@ -1,7 +1,8 @@
 """GPU parity at the paper-scale size, in the benchmark's launch: the
 1987 x 1351 x 2449 billowed cloud (26.3 GB dense) at 1:10, the majorant grid
 of the whole volume at macrocell 64, the path tracer at 1920 x 1080 x 64 spp
-with at most 16 bounces, 8 x 8 wave tiles and work items of 8 samples, and
+with at most 16 bounces, 16 x 4 wave tiles, work items of 8 samples and the
+cost-ordered work queue, and
 random trilinear samples
 in the bricks that hold a non-background voxel.  The oracle computes the
 majorant grid (threaded over disjoint cell ranges), a sample of the image's
@@ -20,7 +21,7 @@ from synth import scenes
 pytestmark = pytest.mark.gpu
 
 THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
-C, TW, CHUNK = 64, 8, 8
+C, TW, CHUNK = 64, 16, 8
 
 
 def relmse(x, y):
@@ -67,7 +68,7 @@ def test_paper_scale_path_tracer_sampled_pixels(paper):
     dims = P["dims"]
     cam = scenes.orbit_camera(dims, P["width"], P["height"])
     prm = dict(spp=P["spp"], max_bounces=P["max_bounces"], seed=P["seed"], macrocell=C, tile_w=TW,
-               chunk_spp=CHUNK)
+               chunk_spp=CHUNK, flags=vdbc.RENDER_COST_ORDER)
     img = vdbc.render(paper["grid"], cam, paper["med"], prm, vdbc.MODE_PT).cpu().numpy().reshape(-1, 4)
     assert np.all(np.isfinite(img))
     rng = np.random.default_rng(62)

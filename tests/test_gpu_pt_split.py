@@ -127,3 +127,21 @@ def test_split_paper_launch_sampled_pixels():
     want = oracle.render_pt(oracle.VdbField(buf), cam, med, prm, pixels=pix)
     assert relmse(img[pix], want) <= 1e-4
     assert np.count_nonzero(want[:, 3] > 0) >= 16
+
+
+@pytest.mark.parametrize("tw,chunk", [(8, 0), (8, 3), (64, 4)])
+def test_cost_order_bit_identical(tw, chunk):
+    # tiles handed out in decreasing estimated cost instead of raster order:
+    # the same image, AOV and counts, on VDB and dense volumes
+    v = synth.mid_volume(n=64)
+    buf, _ = vdbc.encode(v, 0.10)
+    cam, med, prm = _scene(64, 70, 33, 12)
+    prm.update(tile_w=tw, chunk_spp=chunk)
+    d = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+    for field, bg in ((vdbc.Grid(buf), None), (d, 0.0)):
+        r0 = _launch(field, cam, med, dict(prm, flags=vdbc.RENDER_COUNT), background=bg)
+        r1 = _launch(field, cam, med, dict(prm, flags=vdbc.RENDER_COUNT | vdbc.RENDER_COST_ORDER),
+                     stale=True, background=bg)
+        assert np.array_equal(_bits(r1.image), _bits(r0.image))
+        assert np.array_equal(_bits(r1.aov), _bits(r0.aov))
+        assert (r1.sample_count(), r1.segment_count()) == (r0.sample_count(), r0.segment_count())

@@ -258,6 +258,18 @@ def test_device_calls_reject_bad_arguments_before_launch(lib):
         want = vdbc.OK if extra == 0 else vdbc.E_INVALID
         assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == want
     pt.spp, pt.chunk_spp = 1, 0
+    # the cost order: 8 bytes per 256-pixel tile + 512, after the pixel sums;
+    # 100 x 30 pixels are 4 x 4 tiles of 32 x 8 (8-wide wave tiles) or 1 x 30
+    # tiles of 256 x 1 (64-wide rows)
+    pt.flags = vdbc.RENDER_COST_ORDER
+    for spp, chunk, tw, extra in ((1, 0, 8, 768), (1, 0, 64, 768), (8, 2, 8, 120064 + 768)):
+        pt.spp, pt.chunk_spp, pt.tile_w = spp, chunk, tw
+        assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(big), C.byref(ws)) == 0
+        assert ws.value == 768 + extra, (spp, chunk, tw)
+        assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), None, C.byref(ws)) == vdbc.E_INVALID
+    pt.tile_w = 128
+    assert lib.vdbc_render_workspace(C.byref(pt), vdbc.Dims(16, 16, 16), C.byref(big), C.byref(ws)) == vdbc.E_INVALID
+    pt.spp, pt.chunk_spp, pt.tile_w, pt.flags = 1, 0, 8, 0
     assert lib.vdbc_status_string(3) == b"buffer too small"
     # degenerate scenes are refused before launch
     zero_dir = vdbc.camera_c(dict(kind=0, width=4, height=4))

@@ -271,6 +271,8 @@ typedef struct {
     uint64_t seed;          /* PT Philox key material */
     uint32_t frame;         /* PT counter word 3 */
     uint32_t tile_w;        /* PT pixels per wave row: 8 (default; 0 = 8), 16, 32, 64;
+                               a wave covers tile_w x 64 / tile_w pixels and a
+                               workgroup's 256-pixel tile four of them side by side;
                                any other value -> VDBC_E_INVALID; the image does not
                                depend on it */
     float iso;              /* ISO: iso value */

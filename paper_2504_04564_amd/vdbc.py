@@ -349,6 +349,10 @@ def medium_c(med: dict) -> MediumC:
 
 
 def params_c(p: dict, mode: int) -> RenderParamsC:
+    """vdbc_render_params from a dict: spp (1), max_bounces (8), macrocell
+    (8), flags (0; RENDER_*), step (0.5), t_terminate (0), seed (0), frame
+    (0), tile_w (8: pixels per wave row), iso (0.5), refine (12), chunk_spp
+    (0: one work item per tile; else samples per work item)."""
     r = RenderParamsC()
     r.mode = mode
     r.spp = p.get("spp", 1)

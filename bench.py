@@ -36,7 +36,11 @@ BRICK = 32                        # brick edge of the encoder (Alg. 1)
 # majorant cell edge of each frame: the fastest candidate of the render
 # autotuner (--workload tune --tune-frame paper / mid) for both the VDB and
 # the dense array
-DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16}
+DEFAULT_MACROCELL = {"paper": 64, "sweep": 64, "mid": 16,
+                     # lossless noise: every block is a stored leaf, and at 16 the
+                     # majorant rebuild dominates both frames; 64 gives the fastest
+                     # frame for both arrays at 1024^3 and 2048^3
+                     "worstcase": 64}
 # wave tile width (pixels per wave row) of each frame, the same autotuner's
 # choice; the image does not depend on it
 DEFAULT_TILE_W = {"paper": 16, "sweep": 16, "mid": 16}

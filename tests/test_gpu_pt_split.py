@@ -145,3 +145,21 @@ def test_cost_order_bit_identical(tw, chunk):
         assert np.array_equal(_bits(r1.image), _bits(r0.image))
         assert np.array_equal(_bits(r1.aov), _bits(r0.aov))
         assert (r1.sample_count(), r1.segment_count()) == (r0.sample_count(), r0.segment_count())
+
+
+def test_noalloc_split_and_cost_order_equal_the_workspace_render():
+    # the allocation-free entry point keeps the pixel sums and the cost order
+    # in its fixed scratch: same bits as the render with a workspace, on two
+    # calls in a row (the second smaller), image and AOV
+    v = synth.mid_volume(n=64)
+    buf, _ = vdbc.encode(v, 0.10)
+    g = vdbc.Grid(buf)
+    for w, h, spp, chunk in ((96, 80, 12, 5), (40, 24, 6, 1)):
+        cam, med, prm = _scene(64, w, h, spp)
+        prm.update(tile_w=16, chunk_spp=chunk, flags=vdbc.RENDER_COST_ORDER)
+        ref = _launch(g, cam, med, prm)
+        aov = torch.empty((h, w, 2), dtype=torch.float32, device="cuda")
+        img = vdbc.render_noalloc(g, cam, med, prm, vdbc.MODE_PT, aov=aov)
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(img), _bits(ref.image)), (w, h)
+        assert np.array_equal(_bits(aov), _bits(ref.aov)), (w, h)

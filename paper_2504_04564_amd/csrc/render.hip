@@ -401,7 +401,10 @@ static void pt_geometry(uint32_t C, int nx, int ny, int nz, PtArgs* g)
     g->gy = (ny + g->C - 1) / g->C;
     g->gz = (nz + g->C - 1) / g->C;
     int lf = 0;
-    while ((C << (lf + 1)) <= 64) ++lf;      // block edge C * 2^lf <= 64 voxels
+    // coarse blocks of at least 4 macrocells and at least 64 voxels per axis
+    // (64 voxels up to C = 16, 4 cells from there on)
+    const uint32_t edge = std::max<uint32_t>(64u, 4u * C);
+    while ((C << (lf + 1)) <= edge) ++lf;
     for (;;) {
         const int F = 1 << lf;
         g->lf = lf;

@@ -641,9 +641,9 @@ def test_pt_env_map_axis_directions(direction, texel):
 
 @pytest.mark.parametrize("C", [4, 32, 64])
 def test_pt_macrocell_sizes_vs_oracle(C):
-    # the coarse-block skip covers 2^lf macrocells with C * 2^lf <= 64 voxels:
-    # lf = 4 at C = 4, lf = 1 at C = 32, none at C = 64; each must follow the
-    # oracle's uniform walk
+    # the coarse-block skip covers 2^lf macrocells, blocks of at least 4 cells
+    # and 64 voxels per axis: lf = 4 at C = 4, lf = 2 at C = 32 and 64; each
+    # must follow the oracle's uniform walk
     v = synth.mid_volume(n=80)
     buf, _ = vdbc.encode(v, 0.25)
     cam, med, prm = _pt_scene(80, 40, 36, 3)

@@ -376,6 +376,12 @@ typedef struct {
     uint32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4) */
     uint32_t persistent;     /* 1: one persistent launch over all (volume, tile)
                                 items; 0: one launch per volume */
+    uint32_t chunk_spp;      /* samples per work item: 0 (or >= a volume's spp)
+                                keeps one item per tile; 0 < chunk_spp < spp
+                                splits each tile of that volume into
+                                ceil(spp / chunk_spp) items whose pixels meet in
+                                integer sums in the workspace (bit-identical
+                                images); at most 2^20 - 1 items per volume */
 } vdbc_tuning;
 
 typedef struct vdbc_batch vdbc_batch;

@@ -27,7 +27,7 @@ RENDER_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32, 64), "cache"
 # raster-order candidates (a second stage instead of doubling the grid)
 ORDER_STAGE = 8
 BATCH_SPACE = {"macrocell": (8, 16, 32, 64), "tile_w": (8, 16, 32), "blocks_per_cu": (2, 4, 8),
-               "persistent": (1,)}
+               "persistent": (1,), "chunk_spp": (0, 1, 2, 4)}
 
 
 def _median_ms(fn, reps: int) -> float:
@@ -101,18 +101,30 @@ def tune_render(field, camera: dict, medium: dict, params: dict, background=None
 
 
 def tune_batch(items: list, space: dict | None = None, reps: int = 5):
-    """Best batched-launch tuning for a list of batch items."""
+    """Best batched-launch tuning for a list of batch items: the grid over
+    macrocell, wave tile width, workgroups per CU and launch kind with whole
+    tiles as work items, then the item sizes of `chunk_spp` (if the space
+    has them) at the fastest candidate of the grid."""
     space = space or BATCH_SPACE
+
+    def timed(t):
+        b = vdbc.Batch(items, t)
+        ms = _median_ms(b.launch, reps)
+        b.close()
+        return dict(t, ms=ms)
+
     results = []
     for C_ in space["macrocell"]:
         for tw in space["tile_w"]:
             for bpc in space["blocks_per_cu"]:
                 for pers in space["persistent"]:
-                    t = dict(macrocell=C_, tile_w=tw, blocks_per_cu=bpc, persistent=pers)
-                    b = vdbc.Batch(items, t)
-                    ms = _median_ms(b.launch, reps)
-                    b.close()
-                    results.append(dict(t, ms=ms))
+                    results.append(timed(dict(macrocell=C_, tile_w=tw, blocks_per_cu=bpc, persistent=pers,
+                                              chunk_spp=0)))
+    best = min(results, key=lambda x: x["ms"])
+    for ch in space.get("chunk_spp", ()):
+        if ch:
+            t = {k: v for k, v in best.items() if k != "ms"}
+            results.append(timed(dict(t, chunk_spp=ch)))
     best = min(results, key=lambda x: x["ms"])
     return best, results
 

@@ -564,10 +564,12 @@ __global__ __launch_bounds__(kBlock, 4) void pt_kernel(View view, CameraK cam, M
 }
 
 // ---------------------------------------------------------------- batched PT
-// Many volumes in one persistent launch: workgroups pull (volume, tile) items
-// from an atomic counter over a list ordered by estimated cost (largest
-// first) and render each tile with the per-pixel code of pt_kernel, so every
-// image is bit-identical to its own launch.
+// Many volumes in one persistent launch: workgroups pull (volume, work item)
+// entries from an atomic counter over a list ordered by estimated cost
+// (largest first) and render each item with the per-pixel code of pt_kernel,
+// so every image is bit-identical to its own launch.  A volume's items are
+// its tiles, or with g.chunks > 1 each tile's chunks of g.chunk samples
+// (item = tile * g.chunks + chunk), which add into the volume's pixel sums.
 struct BatchDesc {
     VdbView view;
     CameraK cam;
@@ -576,6 +578,7 @@ struct BatchDesc {
     const float* maj;
     const uint32_t* coarse;
     float* image;
+    PtSums sums;   // per-pixel integer sums when g.chunks > 1, else null
     int tiles_x;
 };
 
@@ -600,8 +603,9 @@ __global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __
         if (it >= n_items) break;
         const uint32_t code = __builtin_amdgcn_readfirstlane(items[it]);
         const BatchDesc* D = descs + (code >> 20);
-        const uint32_t tile = code & 0xFFFFFu;
         const PtArgs g = D->g;
+        const uint32_t sub = code & 0xFFFFFu;
+        const uint32_t tile = sub / g.chunks, s0 = (sub % g.chunks) * g.chunk;
         const CameraK cam = D->cam;
         for (int i = threadIdx.x; i < g.cwords; i += kBlock) cbits[i] = D->coarse[i];
         for (int i = threadIdx.x; i < D->med.tf_n; i += kBlock) tf_lds[i] = D->med.tf[i];
@@ -611,7 +615,8 @@ __global__ __launch_bounds__(kBlock, 4) void pt_batch_kernel(const BatchDesc* __
         uint32_t ns = 0, nc = 0, nsg = 0;
         pt_tile<VdbAcc, false, true>(acc, D->view.nx, D->view.ny, D->view.nz, cam, D->med, g, D->maj, cbits,
                                (int)(tile % (uint32_t)D->tiles_x), (int)(tile / (uint32_t)D->tiles_x), ts,
-                               tf_lds, D->image, nullptr, ns, nc, nsg, 0u, (uint32_t)g.spp, PtSums{});
+                               tf_lds, D->image, nullptr, ns, nc, nsg, s0, min(s0 + g.chunk, (uint32_t)g.spp),
+                               D->sums);
     }
 }
 

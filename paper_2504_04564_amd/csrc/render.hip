@@ -828,6 +828,7 @@ struct vdbc_batch {
     std::vector<float*> majs;
     std::vector<uint32_t*> coarse;
     std::vector<float*> images;
+    std::vector<PtSums> sums;          // per volume: pixel sums of split items, or null
     std::vector<int> tiles_x, tiles_y;
     BatchDesc* d_descs = nullptr;
     uint32_t* d_items = nullptr;
@@ -843,7 +844,7 @@ namespace vdbc {
 
 static vdbc_status batch_tuning(const vdbc_tuning* t, vdbc_tuning* out)
 {
-    vdbc_tuning d{16, 8, 4, 1};
+    vdbc_tuning d{16, 8, 4, 1, 0};
     if (t) d = *t;
     if (d.macrocell < 4 || d.macrocell > 64 || (d.macrocell & (d.macrocell - 1)))
         return fail(VDBC_E_INVALID, "tuning.macrocell must be 4, 8, 16, 32 or 64");
@@ -856,12 +857,17 @@ static vdbc_status batch_tuning(const vdbc_tuning* t, vdbc_tuning* out)
     return VDBC_OK;
 }
 
-// Validates the items and fills the per-volume launch state; `layout`
-// receives the workspace offsets (counter, descriptors, item list, then per
-// volume majorant and coarse bits) and the total size.
+// Bytes of a batch volume's pixel sums (32 per pixel: RGB and the hit and
+// escape counts; the batched launch writes no depth).
+static uint64_t batch_sums_bytes(uint64_t npix) { return align256(32ull * npix); }
+
+// Validates the items and fills the per-volume launch state; the offsets
+// receive the workspace layout (counter, descriptors, item list, then per
+// volume majorant, coarse bits and, for a split volume, its pixel sums; 0 for
+// a volume that is not split) and the total size.
 static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vdbc_tuning& t, vdbc_batch* b,
                               std::vector<uint64_t>* maj_off, std::vector<uint64_t>* coarse_off,
-                              uint64_t* items_off, uint64_t* total)
+                              std::vector<uint64_t>* sums_off, uint64_t* items_off, uint64_t* total)
 {
     if (!items || n == 0 || n > 4096) return fail(VDBC_E_INVALID, "need 1..4096 batch items");
     b->n = n;
@@ -892,11 +898,13 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         g.seed_hi = (uint32_t)(it.seed >> 32);
         g.frame = it.frame;
         g.rr = 0;
-        g.chunk = g.spp;
-        g.chunks = 1;
+        const bool split = t.chunk_spp != 0 && t.chunk_spp < it.spp;
+        g.chunk = split ? t.chunk_spp : (uint32_t)g.spp;
+        g.chunks = split ? (it.spp + t.chunk_spp - 1) / t.chunk_spp : 1u;
         const int tx = (int)pt_tiles_x((uint64_t)cam.width, (uint64_t)g.tw),
                   ty = (int)(pt_tiles((uint64_t)cam.width, (uint64_t)cam.height, (uint64_t)g.tw) / (uint64_t)tx);
-        if ((uint64_t)tx * ty > 0xFFFFFu) return fail(VDBC_E_INVALID, "batch item %u: image too large", i);
+        if ((uint64_t)tx * ty * g.chunks > 0xFFFFFu)
+            return fail(VDBC_E_INVALID, "batch item %u: image too large for %u work items per tile", i, g.chunks);
         b->views.push_back(v);
         b->cams.push_back(cam);
         b->meds.push_back(m);
@@ -904,7 +912,7 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         b->images.push_back(it.image);
         b->tiles_x.push_back(tx);
         b->tiles_y.push_back(ty);
-        tiles_total += (uint64_t)tx * ty;
+        tiles_total += (uint64_t)tx * ty * g.chunks;
         b->max_cwords = std::max(b->max_cwords, g.cwords);
     }
     uint64_t o = 256;                                   // counter
@@ -917,10 +925,30 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
         o += align256(majorant_bytes(t.macrocell, b->views[i].nx, b->views[i].ny, b->views[i].nz));
         coarse_off->push_back(o);
         o += align256(4ull * b->gs[i].cwords);
+        if (b->gs[i].chunks > 1) {
+            sums_off->push_back(o);
+            o += batch_sums_bytes((uint64_t)b->cams[i].width * b->cams[i].height);
+        } else {
+            sums_off->push_back(0);
+        }
     }
     (void)descs_off;
     b->n_items = (uint32_t)tiles_total;
     *total = o;
+    return VDBC_OK;
+}
+
+// The images of the split volumes from their pixel sums.
+static vdbc_status batch_resolve(vdbc_batch* b, hipStream_t st)
+{
+    for (uint32_t i = 0; i < b->n; ++i) {
+        if (!b->sums[i].rgbn) continue;
+        const uint64_t npix = (uint64_t)b->cams[i].width * b->cams[i].height;
+        hipLaunchKernelGGL(pt_resolve_kernel, dim3((unsigned)((npix + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           b->sums[i], b->images[i], nullptr, (uint32_t)npix, b->gs[i].spp);
+        vdbc_status s = launch_check("batch pixel sums to image");
+        if (s) return s;
+    }
     return VDBC_OK;
 }
 
@@ -934,31 +962,39 @@ static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
         hipLaunchKernelGGL(coarse_bits_kernel, dim3((unsigned)((ncoarse + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            st, b->majs[i], g, b->coarse[i]);
         if ((s = launch_check("batch coarse occupancy"))) return s;
+        if (b->sums[i].rgbn) {
+            const uint64_t words = batch_sums_bytes((uint64_t)b->cams[i].width * b->cams[i].height) / 16;
+            hipLaunchKernelGGL(pt_sums_clear_kernel,
+                               dim3((unsigned)std::min<uint64_t>((words + kBlock - 1) / kBlock, 4096)), dim3(kBlock), 0,
+                               st, reinterpret_cast<uint4*>(b->sums[i].rgbn), words);
+            if ((s = launch_check("batch pixel sums clear"))) return s;
+        }
     }
     if (b->t.persistent) {
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, b->d_counter);
         hipLaunchKernelGGL(pt_batch_kernel, dim3(b->grid_blocks), dim3(kBlock), 4u * (size_t)b->max_cwords, st,
                            b->d_descs, b->d_items, b->n_items, b->d_counter);
-        return launch_check("batched render");
+        if ((s = launch_check("batched render"))) return s;
+        return batch_resolve(b, st);
     }
     // one launch per volume; the launches run in stream order, so they share
     // the tile queue, cleared before each
     for (uint32_t i = 0; i < b->n; ++i) {
         const PtArgs& g = b->gs[i];
-        const uint32_t tiles = (uint32_t)(b->tiles_x[i] * b->tiles_y[i]);
+        const uint32_t items = (uint32_t)(b->tiles_x[i] * b->tiles_y[i]) * g.chunks;
         hipLaunchKernelGGL(zero_u32, dim3(1), dim3(64), 0, st, b->d_counter);
-        const dim3 grid(std::min<uint32_t>(tiles, (uint32_t)b->grid_blocks));
+        const dim3 grid(std::min<uint32_t>(items, (uint32_t)b->grid_blocks));
         if (b->meds[i].env)
             hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, true>), grid, dim3(kBlock),
                                4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{}, nullptr);
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, b->sums[i], nullptr);
         else
             hipLaunchKernelGGL((pt_kernel<VdbAcc, VdbView, false, false, false>), grid, dim3(kBlock),
                                4u * (size_t)g.cwords, st, b->views[i], b->cams[i], b->meds[i], g, b->majs[i],
-                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, PtSums{}, nullptr);
+                               b->coarse[i], b->images[i], nullptr, nullptr, b->d_counter, b->sums[i], nullptr);
         if ((s = launch_check("per-volume render"))) return s;
     }
-    return VDBC_OK;
+    return batch_resolve(b, st);
 }
 
 }  // namespace vdbc
@@ -972,9 +1008,9 @@ extern "C" vdbc_status vdbc_batch_workspace(const vdbc_batch_item* items, uint32
     vdbc_status s = batch_tuning(t, &tt);
     if (s) return s;
     vdbc_batch b;
-    std::vector<uint64_t> mo, co;
+    std::vector<uint64_t> mo, co, so;
     uint64_t io, total;
-    if ((s = batch_plan(items, n, tt, &b, &mo, &co, &io, &total))) return s;
+    if ((s = batch_plan(items, n, tt, &b, &mo, &co, &so, &io, &total))) return s;
     *bytes = total;
     return VDBC_OK;
 }
@@ -991,9 +1027,9 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
     if (s) return s;
     std::unique_ptr<vdbc_batch> b(new (std::nothrow) vdbc_batch());
     if (!b) return fail(VDBC_E_NOMEM, "no memory");
-    std::vector<uint64_t> mo, co;
+    std::vector<uint64_t> mo, co, so;
     uint64_t io, total;
-    if ((s = batch_plan(items, n, tt, b.get(), &mo, &co, &io, &total))) return s;
+    if ((s = batch_plan(items, n, tt, b.get(), &mo, &co, &so, &io, &total))) return s;
     if (ws_bytes < total)
         return fail(VDBC_E_BUFFER_TOO_SMALL, "batch workspace needs %llu bytes", (unsigned long long)total);
     uint8_t* w = static_cast<uint8_t*>(ws);
@@ -1003,6 +1039,7 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
     for (uint32_t i = 0; i < n; ++i) {
         b->majs.push_back(reinterpret_cast<float*>(w + mo[i]));
         b->coarse.push_back(reinterpret_cast<uint32_t*>(w + co[i]));
+        b->sums.push_back(so[i] ? PtSums{reinterpret_cast<unsigned long long*>(w + so[i]), nullptr} : PtSums{});
     }
     // descriptors and the cost-ordered work list (largest estimated cost first:
     // samples per pixel x ray length through the volume)
@@ -1010,7 +1047,7 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
     std::vector<uint32_t> order(n);
     for (uint32_t i = 0; i < n; ++i) {
         descs[i] = BatchDesc{b->views[i], b->cams[i], b->meds[i], b->gs[i], b->majs[i], b->coarse[i], b->images[i],
-                             b->tiles_x[i]};
+                             b->sums[i], b->tiles_x[i]};
         order[i] = i;
     }
     auto cost = [&](uint32_t i) {
@@ -1020,7 +1057,8 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
     std::vector<uint32_t> list;
     list.reserve(b->n_items);
     for (uint32_t i : order)
-        for (uint32_t tl = 0; tl < (uint32_t)(b->tiles_x[i] * b->tiles_y[i]); ++tl) list.push_back((i << 20) | tl);
+        for (uint32_t k = 0; k < (uint32_t)(b->tiles_x[i] * b->tiles_y[i]) * b->gs[i].chunks; ++k)
+            list.push_back((i << 20) | k);
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(b->d_descs, descs.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(b->d_items, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||

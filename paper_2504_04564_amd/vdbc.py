@@ -686,7 +686,7 @@ class BatchItemC(C.Structure):
 
 class TuningC(C.Structure):
     _fields_ = [("macrocell", C.c_uint32), ("tile_w", C.c_uint32),
-                ("blocks_per_cu", C.c_uint32), ("persistent", C.c_uint32)]
+                ("blocks_per_cu", C.c_uint32), ("persistent", C.c_uint32), ("chunk_spp", C.c_uint32)]
 
 
 def _batch_signatures(L):
@@ -714,7 +714,7 @@ def _bt():
 def tuning_c(t: dict | None) -> TuningC:
     t = t or {}
     return TuningC(t.get("macrocell", 16), t.get("tile_w", 8), t.get("blocks_per_cu", 4),
-                   int(t.get("persistent", 1)))
+                   int(t.get("persistent", 1)), int(t.get("chunk_spp", 0)))
 
 
 class Batch:

@@ -52,9 +52,15 @@ def _same(a, b):
     return torch.equal(a.view(torch.int32), b.view(torch.int32))
 
 
+# chunk_spp splits the tiles of every volume with more samples than that into
+# work items (the items' spp are 1..4: chunk 3 leaves a ragged last item and
+# some volumes whole, so one batch mixes split and whole volumes)
 @pytest.mark.parametrize("tuning", [dict(macrocell=16, tile_w=8, blocks_per_cu=4, persistent=1),
                                     dict(macrocell=8, tile_w=16, blocks_per_cu=2, persistent=1),
-                                    dict(macrocell=16, tile_w=32, blocks_per_cu=1, persistent=0)])
+                                    dict(macrocell=16, tile_w=32, blocks_per_cu=1, persistent=0),
+                                    dict(macrocell=16, tile_w=8, blocks_per_cu=4, persistent=1, chunk_spp=1),
+                                    dict(macrocell=8, tile_w=16, blocks_per_cu=2, persistent=1, chunk_spp=3),
+                                    dict(macrocell=16, tile_w=32, blocks_per_cu=1, persistent=0, chunk_spp=2)])
 def test_batch_equals_single_launches(tuning):
     items = _items()
     ref = [_single(it, tuning["macrocell"]) for it in items]
@@ -92,10 +98,12 @@ def test_batch_images_match_oracle_with_coloured_tfs():
     b.close()
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("chunk_spp", [0, 2])
+def test_graph_replays_match_eager(chunk_spp):
+    # with chunk_spp 2 every replay also clears and resolves the pixel sums
     items = _items(8, seed=5)
     ref = [_single(it, 16) for it in items]
-    b = vdbc.Batch(items, dict(macrocell=16))
+    b = vdbc.Batch(items, dict(macrocell=16, chunk_spp=chunk_spp))
     s = torch.cuda.Stream()
     torch.cuda.synchronize()
     b.capture(s)
@@ -119,6 +127,11 @@ def test_autotuner_picks_a_measured_candidate(tmp_path):
                                                  blocks_per_cu=(2, 4), persistent=(0, 1)), reps=2)
     assert best in allr and len(allr) == 8
     assert best["ms"] == min(r["ms"] for r in allr)
+    # the item sizes are a second stage at the fastest whole-tile candidate
+    best2, allr2 = autotune.tune_batch(items, dict(macrocell=(16,), tile_w=(8,), blocks_per_cu=(4,),
+                                                   persistent=(1,), chunk_spp=(0, 1, 2)), reps=2)
+    assert [r["chunk_spp"] for r in allr2] == [0, 1, 2]
+    assert best2["ms"] == min(r["ms"] for r in allr2)
     it = items[0]
     prm = dict(spp=it["spp"], max_bounces=it["max_bounces"], seed=it["seed"])
     path = str(tmp_path / "tune.json")

@@ -307,6 +307,43 @@ def test_binding_structs_match_c_header(tmp_path):
     assert got == want
 
 
+def test_batch_workspace_holds_the_pixel_sums_of_split_volumes(lib):
+    # vdbc_batch_workspace plans on the host only (the grid's device pointer
+    # and the images are never touched); a volume whose spp exceeds chunk_spp
+    # gets 32 bytes of pixel sums per pixel, the others none
+    vdbc._batch_signatures(lib)
+    g = vdbc.GridC()
+    buf, _ = vdbc.encode(_rand((16, 16, 16), 1), 0.5)
+    assert lib.vdbc_grid_init(C.byref(g), 512, buf.size, buf.ctypes.data) == vdbc.OK
+    items = (vdbc.BatchItemC * 2)()
+    for it, spp in zip(items, (8, 2)):
+        it.grid = g
+        it.camera = vdbc.camera_c(dict(kind=0, width=100, height=30, dir=(0, 0, 1)))
+        it.medium = vdbc.medium_c(dict(sigma_scale=1.0, tf=[(0, 0, 0, 0), (1, 1, 1, 1)]))
+        it.spp, it.max_bounces, it.image = spp, 4, 4096
+
+    def ws(**t):
+        n = C.c_uint64(0)
+        st = lib.vdbc_batch_workspace(C.cast(items, C.c_void_p), 2, C.byref(vdbc.tuning_c(t)), C.byref(n))
+        return st, n.value
+
+    st, whole = ws(macrocell=8)
+    assert st == vdbc.OK
+    for chunk, extra in ((0, 0), (8, 0), (9, 0), (4, 96000), (3, 96000), (1, 2 * 96000)):
+        st, n = ws(macrocell=8, chunk_spp=chunk)
+        assert st == vdbc.OK
+        # align256(32 * 3000) = 96000 per split volume; the item list holds 4
+        # bytes per work item (16 tiles of 32 x 8 pixels each) in 256-byte steps
+        chunks = [(spp + chunk - 1) // chunk if 0 < chunk < spp else 1 for spp in (8, 2)]
+        list_extra = -(-sum(16 * c for c in chunks) * 4 // 256) * 256 - 256
+        assert n == whole + extra + list_extra, (chunk, n, whole)
+    # more than 2^20 - 1 work items for one volume is refused before any launch
+    items[0].camera = vdbc.camera_c(dict(kind=0, width=2048, height=2048, dir=(0, 0, 1)))
+    items[0].spp = 65536
+    assert ws(macrocell=8, chunk_spp=1)[0] == vdbc.E_INVALID
+    assert ws(macrocell=8)[0] == vdbc.OK
+
+
 def test_iso_and_compare_reject_bad_arguments_before_launch(lib):
     # iso-surface mode and the compression-error call validate everything on
     # the host, so these run without a GPU

@@ -27,10 +27,11 @@ struct PtArgs {
 // Occupancy of the coarse blocks: bit set iff some macrocell of the block has
 // a non-zero majorant.  One thread per block; a wave ballot assembles two
 // 32-bit words per wave.
-__global__ __launch_bounds__(kBlock) void coarse_bits_kernel(const float* __restrict__ maj,
-                                                             PtArgs g, uint32_t* __restrict__ bits)
+// Workgroup `blk` of that launch (the whole workgroup calls it).
+__device__ inline void coarse_bits_block(const float* __restrict__ maj, const PtArgs& g, uint32_t* __restrict__ bits,
+                                         uint32_t blk)
 {
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cell = (int)blk * blockDim.x + threadIdx.x;
     const int ncoarse = g.cgx * g.cgy * g.cgz;
     const int F = 1 << g.lf;
     bool occ = false;
@@ -46,9 +47,15 @@ __global__ __launch_bounds__(kBlock) void coarse_bits_kernel(const float* __rest
     }
     const uint64_t ballot = __ballot(occ);
     const int lane = threadIdx.x & 63;
-    const int w = (blockIdx.x * blockDim.x + threadIdx.x - lane) >> 5;   // first word of the wave
+    const int w = ((int)blk * blockDim.x + threadIdx.x - lane) >> 5;   // first word of the wave
     if (lane == 0 && w < g.cwords) bits[w] = (uint32_t)ballot;
     if (lane == 0 && w + 1 < g.cwords) bits[w + 1] = (uint32_t)(ballot >> 32);
+}
+
+__global__ __launch_bounds__(kBlock) void coarse_bits_kernel(const float* __restrict__ maj,
+                                                             PtArgs g, uint32_t* __restrict__ bits)
+{
+    coarse_bits_block(maj, g, bits, blockIdx.x);
 }
 
 // One ray segment being tracked through the majorant grid (Section 4): a 3D

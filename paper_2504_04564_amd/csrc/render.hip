@@ -31,13 +31,12 @@ __global__ void zero_u64(unsigned long long* p)
 // the largest macrocell, 64.
 constexpr int kMajorantQueue = 11 * 11 * 11;
 
-template <class Acc, class View>
-__global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, int C, int gx,
-                                                          int gy, int gz, float* __restrict__ out)
+// The majorant of macrocell `cell` of a gx x gy x .. grid, by the whole
+// workgroup; thread 0 writes it.
+template <class Acc>
+__device__ void majorant_cell(Acc& acc, const MediumK& m, int C, int gx, int gy, uint32_t cell,
+                              float* __restrict__ out)
 {
-    Acc acc{view};
-    acc.reset();
-    const uint32_t cell = blockIdx.x;
     const int cx = (int)(cell % (uint32_t)gx), cy = (int)((cell / (uint32_t)gx) % (uint32_t)gy),
               cz = (int)(cell / ((uint32_t)gx * (uint32_t)gy));
     const int E = C + 2, x0 = C * cx - 1, y0 = C * cy - 1, z0 = C * cz - 1;
@@ -121,6 +120,16 @@ __global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, 
     for (int q = 0; q < m.tf_n; ++q)
         if ((float)q > p0 && (float)q < p1) a = fmaxf(a, m.tf[q].w);
     out[cell] = m.ds * a;
+}
+
+template <class Acc, class View>
+__global__ __launch_bounds__(kBlock) void majorant_kernel(View view, MediumK m, int C, int gx,
+                                                          int gy, int gz, float* __restrict__ out)
+{
+    (void)gz;
+    Acc acc{view};
+    acc.reset();
+    majorant_cell(acc, m, C, gx, gy, blockIdx.x, out);
 }
 
 // ---------------------------------------------------------------- EA
@@ -816,6 +825,53 @@ extern "C" vdbc_status vdbc_majorant_dense(const float* dense, vdbc_dims d, floa
     return launch_majorant<DenseAcc>(v, m, C, out, static_cast<hipStream_t>(stream));
 }
 
+// ---------------------------------------------------------------- batched majorants
+// The majorant grids and the coarse occupancy bits of every volume of a batch
+// in one launch each, with the per-cell code of the single-volume kernels (so
+// the grids and bits are bitwise those of per-volume launches): workgroup b
+// belongs to the volume v with base[v] <= b < base[v + 1], a prefix table of
+// the volumes' macrocells (coarse-bit workgroups), and works on its local
+// index b - base[v].  Small volumes no longer leave the chip idle one launch
+// at a time.
+
+namespace vdbc {
+
+__device__ inline uint32_t batch_volume_of(const uint32_t* __restrict__ base, uint32_t n, uint32_t b)
+{
+    uint32_t lo = 0, hi = n;   // base[lo] <= b < base[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void majorant_batch_kernel(const BatchDesc* __restrict__ descs,
+                                                                const uint32_t* __restrict__ base, uint32_t n)
+{
+    __shared__ uint32_t s_v;
+    if (threadIdx.x == 0) s_v = batch_volume_of(base, n, blockIdx.x);
+    __syncthreads();
+    const uint32_t v = s_v;
+    const BatchDesc* D = descs + v;
+    VdbAcc acc{D->view};
+    acc.reset();
+    majorant_cell(acc, D->med, D->g.C, D->g.gx, D->g.gy, blockIdx.x - base[v], const_cast<float*>(D->maj));
+}
+
+__global__ __launch_bounds__(kBlock) void coarse_bits_batch_kernel(const BatchDesc* __restrict__ descs,
+                                                                   const uint32_t* __restrict__ base, uint32_t n)
+{
+    // every thread finds the volume itself: a workgroup lies in one volume,
+    // and no barrier is needed before the ballot
+    const uint32_t v = batch_volume_of(base, n, blockIdx.x);
+    const BatchDesc* D = descs + v;
+    coarse_bits_block(D->maj, D->g, const_cast<uint32_t*>(D->coarse), blockIdx.x - base[v]);
+}
+
+}  // namespace vdbc
+
 // ---------------------------------------------------------------- batched PT (host)
 
 struct vdbc_batch {
@@ -833,6 +889,9 @@ struct vdbc_batch {
     BatchDesc* d_descs = nullptr;
     uint32_t* d_items = nullptr;
     uint32_t* d_counter = nullptr;
+    uint32_t* d_cell_base = nullptr;     // prefix tables of macrocells and coarse-bit workgroups
+    uint32_t* d_coarse_base = nullptr;
+    uint64_t cells_total = 0, cblocks_total = 0;
     uint32_t n_items = 0;
     int max_cwords = 0;
     int grid_blocks = 0;
@@ -918,6 +977,7 @@ static vdbc_status batch_plan(const vdbc_batch_item* items, uint32_t n, const vd
     uint64_t o = 256;                                   // counter
     const uint64_t descs_off = o;
     o += align256((uint64_t)n * sizeof(BatchDesc));
+    o += align256(8ull * (n + 1));                      // the two prefix tables of the batched majorants
     *items_off = o;
     o += align256(tiles_total * 4);
     for (uint32_t i = 0; i < n; ++i) {
@@ -955,13 +1015,28 @@ static vdbc_status batch_resolve(vdbc_batch* b, hipStream_t st)
 static vdbc_status batch_enqueue(vdbc_batch* b, hipStream_t st)
 {
     vdbc_status s;
+    // the persistent launch builds every volume's majorant grid and coarse
+    // bits in one launch each (below the grid-size limit); one launch per
+    // volume otherwise, and for the per-volume baseline
+    const bool batched_pre = b->t.persistent && b->cells_total < (1ull << 24) && b->cblocks_total < (1ull << 24);
+    if (batched_pre) {
+        hipLaunchKernelGGL(majorant_batch_kernel, dim3((unsigned)b->cells_total), dim3(kBlock), 0, st, b->d_descs,
+                           b->d_cell_base, b->n);
+        if ((s = launch_check("batched majorants"))) return s;
+        hipLaunchKernelGGL(coarse_bits_batch_kernel, dim3((unsigned)b->cblocks_total), dim3(kBlock), 0, st,
+                           b->d_descs, b->d_coarse_base, b->n);
+        if ((s = launch_check("batched coarse occupancy"))) return s;
+    }
     for (uint32_t i = 0; i < b->n; ++i) {
-        if ((s = launch_majorant<VdbAcc>(b->views[i], b->meds[i], (uint32_t)b->gs[i].C, b->majs[i], st))) return s;
-        const PtArgs& g = b->gs[i];
-        const uint64_t ncoarse = (uint64_t)g.cgx * g.cgy * g.cgz;
-        hipLaunchKernelGGL(coarse_bits_kernel, dim3((unsigned)((ncoarse + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                           st, b->majs[i], g, b->coarse[i]);
-        if ((s = launch_check("batch coarse occupancy"))) return s;
+        if (!batched_pre) {
+            if ((s = launch_majorant<VdbAcc>(b->views[i], b->meds[i], (uint32_t)b->gs[i].C, b->majs[i], st)))
+                return s;
+            const PtArgs& g = b->gs[i];
+            const uint64_t ncoarse = (uint64_t)g.cgx * g.cgy * g.cgz;
+            hipLaunchKernelGGL(coarse_bits_kernel, dim3((unsigned)((ncoarse + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                               st, b->majs[i], g, b->coarse[i]);
+            if ((s = launch_check("batch coarse occupancy"))) return s;
+        }
         if (b->sums[i].rgbn) {
             const uint64_t words = batch_sums_bytes((uint64_t)b->cams[i].width * b->cams[i].height) / 16;
             hipLaunchKernelGGL(pt_sums_clear_kernel,
@@ -1035,6 +1110,8 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
     uint8_t* w = static_cast<uint8_t*>(ws);
     b->d_counter = reinterpret_cast<uint32_t*>(w);
     b->d_descs = reinterpret_cast<BatchDesc*>(w + 256);
+    b->d_cell_base = reinterpret_cast<uint32_t*>(w + 256 + align256((uint64_t)n * sizeof(BatchDesc)));
+    b->d_coarse_base = b->d_cell_base + (n + 1);
     b->d_items = reinterpret_cast<uint32_t*>(w + io);
     for (uint32_t i = 0; i < n; ++i) {
         b->majs.push_back(reinterpret_cast<float*>(w + mo[i]));
@@ -1059,8 +1136,20 @@ extern "C" vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t 
     for (uint32_t i : order)
         for (uint32_t k = 0; k < (uint32_t)(b->tiles_x[i] * b->tiles_y[i]) * b->gs[i].chunks; ++k)
             list.push_back((i << 20) | k);
+    // prefix tables of the batched majorant launches: macrocells and
+    // coarse-bit workgroups per volume (the launch is used only while both
+    // totals stay below 2^24 workgroups)
+    std::vector<uint32_t> bases(2 * (size_t)(n + 1), 0u);
+    for (uint32_t i = 0; i < n; ++i) {
+        const PtArgs& g = b->gs[i];
+        b->cells_total += (uint64_t)g.gx * g.gy * g.gz;
+        b->cblocks_total += ((uint64_t)g.cgx * g.cgy * g.cgz + kBlock - 1) / kBlock;
+        bases[i + 1] = (uint32_t)std::min<uint64_t>(b->cells_total, 0xFFFFFFFFull);
+        bases[n + 1 + i + 1] = (uint32_t)std::min<uint64_t>(b->cblocks_total, 0xFFFFFFFFull);
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (hipMemcpyAsync(b->d_descs, descs.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+    if (hipMemcpyAsync(b->d_cell_base, bases.data(), bases.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(b->d_descs, descs.data(), n * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(b->d_items, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(VDBC_E_DEVICE, "batch descriptor upload: %s", hipGetErrorString(hipGetLastError()));

@@ -374,8 +374,10 @@ typedef struct {
     uint32_t macrocell;      /* majorant cell edge in voxels: 4, 8, 16, 32, 64 (default 16) */
     uint32_t tile_w;         /* pixels per wave row: 8, 16, 32, 64 (default 8) */
     uint32_t blocks_per_cu;  /* persistent workgroups per compute unit (default 4) */
-    uint32_t persistent;     /* 1: one persistent launch over all (volume, tile)
-                                items; 0: one launch per volume */
+    uint32_t persistent;     /* 1: one launch of every volume's majorant grid, one
+                                of their coarse bits and one persistent render
+                                launch over all (volume, work item) entries;
+                                0: these launches once per volume */
     uint32_t chunk_spp;      /* samples per work item: 0 (or >= a volume's spp)
                                 keeps one item per tile; 0 < chunk_spp < spp
                                 splits each tile of that volume into
@@ -386,12 +388,15 @@ typedef struct {
 
 typedef struct vdbc_batch vdbc_batch;
 
-/* Workspace bytes for a batch (counter, descriptor table, work list, and per
- * volume a majorant grid and coarse occupancy bits).  tuning may be NULL. */
+/* Workspace bytes for a batch (counter, descriptor table, the prefix tables
+ * of the batched majorant launches, work list, and per volume a majorant grid,
+ * coarse occupancy bits and, for a volume split into work items, its pixel
+ * sums).  tuning may be NULL. */
 vdbc_status vdbc_batch_workspace(const vdbc_batch_item* items, uint32_t n,
                                  const vdbc_tuning* tuning, uint64_t* bytes);
-/* Validates the items, uploads the descriptor table and the work list (tiles
- * ordered by estimated cost, largest first) into ws (synchronises `stream`),
+/* Validates the items, uploads the descriptor table, the prefix tables and
+ * the work list (volumes ordered by estimated cost, largest first; a volume's
+ * tiles, or their work items, in raster order) into ws (synchronises `stream`),
  * and returns a plan.  Buffers and images must outlive the plan.  Each image
  * is bit-identical to vdbc_render of that item with the same tuning. */
 vdbc_status vdbc_batch_create(const vdbc_batch_item* items, uint32_t n,
